@@ -1,0 +1,200 @@
+/*
+ * gf.h - C ABI of the MI355X (gfx950) library for Fourier-accelerated
+ * steepest-descent Landau gauge fixing of 4D SU(3) lattice gauge fields
+ * (Cardoso, Silva, Oliveira, Bicudo, "GPU implementation of a Landau gauge
+ * fixing algorithm", Lattice 2012).
+ *
+ * The problem (section 1, Eq. 1): maximise over gauge transformations g(x)
+ *   F_U[g] = 1/(4 N_c V) sum_x sum_mu Re Tr[ g(x) U_mu(x) g^dag(x+mu) ],  N_c = 3,
+ * by the Fourier-accelerated iteration of Alg. 1 (Eq. 2 to Eq. 5), monitored
+ * by theta = 1/(N_c V) sum_x Tr[Delta(x) Delta^dag(x)] (Eq. 4) and stopped
+ * once theta <= eps (the paper uses eps = 1e-15).
+ *
+ * Conventions shared by every call:
+ *   - dims = (Lx, Ly, Lz, Lt); each L is 2^a 3^b with 2 <= L <= 256;
+ *     V = Lx Ly Lz Lt; periodic boundaries.
+ *   - site s = x + Lx*(y + Ly*(z + Lz*t)) (the lexicographic layout of
+ *     section 2.1); direction mu = 0..3 is x, y, z, t.
+ *   - links: device array of complex128 (re, im interleaved doubles) in
+ *     structure-of-arrays order U[((mu*3 + i)*3 + j)*V + s], i.e. a
+ *     contiguous (4, 3, 3, Lt, Lz, Ly, Lx) complex128 tensor (section 2.2:
+ *     one array per matrix element). U_mu(x) joins x to x + mu.
+ *   - matrix fields (Delta, g): complex128 M[(i*3 + j)*V + s].
+ *   - Lie-algebra fields: float64 omega[a*V + s], a = 0..7, Gell-Mann basis
+ *     with Tr(lambda_a lambda_b) = 2 delta_ab.
+ *   - streams are hipStream_t passed as void*; NULL is the null stream.
+ *
+ * Ownership: the caller allocates every device buffer (links, workspace,
+ * gradients) and keeps it alive for the lifetime of the context; the
+ * library never allocates device memory. A context holds host-side state
+ * only (plan, captured graphs, a pinned mirror of the device control block)
+ * and is bound to the stream given at init. A context is not thread-safe.
+ *
+ * Errors: every call returns a gf_status. GF_ERR_ARG: a NULL or
+ * out-of-range argument; GF_ERR_SHAPE: unsupported dims or a workspace
+ * smaller than gf_workspace_bytes(); GF_ERR_HIP: a HIP runtime call failed
+ * (gf_last_error() gives the message); GF_ERR_NONFINITE: theta or F became
+ * NaN or Inf; GF_ERR_MAXITER: the iteration cap was reached before
+ * theta <= eps; GF_ERR_STATE: the call does not apply to this context
+ * (for example a single-configuration call on a batch context).
+ * Scalar outputs are written whenever the status is GF_OK,
+ * GF_ERR_MAXITER or GF_ERR_NONFINITE; output pointers may be NULL.
+ */
+#ifndef GF_H_
+#define GF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gf_ctx_s *gf_ctx;
+
+typedef enum {
+    GF_OK = 0,
+    GF_ERR_ARG = 1,
+    GF_ERR_SHAPE = 2,
+    GF_ERR_HIP = 3,
+    GF_ERR_NONFINITE = 4,
+    GF_ERR_MAXITER = 5,
+    GF_ERR_STATE = 6
+} gf_status;
+
+typedef struct {
+    int32_t dims[4];      /* Lx, Ly, Lz, Lt                                          */
+    double alpha;         /* step parameter of Eq. 2; the paper uses 0.08 (section 1) */
+    int32_t fft_prec;     /* 0: FFT, momentum scaling and inverse FFT in FP64;
+                             1: the same three steps in FP32 (complex64); the
+                             divergence, g, reunitarisation, link update and the
+                             theta/F sums stay FP64 in both                         */
+    int32_t reunit_every; /* 0: Alg. 1 as printed; R > 0: also project every link
+                             to SU(3) after every R-th update (drift control)       */
+    int32_t chunk;        /* iterations per captured graph launch; 0 = default (8)  */
+    int32_t reserved;     /* must be 0                                              */
+} gf_params;
+
+/* Bytes of device workspace a context with these parameters needs. Returns 0
+ * for invalid parameters. */
+size_t gf_workspace_bytes(const gf_params *params);
+
+/*
+ * Create a context for one configuration and measure it: computes Delta,
+ * F and theta of the given links (the first line of Alg. 1).
+ * d_links: device links (layout above), updated in place by later calls.
+ * d_ws: device workspace of at least gf_workspace_bytes(params) bytes,
+ * 256-byte aligned. stream: the hipStream_t all work is ordered on.
+ */
+gf_status gf_init(gf_ctx *ctx, const gf_params *params, void *d_links, void *d_ws, size_t ws_bytes,
+                  void *stream);
+
+/* F (Eq. 1 at g = 1) and theta (Eq. 4) of the current links; synchronises. */
+gf_status gf_functional(gf_ctx ctx, double *F, double *theta);
+
+/*
+ * Run exactly n iterations of Alg. 1 (transform each element of Delta, apply
+ * (alpha/2) p2max/p2 with the zero mode removed, transform back and
+ * normalise, form g = 1 + Delta~ and project to SU(3), update every link
+ * U_mu(x) -> g(x) U_mu(x) g^dag(x + mu), recompute Delta, F, theta),
+ * ignoring the stopping rule. F and theta are the values after the last
+ * update. Synchronises.
+ */
+gf_status gf_step(gf_ctx ctx, int32_t n, double *F, double *theta);
+
+/*
+ * Alg. 1 with its stopping rule: iterate while theta > theta_eps, at most
+ * max_iter iterations in this call. *iters receives the number of updates
+ * made in this call (0 if the links already satisfy theta <= theta_eps).
+ * Returns GF_ERR_MAXITER if the cap was reached first. Synchronises.
+ */
+gf_status gf_fix_until(gf_ctx ctx, double theta_eps, int64_t max_iter, int64_t *iters, double *F,
+                       double *theta);
+
+/*
+ * (F, theta) after every update since gf_init: entry 0 is the initial
+ * measurement, entry k the values after update k. Copies
+ * min(cap, available) entries; *n receives the number available.
+ */
+gf_status gf_history(gf_ctx ctx, int64_t cap, double *F_hist, double *theta_hist, int64_t *n);
+
+/* Stage entry points: each is one step of Alg. 1 on the current links, for
+ * step-by-step checks. They do not advance the iteration count. */
+
+/* Delta(x) of Eq. 5 as a full matrix field d_delta[(i*3+j)*V + s] (complex128). */
+gf_status gf_delta(gf_ctx ctx, void *d_delta);
+
+/* The gauge vector of one iteration (Eq. 2 to first order, then projection
+ * to SU(3)) for the current links, written to d_g[(i*3+j)*V + s]. */
+gf_status gf_gauge(gf_ctx ctx, void *d_g);
+
+/* The link update of Alg. 1, U_mu(x) -> g(x) U_mu(x) g^dag(x + mu), with a
+ * caller-given gauge field d_g (same layout), then F and theta are
+ * re-measured. */
+gf_status gf_apply_gauge(gf_ctx ctx, const void *d_g);
+
+/*
+ * The context's 4D transform applied in place to nfields complex fields
+ * d_fields[f*V + s] (complex128 if fft_prec = 0, complex64 if 1); sign -1
+ * forward exp(-i p.x), +1 backward exp(+i p.x); unnormalised.
+ */
+gf_status gf_fft(gf_ctx ctx, void *d_fields, int32_t nfields, int32_t sign);
+
+/*
+ * Batches: n_cfg independent configurations of possibly different dims in
+ * one context. Every kernel launch covers the tiles of every configuration
+ * still iterating; each configuration has its own device-side stopping test.
+ * params and d_links are arrays of n_cfg entries (n_cfg <= 64).
+ */
+size_t gf_workspace_bytes_batch(int32_t n_cfg, const gf_params *params);
+gf_status gf_init_batch(gf_ctx *ctx, int32_t n_cfg, const gf_params *params, void *const *d_links,
+                        void *d_ws, size_t ws_bytes, void *stream);
+/* iters, F, theta: host arrays of n_cfg entries. GF_ERR_MAXITER if any
+ * configuration hit the cap. */
+gf_status gf_fix_until_batch(gf_ctx ctx, double theta_eps, int64_t max_iter, int64_t *iters, double *F,
+                             double *theta);
+/* F and theta of every configuration of a batch context (host arrays). */
+gf_status gf_functional_batch(gf_ctx ctx, double *F, double *theta);
+
+/*
+ * Differentiable functional (Eq. 1 as a function of gauge parameters):
+ *   F = 1/(12 V) sum_x sum_mu Re Tr[g(x) U_mu(x) g^dag(x+mu)],
+ *   g(x) = exp(i sum_a lambda_a omega_a(x)),
+ * for the context's current links. d_omega: device float64 [8][V].
+ */
+gf_status gf_functional_g(gf_ctx ctx, const double *d_omega, double *F);
+
+/*
+ * Backward of gf_functional_g for an upstream gradient grad_out:
+ *   d_dF_domega[a*V + s] = grad_out * dF/domega_a(x)            (float64 [8][V])
+ *   d_dF_dU   (link layout) = grad_out * (dF/dRe U + i dF/dIm U)
+ *                           = grad_out * g^dag(x) g(x+mu) / (12 V)
+ * Either output pointer may be NULL to skip it.
+ */
+gf_status gf_functional_g_backward(gf_ctx ctx, const double *d_omega, double grad_out, double *d_dF_domega,
+                                   void *d_dF_dU);
+
+/* Release the context (host state and graphs only). */
+gf_status gf_destroy(gf_ctx ctx);
+
+const char *gf_strerror(gf_status status);
+/* Detail of the last error on this context (empty string if none). */
+const char *gf_last_error(gf_ctx ctx);
+
+/*
+ * Per-kernel timing. With timing on, iterations are launched one kernel at
+ * a time (no graph) and every launch is bracketed by hipEvents on the
+ * context's stream; the accumulated time per kernel is readable below.
+ */
+gf_status gf_set_timing(gf_ctx ctx, int32_t on);
+int32_t gf_kernel_count(gf_ctx ctx);
+const char *gf_kernel_name(gf_ctx ctx, int32_t k);
+/* Accumulated milliseconds and launches of kernel k since the last reset. */
+gf_status gf_kernel_time(gf_ctx ctx, int32_t k, double *total_ms, int64_t *launches);
+gf_status gf_reset_timing(gf_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF_H_ */

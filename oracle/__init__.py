@@ -22,7 +22,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C99, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=gnu99", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", "-O2", "-std=gnu99", "-fopenmp", "-fcx-limited-range", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB

@@ -224,8 +224,10 @@ static int smallest_factor(int n)
  * are transformed (length m) into out[r*m .. r*m+m-1], then
  *   X[k + q m] = sum_r w_n^{r (k + q m)} S_r[k],   k < m, q < p.
  * A prime length is a direct DFT (p = n, m = 1).
+ * roots[e] = exp(sign 2 pi i e / N) for the full length N of the top-level
+ * call; w_n^e = roots[(e mod n) * (N / n)] since n divides N.
  */
-static void dft_rec(const cplx *in, int64_t stride, cplx *out, int n, int sign)
+static void dft_rec(const cplx *in, int64_t stride, cplx *out, int n, int sign, const cplx *roots, int N)
 {
     if (n == 1) {
         out[0] = in[0];
@@ -233,14 +235,15 @@ static void dft_rec(const cplx *in, int64_t stride, cplx *out, int n, int sign)
     }
     const int p = smallest_factor(n);
     const int m = n / p;
-    for (int r = 0; r < p; ++r) dft_rec(in + r * stride, stride * p, out + (int64_t)r * m, m, sign);
+    for (int r = 0; r < p; ++r) dft_rec(in + r * stride, stride * p, out + (int64_t)r * m, m, sign, roots, N);
     cplx tmp[64];
     cplx *t = p <= 64 ? tmp : malloc(sizeof(cplx) * p);
+    const int step = N / n;
     for (int k = 0; k < m; ++k) {
         for (int r = 0; r < p; ++r) t[r] = out[(int64_t)r * m + k];
         for (int q = 0; q < p; ++q) {
             cplx acc = 0;
-            for (int r = 0; r < p; ++r) acc += root_of_unity(n, (int64_t)r * (k + (int64_t)q * m), sign) * t[r];
+            for (int r = 0; r < p; ++r) acc += roots[(((int64_t)r * (k + (int64_t)q * m)) % n) * step] * t[r];
             out[k + (int64_t)q * m] = acc;
         }
     }
@@ -256,6 +259,8 @@ void or_fft4d(const int L[4], cplx *f, int sign)
         const int n = L[mu];
         const int64_t inner = stride, outer = V / (stride * n);
         const int64_t pencils = inner * outer;
+        cplx *roots = malloc(sizeof(cplx) * n);
+        for (int e = 0; e < n; ++e) roots[e] = root_of_unity(n, e, sign);
 #pragma omp parallel
         {
             cplx *buf = malloc(sizeof(cplx) * n);
@@ -265,12 +270,13 @@ void or_fft4d(const int L[4], cplx *f, int sign)
                 const int64_t i0 = pcl % inner, o = pcl / inner;
                 const int64_t base = o * inner * n + i0;
                 for (int k = 0; k < n; ++k) buf[k] = f[base + k * inner];
-                dft_rec(buf, 1, res, n, sign);
+                dft_rec(buf, 1, res, n, sign, roots, n);
                 for (int k = 0; k < n; ++k) f[base + k * inner] = res[k];
             }
             free(buf);
             free(res);
         }
+        free(roots);
         stride *= n;
     }
 }
@@ -526,30 +532,29 @@ static void algebra_matrix(const double w[8], mat3 Q)
 /*
  * Cyclic Jacobi diagonalisation of a hermitian 3x3 matrix: Q = W diag(lam) W^dag.
  * Each rotation acts on one (p, q) pair: a phase on column q makes Q_pq real,
- * then the classical real Jacobi rotation annihilates it. Sweeps until the
- * off-diagonal part is below roundoff.
+ * then the classical real Jacobi rotation annihilates it. An off-diagonal
+ * entry below the rounding level of its two diagonal entries is set to zero
+ * instead of rotated (a rotation by the phase of a denormal entry is not
+ * unitary to working precision); sweeps stop when nothing is left to rotate.
  */
 void or_eigh3(const cplx *Qin, double lam[3], cplx *Wout)
 {
     mat3 A, W = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     memcpy(A, Qin, sizeof(mat3));
     for (int sweep = 0; sweep < 50; ++sweep) {
-        double off = 0.0, diag = 0.0;
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                double v = creal(A[i][j] * conj(A[i][j]));
-                if (i == j)
-                    diag += v;
-                else
-                    off += v;
-            }
-        if (off <= 1e-36 * (diag + 1e-300) || off == 0.0) break;
+        int rotated = 0;
         for (int p = 0; p < 2; ++p)
             for (int q = p + 1; q < 3; ++q) {
                 double apq = cabs(A[p][q]);
-                if (apq == 0.0) continue;
-                cplx phase = A[p][q] / apq; /* e^{i phi} */
                 double app = creal(A[p][p]), aqq = creal(A[q][q]);
+                if (apq == 0.0) continue;
+                if (apq <= 1e-18 * (fabs(app) + fabs(aqq))) {
+                    A[p][q] = 0.0;
+                    A[q][p] = 0.0;
+                    continue;
+                }
+                rotated = 1;
+                cplx phase = A[p][q] / apq; /* e^{i phi} */
                 double th = (aqq - app) / (2.0 * apq);
                 double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                 double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
@@ -564,6 +569,7 @@ void or_eigh3(const cplx *Qin, double lam[3], cplx *Wout)
                 mat_mul(A, J, A);
                 mat_mul(W, J, W);
             }
+        if (!rotated) break;
     }
     for (int i = 0; i < 3; ++i) lam[i] = creal(A[i][i]);
     memcpy(Wout, W, sizeof(mat3));

@@ -1,0 +1,251 @@
+// Device helpers: complex arithmetic, 3x3 complex matrices, compensated
+// (double-double) sums with wave64 shuffles, lattice indexing, block mapping.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gf_internal.h"
+
+namespace gfk {
+
+// ---------------------------------------------------------------- complex
+__device__ __forceinline__ double2 cz() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// conj(a) * b
+__device__ __forceinline__ double2 ccmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double cnorm2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// ---------------------------------------------------------------- 3x3
+struct M3 {
+    double2 e[9];
+};
+
+__device__ __forceinline__ M3 m3_load(const double2 *__restrict__ base, int V, int s)
+{
+    M3 m;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m.e[k] = base[(size_t)k * V + s];
+    return m;
+}
+
+__device__ __forceinline__ void m3_store(double2 *__restrict__ base, int V, int s, const M3 &m)
+{
+#pragma unroll
+    for (int k = 0; k < 9; ++k) base[(size_t)k * V + s] = m.e[k];
+}
+
+// a b
+__device__ __forceinline__ M3 m3_mul(const M3 &a, const M3 &b)
+{
+    M3 c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double2 acc = cmul(a.e[i * 3], b.e[j]);
+            acc = cadd(acc, cmul(a.e[i * 3 + 1], b.e[3 + j]));
+            acc = cadd(acc, cmul(a.e[i * 3 + 2], b.e[6 + j]));
+            c.e[i * 3 + j] = acc;
+        }
+    return c;
+}
+
+// a b^dag
+__device__ __forceinline__ M3 m3_mul_dag(const M3 &a, const M3 &b)
+{
+    M3 c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double2 acc = cmulc(a.e[i * 3], b.e[j * 3]);
+            acc = cadd(acc, cmulc(a.e[i * 3 + 1], b.e[j * 3 + 1]));
+            acc = cadd(acc, cmulc(a.e[i * 3 + 2], b.e[j * 3 + 2]));
+            c.e[i * 3 + j] = acc;
+        }
+    return c;
+}
+
+// a^dag b
+__device__ __forceinline__ M3 m3_dag_mul(const M3 &a, const M3 &b)
+{
+    M3 c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double2 acc = ccmul(a.e[i], b.e[j]);
+            acc = cadd(acc, ccmul(a.e[3 + i], b.e[3 + j]));
+            acc = cadd(acc, ccmul(a.e[6 + i], b.e[6 + j]));
+            c.e[i * 3 + j] = acc;
+        }
+    return c;
+}
+
+__device__ __forceinline__ M3 m3_add(const M3 &a, const M3 &b)
+{
+    M3 c;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c.e[k] = cadd(a.e[k], b.e[k]);
+    return c;
+}
+
+__device__ __forceinline__ M3 m3_scale(const M3 &a, double s)
+{
+    M3 c;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c.e[k] = cscale(a.e[k], s);
+    return c;
+}
+
+__device__ __forceinline__ M3 m3_zero()
+{
+    M3 c;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c.e[k] = cz();
+    return c;
+}
+
+__device__ __forceinline__ M3 m3_identity()
+{
+    M3 c = m3_zero();
+    c.e[0].x = c.e[4].x = c.e[8].x = 1.0;
+    return c;
+}
+
+// Projection to SU(3) by row Gram-Schmidt; the third row is conj(r0 x r1).
+__device__ __forceinline__ void m3_reunit(M3 &m)
+{
+    double n0 = cnorm2(m.e[0]) + cnorm2(m.e[1]) + cnorm2(m.e[2]);
+    double i0 = 1.0 / sqrt(n0);
+    m.e[0] = cscale(m.e[0], i0);
+    m.e[1] = cscale(m.e[1], i0);
+    m.e[2] = cscale(m.e[2], i0);
+    // overlap <r0, r1> = sum conj(r0_k) r1_k
+    double2 ov = cadd(cadd(ccmul(m.e[0], m.e[3]), ccmul(m.e[1], m.e[4])), ccmul(m.e[2], m.e[5]));
+    m.e[3] = csub(m.e[3], cmul(ov, m.e[0]));
+    m.e[4] = csub(m.e[4], cmul(ov, m.e[1]));
+    m.e[5] = csub(m.e[5], cmul(ov, m.e[2]));
+    double n1 = cnorm2(m.e[3]) + cnorm2(m.e[4]) + cnorm2(m.e[5]);
+    double i1 = 1.0 / sqrt(n1);
+    m.e[3] = cscale(m.e[3], i1);
+    m.e[4] = cscale(m.e[4], i1);
+    m.e[5] = cscale(m.e[5], i1);
+    m.e[6] = cconj(csub(cmul(m.e[1], m.e[5]), cmul(m.e[2], m.e[4])));
+    m.e[7] = cconj(csub(cmul(m.e[2], m.e[3]), cmul(m.e[0], m.e[5])));
+    m.e[8] = cconj(csub(cmul(m.e[0], m.e[4]), cmul(m.e[1], m.e[3])));
+}
+
+// ---------------------------------------------------------------- sums
+struct dd {
+    double hi, lo;
+};
+
+// error-free transformation s + e = a + b
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ dd dd_add(dd a, dd b)
+{
+    double s, e;
+    two_sum(a.hi, b.hi, s, e);
+    e += a.lo + b.lo;
+    dd r;
+    r.hi = s + e;
+    r.lo = e - (r.hi - s);
+    return r;
+}
+
+__device__ __forceinline__ dd dd_shfl_xor(dd v, int m)
+{
+    dd r;
+    r.hi = __shfl_xor(v.hi, m, 64);
+    r.lo = __shfl_xor(v.lo, m, 64);
+    return r;
+}
+
+__device__ __forceinline__ dd wave_sum(dd v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = dd_add(v, dd_shfl_xor(v, m));
+    return v;
+}
+
+// Deterministic block sum of two double-double values; the result is valid in
+// thread 0. `lds` must hold 2 * (blockDim.x / 64) dd entries.
+__device__ __forceinline__ void block_sum2(dd &a, dd &b, dd *lds)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+        lds[2 * w] = a;
+        lds[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        dd x = lds[0], y = lds[1];
+        for (int k = 1; k < nw; ++k) {
+            x = dd_add(x, lds[2 * k]);
+            y = dd_add(y, lds[2 * k + 1]);
+        }
+        a = x;
+        b = y;
+    }
+}
+
+// ---------------------------------------------------------------- mapping
+// Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8).
+// Renumber them so each XCD walks a contiguous range of tiles: neighbouring
+// sites then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int X = 8;
+    const int q = nb / X, r = nb % X;
+    const int xcd = b % X, loc = b / X;
+    return (xcd < r) ? xcd * (q + 1) + loc : r * (q + 1) + (xcd - r) * q + loc;
+}
+
+__device__ __forceinline__ int find_cfg(const int *off, int n, int blk)
+{
+    int c = 0;
+    while (c + 1 < n && blk >= off[c + 1]) ++c;
+    return c;
+}
+
+struct Site {
+    int s;
+    int c[4];
+};
+
+__device__ __forceinline__ void site_coords(const int *dims, int s, int c[4])
+{
+    int r = s;
+    c[0] = r % dims[0];
+    r /= dims[0];
+    c[1] = r % dims[1];
+    r /= dims[1];
+    c[2] = r % dims[2];
+    c[3] = r / dims[2];
+}
+
+}  // namespace gfk

@@ -1,0 +1,46 @@
+"""The HIP library loads without a GPU and exports every entry point of include/gf.h."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "gf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gf_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_method_calls():
+    names = declared_symbols()
+    for n in ("gf_init", "gf_step", "gf_fix_until", "gf_functional", "gf_functional_g", "gf_functional_g_backward",
+              "gf_init_batch", "gf_fix_until_batch"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1210_8018_amd import gf
+
+    lib = gf.lib()
+    for n in declared_symbols():
+        assert hasattr(lib, n), n
+
+
+def test_host_only_calls_without_gpu():
+    from paper_1210_8018_amd import gf
+
+    p = gf.make_params((32, 32, 32, 32))
+    b64 = gf.gf_workspace_bytes(p)
+    b32 = gf.gf_workspace_bytes(gf.make_params((32, 32, 32, 32), fft_prec=1))
+    V = 32**4
+    assert b64 > V * (64 + 144) and b32 < b64
+    assert gf.gf_workspace_bytes(gf.make_params((6, 8, 8, 8))) > 0
+    assert gf.gf_workspace_bytes(gf.make_params((10, 8, 8, 8))) == 0  # factor 5
+    assert gf.gf_workspace_bytes(gf.make_params((8, 8, 8, 8), fft_prec=2)) == 0
+    assert gf.strerror(gf.GF_ERR_MAXITER).startswith("iteration cap")
+    pl = [gf.make_params((12, 12, 12, 12), fft_prec=1), gf.make_params((8, 8, 8, 16), fft_prec=1)]
+    assert gf.gf_workspace_bytes_batch(pl) > 0
+    pl[1] = gf.make_params((8, 8, 8, 16), fft_prec=0)  # one precision per batch
+    assert gf.gf_workspace_bytes_batch(pl) == 0
+    assert gf.lib().gf_init(None, None, None, None, 0, None) == gf.GF_ERR_ARG

@@ -1,0 +1,250 @@
+"""GPU (HIP, gfx950) path against the CPU oracle, stage by stage and per iteration.
+
+Every case draws its inputs from the seeded generator; the oracle computes the
+expected values on the CPU (or, for the 32^4 trajectory, a stored oracle run
+written by tests/golden/make_golden.py). Tolerances: stages 1e-13 absolute on
+O(1) values (FP64 rounding of a few hundred operations); per-iteration F 1e-11
+relative; theta 1e-11 relative down to its rounding floor (theta_tolerance);
+iteration count within 1 %; final F 1e-10.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1210_8018_amd import gf
+from paper_1210_8018_amd.api import BatchGaugeFixer, GaugeFixer
+from paper_1210_8018_amd.inputs import haar_su3, random_links
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ALPHA = 0.08
+EPS = 1e-15
+
+# several tiles, ragged site blocks (V not a multiple of 256), radix-3 lengths, L = 2
+SHAPES = [(8, 8, 8, 8), (12, 8, 6, 4), (6, 6, 6, 2), (2, 2, 2, 2), (24, 4, 2, 6), (4, 12, 4, 8)]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().to("cpu").numpy()
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+def test_delta_and_functional(dims):
+    U = random_links(dims, 0.4, 41)
+    fx = GaugeFixer(dev(U))
+    D = host(fx.delta())
+    Dref = oracle.delta(dims, U)
+    assert np.max(np.abs(D - Dref)) < 1e-13
+    F, th = fx.functional()
+    Fr, thr = oracle.measure(dims, U)
+    assert rel(F, Fr) < 1e-14 and rel(th, thr) < 1e-14
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fft_matches_oracle(dims, prec):
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(42)
+    f = rng.standard_normal((3, V)) + 1j * rng.standard_normal((3, V))
+    fx = GaugeFixer(dev(random_links(dims, 0.3, 1)), fft_prec=prec)
+    ct = torch.complex64 if prec else torch.complex128
+    tol = 3e-6 if prec else 1e-13
+    for sign in (-1, +1):
+        t = torch.from_numpy(f).to(ct).to("cuda").contiguous()
+        got = host(fx.fft(t, sign)).astype(np.complex128)
+        for k in range(3):
+            ref = oracle.fft4d(dims, f[k], sign)
+            assert np.max(np.abs(got[k] - ref)) < tol * np.max(np.abs(ref)), (sign, k)
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gauge_vector_matches_oracle(dims, prec):
+    U = random_links(dims, 0.4, 43)
+    fx = GaugeFixer(dev(U), fft_prec=prec)
+    g = host(fx.gauge())
+    gref = oracle.gauge_from_delta(dims, oracle.delta(dims, U), ALPHA)
+    assert np.max(np.abs(g - gref)) < (2e-6 if prec else 1e-13)
+    M = np.moveaxis(g, 2, 0)
+    assert np.max(np.abs(M @ np.conj(np.swapaxes(M, -1, -2)) - np.eye(3))) < 1e-13
+    assert np.max(np.abs(np.linalg.det(M) - 1)) < 1e-13
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+def test_link_update_matches_oracle(dims):
+    V = int(np.prod(dims))
+    U = random_links(dims, 0.4, 44)
+    g = np.ascontiguousarray(np.moveaxis(haar_su3(np.random.default_rng(5), V), 0, 2))
+    Ud = dev(U)
+    fx = GaugeFixer(Ud)
+    fx.apply_gauge(dev(g))
+    got = host(Ud).reshape(4, 3, 3, V)
+    ref = oracle.apply_gauge(dims, U, g).reshape(4, 3, 3, V)
+    assert np.max(np.abs(got - ref)) < 1e-14
+    assert abs(oracle.plaquette(dims, host(Ud)) - oracle.plaquette(dims, U)) < 1e-13
+
+
+def theta_tolerance(theta, V):
+    """Relative bound on |theta_gpu - theta_oracle| per iteration.
+
+    theta = sum |Delta|^2 / (3V) with Delta a difference of O(1) link entries,
+    so two FP64 codes that agree on every entry of Delta to a few ulps give
+    theta's agreeing to about 2 eps / sqrt(V theta) relative (random rounding
+    over 9V terms). The bound is 1e-11 plus 50 times that floor; it equals
+    1e-11 wherever the floor is below it (theta >~ 5e-6 / V).
+    """
+    return 1e-11 + 50 * np.finfo(float).eps / np.sqrt(V * np.asarray(theta))
+
+
+def compare_trajectory(F, T, Fr, Tr, V):
+    F, T, Fr, Tr = map(np.asarray, (F, T, Fr, Tr))
+    n = min(len(F), len(Fr), 101)
+    assert np.max(np.abs(F[:n] - Fr[:n]) / np.abs(Fr[:n]).clip(1e-300)) < 1e-11
+    err = np.abs(T[:n] - Tr[:n]) / Tr[:n]
+    assert np.all(err < theta_tolerance(Tr[:n], V)), (err, Tr[:n])
+
+
+@pytest.mark.parametrize("dims,eps,seed", [((8, 8, 8, 8), 0.3, 1), ((12, 8, 6, 4), 0.3, 3), ((6, 6, 6, 2), 0.35, 4)])
+def test_trajectory_matches_oracle(dims, eps, seed):
+    U = random_links(dims, eps, seed)
+    n_ref, U_ref, Fr, Tr = oracle.fix(dims, U, alpha=ALPHA, eps=EPS, max_iter=5000)
+    Ud = dev(U)
+    fx = GaugeFixer(Ud)
+    it, F, th = fx.fix_until(EPS, 5000)
+    Fh, Th = fx.history()
+    assert abs(it - n_ref) <= max(0, int(0.01 * n_ref)), (it, n_ref)
+    compare_trajectory(Fh, Th, Fr, Tr, int(np.prod(dims)))
+    assert th <= EPS
+    assert rel(F, Fr[-1]) < 1e-10
+    Uf = host(Ud)
+    assert abs(oracle.plaquette(dims, Uf) - oracle.plaquette(dims, U)) < 1e-13
+    M = np.moveaxis(Uf.reshape(4, 3, 3, -1), 3, 1).reshape(-1, 3, 3)
+    assert np.max(np.abs(M @ np.conj(np.swapaxes(M, -1, -2)) - np.eye(3))) < 1e-13
+    assert np.max(np.abs(np.linalg.det(M) - 1)) < 1e-13
+    Fh = np.asarray(Fh)
+    assert np.all(np.diff(Fh) >= -4 * np.spacing(np.abs(Fh[:-1])))
+
+
+def test_step_equals_fix_prefix():
+    dims = (8, 8, 8, 8)
+    U = random_links(dims, 0.3, 1)
+    a = GaugeFixer(dev(U))
+    a.fix_until(EPS, 5000)
+    Fa, Ta = a.history()
+    b = GaugeFixer(dev(U), chunk=3)
+    for _ in range(5):
+        b.step(2)
+    Fb, Tb = b.history()
+    assert len(Fb) == 11
+    assert Fb == Fa[:11] and Tb == Ta[:11]  # deterministic: bitwise equal
+
+
+def test_trajectory_32x4_matches_stored_oracle():
+    """Plain FP64 at 32^4 (eps 0.3, seed 2) against the stored oracle run."""
+    ref = json.load(open(os.path.join(HERE, "golden", "oracle_32x32x32x32_eps0.3_seed2.json")))
+    dims = tuple(ref["dims"])
+    U = random_links(dims, ref["eps_generator"], ref["seed"])
+    Ud = dev(U)
+    del U
+    fx = GaugeFixer(Ud)
+    it, F, th = fx.fix_until(EPS, 5000)
+    Fh, Th = fx.history()
+    n_ref = ref["iterations"]
+    assert abs(it - n_ref) <= max(0, int(0.01 * n_ref)), (it, n_ref)
+    compare_trajectory(Fh, Th, ref["F"], ref["theta"], int(np.prod(dims)))
+    assert rel(F, ref["F"][-1]) < 1e-10 and th <= EPS
+    Uf = host(Ud)
+    assert abs(oracle.plaquette(dims, Uf) - ref["plaquette_initial"]) < 1e-13
+
+
+@pytest.mark.parametrize("dims,seed", [((8, 8, 8, 8), 1), ((12, 8, 6, 4), 3)])
+def test_fp32_fft_against_fp64_oracle(dims, seed):
+    """FFT, scaling and inverse FFT in complex64; the rest FP64. Same fixed point."""
+    U = random_links(dims, 0.3, seed)
+    n_ref, U_ref, Fr, Tr = oracle.fix(dims, U, alpha=ALPHA, eps=EPS, max_iter=5000)
+    Ud = dev(U)
+    fx = GaugeFixer(Ud, fft_prec=1)
+    it, F, th = fx.fix_until(EPS, 5000)
+    Fh, Th = fx.history()
+    assert abs(it - n_ref) <= max(1, int(0.05 * n_ref)), (it, n_ref)
+    assert th <= EPS
+    assert rel(F, Fr[-1]) < 1e-12
+    n = min(len(Th), len(Tr))
+    big = np.asarray(Tr[:n]) > 1e-10
+    assert np.max(np.abs(np.asarray(Th[:n])[big] - np.asarray(Tr[:n])[big]) / np.asarray(Tr[:n])[big]) < 1e-4
+    assert abs(oracle.plaquette(dims, host(Ud)) - oracle.plaquette(dims, U)) < 1e-13
+
+
+def test_reunit_every_matches_oracle():
+    dims = (6, 6, 6, 2)
+    U = random_links(dims, 0.35, 4)
+    n_ref, _, Fr, Tr = oracle.fix(dims, U, eps=EPS, reunit_every=4)
+    fx = GaugeFixer(dev(U), reunit_every=4)
+    it, F, th = fx.fix_until(EPS, 5000)
+    Fh, Th = fx.history()
+    assert it == n_ref
+    compare_trajectory(Fh, Th, Fr, Tr, int(np.prod(dims)))
+
+
+def test_unit_links_need_no_iteration():
+    dims = (4, 4, 4, 4)
+    U = np.zeros((4, 3, 3, 4, 4, 4, 4), dtype=np.complex128)
+    for i in range(3):
+        U[:, i, i] = 1
+    fx = GaugeFixer(dev(U))
+    assert fx.functional() == (1.0, 0.0)
+    it, F, th = fx.fix_until(EPS, 100)
+    assert it == 0 and F == 1.0 and th == 0.0
+
+
+def test_nonfinite_and_maxiter_statuses():
+    dims = (8, 8, 8, 8)
+    U = random_links(dims, 0.3, 1)
+    fx = GaugeFixer(dev(U))
+    it, F, th, st = gf.gf_fix_until(fx.ctx, EPS, 3, allow_maxiter=True)
+    assert st == gf.GF_ERR_MAXITER and it == 3
+    bad = U.copy()
+    bad[1, 0, 2, 3, 2, 1, 0] = np.nan
+    fb = GaugeFixer(dev(bad))
+    with pytest.raises(gf.GFError) as e:
+        fb.fix_until(EPS, 10)
+    assert e.value.status == gf.GF_ERR_NONFINITE
+
+
+def test_invalid_shapes_rejected():
+    assert gf.gf_workspace_bytes(gf.make_params((5, 8, 8, 8))) == 0
+    assert gf.gf_workspace_bytes(gf.make_params((1, 8, 8, 8))) == 0
+    assert gf.gf_workspace_bytes(gf.make_params((512, 8, 8, 8))) == 0
+    assert gf.gf_workspace_bytes(gf.make_params((8, 8, 8, 8), alpha=-1)) == 0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_equals_single_runs(prec):
+    """Each configuration of a batch evolves bitwise as in its own context."""
+    cases = [((8, 8, 8, 8), 0.3, 1), ((6, 4, 8, 4), 0.25, 2), ((12, 8, 6, 4), 0.45, 3), ((4, 4, 4, 4), 0.2, 4)]
+    Us = [random_links(d, e, s) for d, e, s in cases]
+    single = []
+    for U in Us:
+        Ud = dev(U)
+        fx = GaugeFixer(Ud, fft_prec=prec)
+        single.append((fx.fix_until(EPS, 20000), host(Ud)))
+    Ubs = [dev(U) for U in Us]
+    bx = BatchGaugeFixer(Ubs, fft_prec=prec)
+    its, Fs, ths = bx.fix_until(EPS, 20000)
+    for k in range(len(cases)):
+        (it, F, th), Uf = single[k]
+        assert its[k] == it and Fs[k] == F and ths[k] == th
+        assert np.array_equal(host(Ubs[k]), Uf)

@@ -28,6 +28,18 @@ def test_eigh3_reconstructs(orc):
         assert np.allclose(np.sort(lam), np.linalg.eigvalsh(Q), atol=1e-14 * nrm)
 
 
+def test_expi_on_many_algebra_elements(orc):
+    """exp(i omega.lambda) for 20000 draws at the scales the workloads use, against scipy."""
+    lam = gell_mann()
+    rng = np.random.default_rng(12)
+    for sigma in (1e-6, 0.1, 1.5):
+        w = sigma * rng.standard_normal((20000 if sigma == 0.1 else 2000, 8))
+        Q = np.einsum("na,aij->nij", w, lam)
+        for k in range(len(w)):
+            e = orc.expi(Q[k])
+            assert np.max(np.abs(e - sla.expm(1j * Q[k]))) < 1e-14 * max(1.0, sigma * 8), (sigma, k)
+
+
 def test_expi_matches_scipy_and_closed_forms(orc):
     rng = np.random.default_rng(1)
     for _ in range(50):
