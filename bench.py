@@ -26,19 +26,25 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # FP32 transform fields (c = bytes per complex transform element):
 #   divergence: read 4 links (576) + write 4 packed fields (4c)
 #   transform pass: read + write 4 fields (8c)
-#   gauge: read 4 fields (4c) + write g (144)
+#   gauge, or the inverse (x, y) pass fused with it: read 4 fields (4c) + write g (144)
 #   link update: read 4 links (576) + g(x) (144) + write 4 links (576);
 #     neighbour g(x + mu) is counted once (its own site's read)
+#   fused link update + divergence of the new links: the link update's bytes
+#     + 4 fields written (neighbour links and g recomputed from cache)
 #   reduction: negligible (one double-double pair per 256 sites)
 
 
 def kernel_bytes_per_site(name: str, c: int) -> float:
+    if name == "fft_xy_inv_gauge":  # inverse (x, y) pass fused with g: read 4 fields, write g
+        return 4 * c + 144
     if name.startswith("delta"):
         return 576 + 4 * c
     if name.startswith("fft"):
         return 8 * c
     if name.startswith("gauge"):
         return 4 * c + 144
+    if name == "link_update_delta":  # fused update + divergence: the update's bytes + 4 fields written
+        return 576 + 144 + 576 + 4 * c
     if name.startswith("link_update"):
         return 576 + 144 + 576
     return 0.0
@@ -103,6 +109,7 @@ def main():
         torch.cuda.synchronize()
         dt_ev = time.perf_counter() - t1
         kt = fx.kernel_times()
+        sched = fx.fft_schedule
         fx.set_timing(False)
         fx.close()
         del fx, U
@@ -119,7 +126,7 @@ def main():
         del fx, U
         res[tag] = dict(iters_per_s=args.steps / dt, ms_per_step=1e3 * dt / args.steps,
                         event_region_iters_per_s=args.steps / dt_ev, kernels=kt,
-                        time_to_theta_s=ttt, iterations=it, F_final=F, theta_final=th)
+                        time_to_theta_s=ttt, iterations=it, F_final=F, theta_final=th, fft_schedule=sched)
         log(f"[{tag}] {args.steps / dt:.1f} it/s, fixed in {it} its / {ttt * 1e3:.2f} ms, F={F:.15f}")
 
     c = 16
@@ -127,8 +134,8 @@ def main():
     kern = {}
     for name, (ms, n) in res["fp64"]["kernels"].items():
         b = kernel_bytes_per_site(name, c) * V
-        per_iter_bytes += b
         if n:
+            per_iter_bytes += b
             avg = ms / n
             kern[name] = {"avg_us": round(1e3 * avg, 2), "launches": n,
                           "alg_GBs": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
@@ -186,7 +193,9 @@ def main():
                                    "F_final": f64["F_final"], "theta_final": f64["theta_final"]},
                           "fp32_fft": {"seconds": round(f32["time_to_theta_s"], 5), "iterations": f32["iterations"],
                                        "F_final": f32["F_final"], "theta_final": f32["theta_final"]}},
-        "fp32_fft": {"iters_per_s": round(f32["iters_per_s"], 2), "ms_per_step": round(f32["ms_per_step"], 4)},
+        "fp32_fft": {"iters_per_s": round(f32["iters_per_s"], 2), "ms_per_step": round(f32["ms_per_step"], 4),
+                     "fft_schedule": f32["fft_schedule"]},
+        "fft_schedule": f64["fft_schedule"],
         "hbm": {"alg_bytes_per_iter": per_iter_bytes,
                 "effective_GBs": round(per_iter_bytes * f64["iters_per_s"] / 1e9, 1),
                 "effective_frac": round(per_iter_bytes * f64["iters_per_s"] / 1e9 / HBM_PEAK_GBS, 4)},

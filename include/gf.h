@@ -72,7 +72,13 @@ typedef struct {
     int32_t reunit_every; /* 0: Alg. 1 as printed; R > 0: also project every link
                              to SU(3) after every R-th update (drift control)       */
     int32_t chunk;        /* iterations per captured graph launch; 0 = default (8)  */
-    int32_t reserved;     /* must be 0                                              */
+    int32_t fft_schedule; /* passes of the 4D transform: 0 = autotuned at init
+                             (timed candidates, cached per shape); 1 = four 1D
+                             passes each way; 2 = (x,y) 2D pass, z and t 1D
+                             passes; 3 = (x,y) and (z,t) 2D passes. The inverse
+                             (x,y) 2D pass of schedules 2 and 3 also forms g.
+                             Schedules 2 and 3 need Lx*Ly <= 4096 (and
+                             Lz*Lt <= 4096 for 3); GF_ERR_SHAPE otherwise.   */
 } gf_params;
 
 /* Bytes of device workspace a context with these parameters needs. Returns 0
@@ -192,6 +198,9 @@ const char *gf_kernel_name(gf_ctx ctx, int32_t k);
 /* Accumulated milliseconds and launches of kernel k since the last reset. */
 gf_status gf_kernel_time(gf_ctx ctx, int32_t k, double *total_ms, int64_t *launches);
 gf_status gf_reset_timing(gf_ctx ctx);
+
+/* The transform schedule in use (1, 2 or 3; see gf_params.fft_schedule). */
+int32_t gf_fft_schedule(gf_ctx ctx);
 
 #ifdef __cplusplus
 }

@@ -7,14 +7,27 @@
 
 namespace gfk {
 
-constexpr int kMaxCfg = 64;      // configurations per batch context
-constexpr int kHist = 256;       // device ring of (F, theta) per configuration
-constexpr int kSiteBlock = 256;  // work-items per site-parallel block
-constexpr int kFftThreads = 256; // work-items per transform tile
-constexpr int kMaxStages = 8;    // radix stages per axis
-constexpr int kFields = 4;       // packed transform fields per site
+constexpr int kMaxCfg = 64;        // configurations per batch context
+constexpr int kHist = 256;         // device ring of (F, theta) per configuration
+constexpr int kSiteBlock = 256;    // work-items per site-parallel block
+constexpr int kFftThreads = 256;   // work-items per transform tile
+constexpr int kMaxStages = 8;      // radix stages per axis
+constexpr int kFields = 4;         // packed transform fields per site
+constexpr int kTileElems2D = 4096; // largest LDS tile (elements) of the 2D passes
+
 
 enum : int { kRunning = 0, kConverged = 1, kMaxIter = 2, kNonFinite = 3 };
+
+// Transform schedules: which passes make up the 4D transform, scaling and
+// inverse (the scaling is always fused into the pass that completes the
+// forward transform).
+enum : int {
+    kSchedAuto = 0,
+    kSched1D = 1,    // x, y, z, t+scale, z, y, x (1D passes) + gauge
+    kSchedXY1D = 2,  // xy, z, t+scale, z, xy^-1+gauge
+    kSchedXYZT = 3,  // xy, zt+scale, xy^-1+gauge
+    kSchedCount = 4
+};
 
 // Device control block of one configuration. Written only by device code
 // (the arming and reduction kernels), read back by the host per chunk.
@@ -24,12 +37,12 @@ struct Ctrl {
     long long iter;      // updates since init
     long long max_iter;  // absolute cap on iter
     int done;            // kRunning / kConverged / kMaxIter / kNonFinite
-    int pad;
+    int cur;             // links live in U (0) or in the workspace copy U2 (1)
     double hist[kHist][2];  // (F, theta) after update k at slot k % kHist
 };
 
-// One axis of the 4D transform: tiles of P pencils of length L, elements of
-// a pencil spaced S apart in memory.
+// One axis of a 1D transform pass: tiles of P pencils of length L, elements
+// of a pencil spaced S apart in memory.
 struct FftAxis {
     int L, S, P;
     int ntile;        // tiles per field
@@ -41,11 +54,17 @@ struct FftAxis {
 struct Cfg {
     int dims[4];
     int V;
+    int V2;               // Lx * Ly
+    int V3;               // Lx * Ly * Lz
     int nblk_site;        // site blocks of kSiteBlock
-    double2 *U;           // links [4][3][3][V]
+    int nb3;              // blocks of kSiteBlock over the (x, y, z) volume
+    int tch;              // t-slices marched by one block
+    int nblk_march;       // nb3 * (Lt / tch): blocks of the marching kernels
+    double2 *U;           // links [4][3][3][V] (the caller's array)
+    double2 *U2;          // second link buffer for the fused update (workspace)
     void *fields;         // packed transform fields [4][V], double2 or float2
     double2 *g;           // gauge field [3][3][V]
-    double *partials;     // [nblk_site][4]: (F hi, F lo, theta hi, theta lo)
+    double *partials;     // [nblk_march or nblk_site][4]: (F hi, F lo, theta hi, theta lo)
     Ctrl *ctrl;
     const double *sin2;   // 4 sin^2(pi n / L_mu), axis mu at sin2 + sin2_off[mu]
     int sin2_off[4];
@@ -54,25 +73,36 @@ struct Cfg {
     double kfac;          // (alpha / 2) * p2max / V
     int reunit_every;
     FftAxis ax[4];
+    int xyQ, nxy;         // xy pass: Q consecutive xy-planes per tile, nxy tiles per field
+    int ztP, nzt;         // zt pass: P consecutive xy-sites per tile, nzt tiles per field
 };
 
 // Block-to-configuration maps for every launch shape of a batch.
 struct Batch {
     int n;
     int off_site[kMaxCfg + 1];
+    int off_march[kMaxCfg + 1];
     int off_fft[4][kMaxCfg + 1];
-    int max_lds_elems;    // largest P * L over configurations and axes
+    int off_xy[kMaxCfg + 1];
+    int off_zt[kMaxCfg + 1];
 };
 
-// Launchers (gf_kernels.hip). `active` lists configuration slots; kernels
-// skip configurations whose control block says done when respect_done != 0.
 struct Launch {
     const Cfg *cfgs;      // device array
     const Batch *batch;   // device struct
     int total_site_blocks;
+    int total_march_blocks;
     int total_fft_tiles[4];
-    int max_lds_elems;
+    int total_xy_tiles;
+    int total_zt_tiles;
+    int xy_cap, zt_cap;            // 2D tile capacity variant (1024, 2048 or 4096 elements)
+    int xy_tw2, xy_tw_total;       // LDS twiddle layout of the xy pass: y table offset, entries
+    int zt_tw2, zt_tw_total;       // same for the zt pass
+    int max_lds_elems;    // 1D passes: largest P * L
     int fp32;             // transform precision
+    int fused;            // iterations use the fused update + divergence kernel
+    int any_reunit;       // some configuration projects its links every R updates
+    int ncfg;
     hipStream_t stream;
 };
 
@@ -81,10 +111,17 @@ hipError_t launch_delta(const Launch &L, int respect_done, double2 *full_delta);
 hipError_t launch_reduce(const Launch &L, int ncfg, int count_iter, int respect_done);
 hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *fields_override,
                            int nfields, int respect_done);
+hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done);
+hipError_t launch_fft_xy_inv_gauge(const Launch &L, int respect_done, double2 *g_override);
+hipError_t launch_fft_zt(const Launch &L, int mode, int sign, void *fields_override, int nfields, int respect_done);
+hipError_t launch_fft_zt_scale(const Launch &L, int respect_done);
+hipError_t set_lds_limits();
 hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override);
 hipError_t launch_update(const Launch &L, int respect_done, const double2 *g_override);
-hipError_t launch_functional_g(const Launch &L, const double *omega);
-hipError_t launch_functional_g_backward(const Launch &L, const double *omega, double grad_out,
-                                        double *d_domega, double2 *d_dU);
+hipError_t launch_update_delta(const Launch &L);
+hipError_t launch_links_home(const Launch &L);
+hipError_t launch_functional_g_impl(const Launch &L, int nblk, const double *omega, double scale, double *out);
+hipError_t launch_functional_g_backward_impl(const Launch &L, int nblk, const double *omega, double scale,
+                                             double *d_omega, double2 *d_U);
 
 }  // namespace gfk

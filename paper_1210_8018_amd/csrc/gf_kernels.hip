@@ -23,6 +23,7 @@ __global__ void k_arm(const Cfg *__restrict__ cfgs, int ncfg, double eps, long l
         ct->F = 0.0;
         ct->theta = 0.0;
         ct->done = kRunning;
+        ct->cur = 0;
     }
     ct->eps = eps;
     ct->max_iter = ct->iter + add_iters;
@@ -44,74 +45,101 @@ __global__ void k_arm(const Cfg *__restrict__ cfgs, int ncfg, double eps, long l
 // Im Delta_00 + i Im Delta_11), which carry all 8 real degrees of freedom of
 // the traceless anti-hermitian Delta, and per-block compensated partial sums
 // of sum_mu Re Tr U_mu(x) (Eq. 1 at g = 1) and |Delta|^2 (Eq. 4).
+// A block owns kSiteBlock consecutive sites of the (x, y, z) volume and walks
+// `tch` consecutive t-slices; U_t(x - t) of each slice is the U_t(x) loaded
+// for the previous slice, kept in registers.
 template <typename T2>
 __global__ __launch_bounds__(kSiteBlock) void k_delta(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
                                                       int respect_done, double2 *__restrict__ full)
 {
     __shared__ dd red[2 * (kSiteBlock / 64)];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int c = find_cfg(B->off_site, B->n, blk);
+    const int c = find_cfg(B->off_march, B->n, blk);
     const Cfg &C = cfgs[c];
     if (respect_done && C.ctrl->done) return;
-    const int V = C.V;
-    const int lb = blk - B->off_site[c];
-    const int s = lb * kSiteBlock + threadIdx.x;
-    double fsum = 0.0, tsum = 0.0;
-    if (s < V) {
-        int x[4];
-        site_coords(C.dims, s, x);
-        double2 D[9];
+    const int V = C.V, V3 = C.V3;
+    const int lb = blk - B->off_march[c];
+    const int b3 = lb % C.nb3, tc = lb / C.nb3;
+    const int s3 = b3 * kSiteBlock + threadIdx.x;
+    dd fs = {0.0, 0.0}, ts = {0.0, 0.0};
+    if (s3 < V3) {
+        const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
+        const int x = s3 % Lx, r = s3 / Lx, y = r % Ly, z = r / Ly;
+        int back3[3];
+        back3[0] = (x == 0) ? s3 + (Lx - 1) : s3 - 1;
+        back3[1] = (y == 0) ? s3 + (Ly - 1) * Lx : s3 - Lx;
+        back3[2] = (z == 0) ? s3 + (Lz - 1) * C.V2 : s3 - C.V2;
+        const int t0 = tc * C.tch;
+        const double2 *__restrict__ Ub = C.ctrl->cur ? C.U2 : C.U;
+        const double2 *__restrict__ Ut = Ub + (size_t)27 * V;
+        double2 prev[9];
+        {
+            const int sp = s3 + V3 * ((t0 == 0) ? Lt - 1 : t0 - 1);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) D[k] = cz();
-        int stride = 1;
+            for (int k = 0; k < 9; ++k) prev[k] = Ut[(size_t)k * V + sp];
+        }
+        T2 *__restrict__ f = (T2 *)C.fields;
+        for (int t = t0; t < t0 + C.tch; ++t) {
+            const int s = s3 + V3 * t;
+            double2 D[9];
+            double fsum = 0.0;
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            const int Lm = C.dims[mu];
-            const int sb = (x[mu] == 0) ? s + (Lm - 1) * stride : s - stride;
-            const double2 *__restrict__ Um = C.U + (size_t)mu * 9 * V;
+            for (int k = 0; k < 9; ++k) D[k] = cz();
+#pragma unroll
+            for (int mu = 0; mu < 3; ++mu) {
+                const double2 *__restrict__ Um = Ub + (size_t)mu * 9 * V;
+                const int sb = back3[mu] + V3 * t;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    const double2 here = Um[(size_t)k * V + s];
+                    const double2 back = Um[(size_t)k * V + sb];
+                    D[k] = cadd(D[k], csub(back, here));
+                    if (k == 0 || k == 4 || k == 8) fsum += here.x;
+                }
+            }
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
-                const double2 here = Um[(size_t)k * V + s];
-                const double2 back = Um[(size_t)k * V + sb];
-                D[k] = cadd(D[k], csub(back, here));
+                const double2 here = Ut[(size_t)k * V + s];
+                D[k] = cadd(D[k], csub(prev[k], here));
                 if (k == 0 || k == 4 || k == 8) fsum += here.x;
+                prev[k] = here;
             }
-            stride *= Lm;
-        }
-        // A = D - D^dag (anti-hermitian); remove the trace (pure imaginary)
-        double2 A[9];
+            // A = D - D^dag (anti-hermitian); remove the trace (pure imaginary)
+            double2 A[9];
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) A[i * 3 + j] = csub(D[i * 3 + j], cconj(D[j * 3 + i]));
-        const double tr3 = (A[0].y + A[4].y + A[8].y) * (1.0 / 3.0);
-        A[0] = make_double2(0.0, A[0].y - tr3);
-        A[4] = make_double2(0.0, A[4].y - tr3);
-        A[8] = make_double2(0.0, A[8].y - tr3);
+                for (int j = 0; j < 3; ++j) A[i * 3 + j] = csub(D[i * 3 + j], cconj(D[j * 3 + i]));
+            const double tr3 = (A[0].y + A[4].y + A[8].y) * (1.0 / 3.0);
+            A[0] = make_double2(0.0, A[0].y - tr3);
+            A[4] = make_double2(0.0, A[4].y - tr3);
+            A[8] = make_double2(0.0, A[8].y - tr3);
+            double tsum = 0.0;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) tsum += cnorm2(A[k]);
-        T2 *__restrict__ f = (T2 *)C.fields;
-        f[s].x = A[1].x;
-        f[s].y = A[1].y;
-        f[(size_t)V + s].x = A[2].x;
-        f[(size_t)V + s].y = A[2].y;
-        f[(size_t)2 * V + s].x = A[5].x;
-        f[(size_t)2 * V + s].y = A[5].y;
-        f[(size_t)3 * V + s].x = A[0].y;
-        f[(size_t)3 * V + s].y = A[4].y;
-        if (full) {
+            for (int k = 0; k < 9; ++k) tsum += cnorm2(A[k]);
+            f[s].x = A[1].x;
+            f[s].y = A[1].y;
+            f[(size_t)V + s].x = A[2].x;
+            f[(size_t)V + s].y = A[2].y;
+            f[(size_t)2 * V + s].x = A[5].x;
+            f[(size_t)2 * V + s].y = A[5].y;
+            f[(size_t)3 * V + s].x = A[0].y;
+            f[(size_t)3 * V + s].y = A[4].y;
+            if (full) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) full[(size_t)k * V + s] = A[k];
+                for (int k = 0; k < 9; ++k) full[(size_t)k * V + s] = A[k];
+            }
+            fs = dd_add(fs, dd{fsum, 0.0});
+            ts = dd_add(ts, dd{tsum, 0.0});
         }
     }
-    dd a = {fsum, 0.0}, b = {tsum, 0.0};
-    block_sum2(a, b, red);
+    block_sum2(fs, ts, red);
     if (threadIdx.x == 0) {
         double *p = C.partials + (size_t)lb * 4;
-        p[0] = a.hi;
-        p[1] = a.lo;
-        p[2] = b.hi;
-        p[3] = b.lo;
+        p[0] = fs.hi;
+        p[1] = fs.lo;
+        p[2] = ts.hi;
+        p[3] = ts.lo;
     }
 }
 
@@ -119,14 +147,15 @@ __global__ __launch_bounds__(kSiteBlock) void k_delta(const Cfg *__restrict__ cf
 // One block per configuration: sum the block partials in a fixed order,
 // F = sum/(12 V) (Eq. 1), theta = sum/(3 V) (Eq. 4); with count_iter, count
 // the update, record the history and evaluate the stopping rule theta <= eps.
-__global__ __launch_bounds__(256) void k_reduce(const Cfg *__restrict__ cfgs, int count_iter, int respect_done)
+__global__ __launch_bounds__(256) void k_reduce(const Cfg *__restrict__ cfgs, int count_iter, int respect_done,
+                                                int flip)
 {
     __shared__ dd red[2 * (256 / 64)];
     const Cfg &C = cfgs[blockIdx.x];
     Ctrl *ct = C.ctrl;
     if (respect_done && ct->done) return;
     dd f = {0.0, 0.0}, t = {0.0, 0.0};
-    for (int i = threadIdx.x; i < C.nblk_site; i += blockDim.x) {
+    for (int i = threadIdx.x; i < C.nblk_march; i += blockDim.x) {
         const double *p = C.partials + (size_t)i * 4;
         f = dd_add(f, dd{p[0], p[1]});
         t = dd_add(t, dd{p[2], p[3]});
@@ -141,6 +170,7 @@ __global__ __launch_bounds__(256) void k_reduce(const Cfg *__restrict__ cfgs, in
         if (count_iter) {
             it += 1;
             ct->iter = it;
+            if (flip) ct->cur ^= 1;
         }
         ct->hist[it % kHist][0] = F;
         ct->hist[it % kHist][1] = th;
@@ -240,14 +270,20 @@ __device__ __forceinline__ void dft3(T2 *a, int sign)
 }
 
 template <typename T2>
+__device__ __forceinline__ void dft4r(T2 &a0, T2 &a1, T2 &a2, T2 &a3, int sign)
+{
+    const T2 s02 = t_add(a0, a2), d02 = t_sub(a0, a2);
+    const T2 s13 = t_add(a1, a3), d13 = t_mul_si(t_sub(a1, a3), sign);
+    a0 = t_add(s02, s13);
+    a2 = t_sub(s02, s13);
+    a1 = t_add(d02, d13);
+    a3 = t_sub(d02, d13);
+}
+
+template <typename T2>
 __device__ __forceinline__ void dft4(T2 *a, int sign)
 {
-    T2 s02 = t_add(a[0], a[2]), d02 = t_sub(a[0], a[2]);
-    T2 s13 = t_add(a[1], a[3]), d13 = t_mul_si(t_sub(a[1], a[3]), sign);
-    a[0] = t_add(s02, s13);
-    a[2] = t_sub(s02, s13);
-    a[1] = t_add(d02, d13);
-    a[3] = t_sub(d02, d13);
+    dft4r(a[0], a[1], a[2], a[3], sign);
 }
 
 template <typename T2>
@@ -255,31 +291,31 @@ __device__ __forceinline__ void dft8(T2 *a, int sign)
 {
     using T = typename Cx<T2>::T;
     const T r2 = (T)0.70710678118654752440;
-    T2 e[4] = {a[0], a[2], a[4], a[6]};
-    T2 o[4] = {a[1], a[3], a[5], a[7]};
-    dft4(e, sign);
-    dft4(o, sign);
+    T2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+    T2 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+    dft4r(e0, e1, e2, e3, sign);
+    dft4r(o0, o1, o2, o3, sign);
     // w^q, w = exp(sign 2 pi i / 8): w^1 = (1 + sign i) r2, w^2 = sign i, w^3 = (-1 + sign i) r2
-    T2 t1, t2, t3;
+    T2 t1, t3;
     {
-        T2 si = t_mul_si(o[1], sign);
-        t1.x = (o[1].x + si.x) * r2;
-        t1.y = (o[1].y + si.y) * r2;
+        const T2 si = t_mul_si(o1, sign);
+        t1.x = (o1.x + si.x) * r2;
+        t1.y = (o1.y + si.y) * r2;
     }
-    t2 = t_mul_si(o[2], sign);
+    const T2 t2 = t_mul_si(o2, sign);
     {
-        T2 si = t_mul_si(o[3], sign);
-        t3.x = (si.x - o[3].x) * r2;
-        t3.y = (si.y - o[3].y) * r2;
+        const T2 si = t_mul_si(o3, sign);
+        t3.x = (si.x - o3.x) * r2;
+        t3.y = (si.y - o3.y) * r2;
     }
-    a[0] = t_add(e[0], o[0]);
-    a[4] = t_sub(e[0], o[0]);
-    a[1] = t_add(e[1], t1);
-    a[5] = t_sub(e[1], t1);
-    a[2] = t_add(e[2], t2);
-    a[6] = t_sub(e[2], t2);
-    a[3] = t_add(e[3], t3);
-    a[7] = t_sub(e[3], t3);
+    a[0] = t_add(e0, o0);
+    a[4] = t_sub(e0, o0);
+    a[1] = t_add(e1, t1);
+    a[5] = t_sub(e1, t1);
+    a[2] = t_add(e2, t2);
+    a[6] = t_sub(e2, t2);
+    a[3] = t_add(e3, t3);
+    a[7] = t_sub(e3, t3);
 }
 
 // One Stockham radix-R stage over P pencils of length L held in LDS.
@@ -346,6 +382,57 @@ __device__ void fft_pencils(T2 *&src, T2 *&dst, const T2 *tw, const FftAxis &A, 
     }
 }
 
+// Global -> LDS copies of a tile. The trip count is bounded at compile time
+// and the loop fully unrolled, so the global loads of a work-item can all be
+// issued before the first LDS store (the two address spaces do not alias).
+template <typename T2, int CAP, int TH>
+__device__ __forceinline__ void tile_load_contig(T2 *buf, const T2 *__restrict__ g, int n)
+{
+    constexpr int NL = (CAP + TH - 1) / TH;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * TH;
+        if (i < n) buf[i] = g[i];
+    }
+}
+
+template <typename T2, int CAP, int TH>
+__device__ __forceinline__ void tile_store_contig(T2 *__restrict__ g, const T2 *buf, int n)
+{
+    constexpr int NL = (CAP + TH - 1) / TH;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * TH;
+        if (i < n) g[i] = buf[i];
+    }
+}
+
+// Rows of P consecutive elements, row r at global offset r * rs; element
+// (r, p) at LDS index r * P + p. P divides TH, so each work-item keeps one p.
+template <typename T2, int CAP, int TH>
+__device__ __forceinline__ void tile_load_rows(T2 *buf, const T2 *__restrict__ g, int P, int rows, size_t rs)
+{
+    constexpr int NL = (CAP + TH - 1) / TH;
+    const int p = threadIdx.x % P, r0 = threadIdx.x / P, dr = TH / P;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int r = r0 + k * dr;
+        if (r < rows) buf[r * P + p] = g[(size_t)r * rs + p];
+    }
+}
+
+template <typename T2, int CAP, int TH>
+__device__ __forceinline__ void tile_store_rows(T2 *__restrict__ g, const T2 *buf, int P, int rows, size_t rs)
+{
+    constexpr int NL = (CAP + TH - 1) / TH;
+    const int p = threadIdx.x % P, r0 = threadIdx.x / P, dr = TH / P;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int r = r0 + k * dr;
+        if (r < rows) g[(size_t)r * rs + p] = buf[r * P + p];
+    }
+}
+
 // One axis of the 4D transform for one tile of one field. mode 0: a plain
 // pass with the given sign. mode 1 (last axis only): forward transform,
 // multiplication by K(p) = (alpha/2)(p2max/p2)/V with K(0) = 0 (Eq. 2; the
@@ -377,14 +464,11 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(const Cfg *__restrict__ cfg
     size_t gbase;
     if (!k_fast) {
         gbase = (size_t)t * n;
-        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) buf0[idx] = g[gbase + idx];
+        tile_load_contig<T2, 1024, kFftThreads>(buf0, g + gbase, n);
     } else {
         const int o = t / A.inner_chunks, ic = t % A.inner_chunks;
         gbase = (size_t)o * A.S * L + (size_t)ic * P;
-        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-            const int k = idx % P, l = idx / P;
-            buf0[idx] = g[gbase + k + (size_t)l * A.S];
-        }
+        tile_load_rows<T2, 1024, kFftThreads>(buf0, g + gbase, P, L, A.S);
     }
     __syncthreads();
     T2 *src = buf0, *dst = buf1;
@@ -412,14 +496,187 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(const Cfg *__restrict__ cfg
         __syncthreads();
         fft_pencils(src, dst, tw, A, ks, ls, +1, k_fast);
     }
-    if (!k_fast) {
-        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) g[gbase + idx] = src[idx];
-    } else {
-        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-            const int k = idx % P, l = idx / P;
-            g[gbase + k + (size_t)l * A.S] = src[idx];
+    if (!k_fast)
+        tile_store_contig<T2, 1024, kFftThreads>(g + gbase, src, n);
+    else
+        tile_store_rows<T2, 1024, kFftThreads>(g + gbase, src, P, L, A.S);
+}
+
+// ============================================================ 2D transform tiles (in place)
+// LDS data tile capacity of the 2D passes: 64 KiB of elements.
+// One radix-R Stockham stage over `npen` pencils of length L in one LDS
+// buffer. Pencil k starts at (k % m1) * a1 + (k / m1) * a2, its elements are
+// ls apart. Each work-item loads its butterflies into registers, the block
+// synchronises, then the results are written back in place.
+template <int R, typename T2, int MAXE, int TH>
+__device__ __forceinline__ void stage_ip(T2 *buf, const T2 *__restrict__ tw, int L, int npen, int m1, int a1, int a2,
+                                         int ls, int Ns, int sign, bool k_fast)
+{
+    constexpr int MAXB = (MAXE + R * TH - 1) / (R * TH);
+    const int nb = L / R;
+    const int total = npen * nb;
+    const int tstep = L / (Ns * R);
+    T2 v[MAXB][R];
+    int ob[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = threadIdx.x + i * TH;
+        if (b < total) {
+            int k, j;
+            if (k_fast) {
+                k = b % npen;
+                j = b / npen;
+            } else {
+                j = b % nb;
+                k = b / nb;
+            }
+            const int base = (k % m1) * a1 + (k / m1) * a2;
+            const int kk = j % Ns;
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[i][m] = buf[base + (j + m * nb) * ls];
+#pragma unroll
+            for (int m = 1; m < R; ++m) {
+                T2 w = tw[m * kk * tstep];
+                if (sign > 0) w.y = -w.y;
+                v[i][m] = t_mul(v[i][m], w);
+            }
+            if constexpr (R == 2)
+                dft2(v[i]);
+            else if constexpr (R == 3)
+                dft3(v[i], sign);
+            else if constexpr (R == 4)
+                dft4(v[i], sign);
+            else
+                dft8(v[i], sign);
+            ob[i] = base + ((j - kk) * R + kk) * ls;
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = threadIdx.x + i * TH;
+        if (b < total) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[ob[i] + q * Ns * ls] = v[i][q];
+        }
+    }
+    __syncthreads();
+}
+
+// All stages of one axis over pencils laid out as in stage_ip.
+template <typename T2, int MAXE, int TH>
+__device__ void fft_axis_ip(T2 *buf, const T2 *tw, const FftAxis &A, int npen, int m1, int a1, int a2, int ls,
+                            int sign, bool k_fast)
+{
+    int Ns = 1;
+    for (int st = 0; st < A.nstage; ++st) {
+        const int r = A.radix[st];
+        switch (r) {
+        case 2: stage_ip<2, T2, MAXE, TH>(buf, tw, A.L, npen, m1, a1, a2, ls, Ns, sign, k_fast); break;
+        case 3: stage_ip<3, T2, MAXE, TH>(buf, tw, A.L, npen, m1, a1, a2, ls, Ns, sign, k_fast); break;
+        case 4: stage_ip<4, T2, MAXE, TH>(buf, tw, A.L, npen, m1, a1, a2, ls, Ns, sign, k_fast); break;
+        default: stage_ip<8, T2, MAXE, TH>(buf, tw, A.L, npen, m1, a1, a2, ls, Ns, sign, k_fast); break;
+        }
+        Ns *= r;
+    }
+}
+
+template <typename T2>
+__device__ __forceinline__ void load_twiddles(T2 *dst, const Cfg &C, int axis)
+{
+    const T2 *__restrict__ src = (const T2 *)C.tw + C.tw_off[axis];
+    for (int e = threadIdx.x; e < C.dims[axis]; e += blockDim.x) dst[e] = src[e];
+}
+
+// 2D transform over (x, y) of Q consecutive xy-planes of one field, in LDS.
+template <typename T2, int CAP, int TH>
+__device__ __forceinline__ void xy_transform(T2 *buf, const T2 *twx, const T2 *twy, const Cfg &C, int Q, int sign)
+{
+    const int Lx = C.dims[0], Ly = C.dims[1];
+    // x: pencils k = (y, q), start k * Lx, unit stride
+    fft_axis_ip<T2, CAP, TH>(buf, twx, C.ax[0], Ly * Q, Ly * Q, Lx, 0, 1, sign, false);
+    // y: pencils k = (x, q), start x + V2 q, stride Lx
+    fft_axis_ip<T2, CAP, TH>(buf, twy, C.ax[1], Lx * Q, Lx, 1, C.V2, Lx, sign, true);
+}
+
+// Pass over (x, y): tile = Q consecutive xy-planes of one field. LDS: CAP
+// data elements, then the twiddles of x (tw2 entries reserved) and y.
+template <typename T2, int CAP, int TH>
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_xy(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B, int sign,
+                                               void *fields_override, int respect_done, int tw2)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int field = blockIdx.y;
+    const int c = find_cfg(B->off_xy, B->n, tile);
+    const Cfg &C = cfgs[c];
+    if (respect_done && C.ctrl->done) return;
+    const int t = tile - B->off_xy[c];
+    const int n = C.xyQ * C.V2;
+    T2 *buf = (T2 *)smem;
+    T2 *twx = buf + CAP;
+    T2 *twy = twx + tw2;
+    load_twiddles(twx, C, 0);
+    load_twiddles(twy, C, 1);
+    T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)field * C.V + (size_t)t * n;
+    tile_load_contig<T2, CAP, TH>(buf, g, n);
+    __syncthreads();
+    xy_transform<T2, CAP, TH>(buf, twx, twy, C, C.xyQ, sign);
+    tile_store_contig<T2, CAP, TH>(g, buf, n);
+}
+
+// Pass over (z, t): tile = P consecutive xy-sites times the whole (z, t) plane
+// of one field, LDS layout [t][z][p]. mode 0: plain transform with `sign`;
+// mode 1: forward, multiplication by K(p) = (alpha/2)(p2max/p2)/V with
+// K(0) = 0 (Eq. 2; 1/V normalises the backward transform), backward.
+template <typename T2, int CAP, int TH>
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_zt(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B, int mode,
+                                               int sign, void *fields_override, int respect_done, int tw2)
+{
+    using T = typename Cx<T2>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int field = blockIdx.y;
+    const int c = find_cfg(B->off_zt, B->n, tile);
+    const Cfg &C = cfgs[c];
+    if (respect_done && C.ctrl->done) return;
+    const int t = tile - B->off_zt[c];
+    const int P = C.ztP, Lz = C.dims[2], Lt = C.dims[3], V2 = C.V2;
+    const int n = P * Lz * Lt;
+    const int i0 = t * P;
+    T2 *buf = (T2 *)smem;
+    T2 *twz = buf + CAP;
+    T2 *twt = twz + tw2;
+    load_twiddles(twz, C, 2);
+    load_twiddles(twt, C, 3);
+    T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)field * C.V + i0;
+    tile_load_rows<T2, CAP, TH>(buf, g, P, Lz * Lt, V2);
+    __syncthreads();
+    const int s0 = (mode == 1) ? -1 : sign;
+    // z: pencils k = (p, t), start p + P Lz t, stride P
+    fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, P * Lz, P, s0, true);
+    // t: pencils k = (p, z), start k, stride P Lz
+    fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, P * Lz, s0, true);
+    if (mode == 1) {
+        const double *s2 = C.sin2;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int p = i % P, zt = i / P;
+            const int nz = zt % Lz, nt = zt / Lz;
+            const int i2 = i0 + p;
+            const int nx = i2 % C.dims[0], ny = i2 / C.dims[0];
+            const double p2 = s2[C.sin2_off[0] + nx] + s2[C.sin2_off[1] + ny] + s2[C.sin2_off[2] + nz] +
+                              s2[C.sin2_off[3] + nt];
+            const T k_t = (T)((p2 > 0.0) ? C.kfac / p2 : 0.0);
+            T2 v = buf[i];
+            v.x *= k_t;
+            v.y *= k_t;
+            buf[i] = v;
+        }
+        __syncthreads();
+        fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, P * Lz, +1, true);
+        fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, P * Lz, P, +1, true);
+    }
+    tile_store_rows<T2, CAP, TH>(g, buf, P, Lz * Lt, V2);
 }
 
 // ============================================================ S4: g = 1 + Delta~, projected
@@ -428,18 +685,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(const Cfg *__restrict__ cfg
 // Delta~_22 = -Delta~_00 - Delta~_11) in FP64, forms g = 1 + Delta~ (first
 // order in alpha) and projects it to SU(3).
 template <typename T2>
-__global__ __launch_bounds__(kSiteBlock) void k_gauge(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
-                                                      int respect_done, double2 *__restrict__ g_override)
+__device__ __forceinline__ M3 gauge_from_fields(T2 a, T2 b, T2 d, T2 e)
 {
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int c = find_cfg(B->off_site, B->n, blk);
-    const Cfg &C = cfgs[c];
-    if (respect_done && C.ctrl->done) return;
-    const int V = C.V;
-    const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
-    if (s >= V) return;
-    const T2 *__restrict__ f = (const T2 *)C.fields;
-    const T2 a = f[s], b = f[(size_t)V + s], d = f[(size_t)2 * V + s], e = f[(size_t)3 * V + s];
     const double2 f01 = make_double2((double)a.x, (double)a.y);
     const double2 f02 = make_double2((double)b.x, (double)b.y);
     const double2 f12 = make_double2((double)d.x, (double)d.y);
@@ -455,15 +702,12 @@ __global__ __launch_bounds__(kSiteBlock) void k_gauge(const Cfg *__restrict__ cf
     m.e[7] = make_double2(-f12.x, f12.y);
     m.e[8] = make_double2(1.0, -i00 - i11);
     m3_reunit(m);
-    m3_store(g_override ? g_override : C.g, V, s, m);
+    return m;
 }
 
-// ============================================================ S5: link update
-// U_mu(x) -> g(x) U_mu(x) g^dag(x + mu) for the four links of each site; all
-// g were formed before this launch (the two separate loops of Alg. 1).
-__global__ __launch_bounds__(kSiteBlock) void k_update(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
-                                                       int respect_done, const double2 *__restrict__ g_override,
-                                                       int allow_reunit)
+template <typename T2>
+__global__ __launch_bounds__(kSiteBlock) void k_gauge(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                      int respect_done, double2 *__restrict__ g_override)
 {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int c = find_cfg(B->off_site, B->n, blk);
@@ -472,25 +716,245 @@ __global__ __launch_bounds__(kSiteBlock) void k_update(const Cfg *__restrict__ c
     const int V = C.V;
     const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
     if (s >= V) return;
+    const T2 *__restrict__ f = (const T2 *)C.fields;
+    const M3 m = gauge_from_fields(f[s], f[(size_t)V + s], f[(size_t)2 * V + s], f[(size_t)3 * V + s]);
+    m3_store(g_override ? g_override : C.g, V, s, m);
+}
+
+// Inverse transform over (x, y) of the four fields of Q xy-planes, then g and
+// its projection at every site of the tile (the last steps of the transform
+// and the gauge step in one pass; the fields are not written back).
+template <typename T2, int CAP, int TH>
+__global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                         int respect_done, double2 *__restrict__ g_override, int tw2)
+{
+    constexpr int MS = (CAP + TH - 1) / TH;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int c = find_cfg(B->off_xy, B->n, tile);
+    const Cfg &C = cfgs[c];
+    if (respect_done && C.ctrl->done) return;
+    const int t = tile - B->off_xy[c];
+    const int n = C.xyQ * C.V2;
+    const size_t site0 = (size_t)t * n;
+    T2 *buf = (T2 *)smem;
+    T2 *twx = buf + CAP;
+    T2 *twy = twx + tw2;
+    load_twiddles(twx, C, 0);
+    load_twiddles(twy, C, 1);
+    T2 val[kFields][MS];
+#pragma unroll
+    for (int f = 0; f < kFields; ++f) {
+        const T2 *__restrict__ src = (const T2 *)C.fields + (size_t)f * C.V + site0;
+        tile_load_contig<T2, CAP, TH>(buf, src, n);
+        __syncthreads();
+        xy_transform<T2, CAP, TH>(buf, twx, twy, C, C.xyQ, +1);
+#pragma unroll
+        for (int k = 0; k < MS; ++k) {
+            const int i = threadIdx.x + k * TH;
+            if (i < n) val[f][k] = buf[i];
+        }
+        __syncthreads();
+    }
+    double2 *__restrict__ G = g_override ? g_override : C.g;
+#pragma unroll
+    for (int k = 0; k < MS; ++k) {
+        const int i = threadIdx.x + k * TH;
+        if (i < n) m3_store(G, C.V, (int)(site0 + i), gauge_from_fields(val[0][k], val[1][k], val[2][k], val[3][k]));
+    }
+}
+
+// ============================================================ S5: link update
+// U_mu(x) -> g(x) U_mu(x) g^dag(x + mu) for the four links of each site; all
+// g were formed before this launch (the two separate loops of Alg. 1). A block
+// owns kSiteBlock consecutive sites of the (x, y, z) volume and walks `tch`
+// t-slices: g(x + t) of one slice is g(x) of the next, kept in registers.
+__global__ __launch_bounds__(kSiteBlock) void k_update(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                       int respect_done, const double2 *__restrict__ g_override,
+                                                       int allow_reunit)
+{
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int c = find_cfg(B->off_march, B->n, blk);
+    const Cfg &C = cfgs[c];
+    if (respect_done && C.ctrl->done) return;
+    const int V = C.V, V3 = C.V3;
+    const int lb = blk - B->off_march[c];
+    const int b3 = lb % C.nb3, tc = lb / C.nb3;
+    const int s3 = b3 * kSiteBlock + threadIdx.x;
+    if (s3 >= V3) return;
     const double2 *__restrict__ G = g_override ? g_override : C.g;
     const bool reunit =
         allow_reunit && C.reunit_every > 0 && ((C.ctrl->iter + 1) % (long long)C.reunit_every) == 0;
-    int x[4];
-    site_coords(C.dims, s, x);
-    const M3 gx = m3_load(G, V, s);
-    int stride = 1;
+    const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
+    const int x = s3 % Lx, r = s3 / Lx, y = r % Ly, z = r / Ly;
+    int fwd3[3];
+    fwd3[0] = (x == Lx - 1) ? s3 - (Lx - 1) : s3 + 1;
+    fwd3[1] = (y == Ly - 1) ? s3 - (Ly - 1) * Lx : s3 + Lx;
+    fwd3[2] = (z == Lz - 1) ? s3 - (Lz - 1) * C.V2 : s3 + C.V2;
+    const int t0 = tc * C.tch;
+    M3 gx = m3_load(G, V, s3 + V3 * t0);
+    for (int t = t0; t < t0 + C.tch; ++t) {
+        const int s = s3 + V3 * t;
+        const int tn = (t + 1 == Lt) ? 0 : t + 1;
+        const M3 gn = m3_load(G, V, s3 + V3 * tn);
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        const int Lm = C.dims[mu];
-        const int sf = (x[mu] == Lm - 1) ? s - (Lm - 1) * stride : s + stride;
-        stride *= Lm;
-        double2 *__restrict__ Um = C.U + (size_t)mu * 9 * V;
-        const M3 u = m3_load(Um, V, s);
-        const M3 gf = m3_load(G, V, sf);
-        M3 w = m3_mul_dag(m3_mul(gx, u), gf);
-        if (reunit) m3_reunit(w);
-        m3_store(Um, V, s, w);
+        for (int mu = 0; mu < 3; ++mu) {
+            double2 *__restrict__ Um = C.U + (size_t)mu * 9 * V;
+            const M3 u = m3_load(Um, V, s);
+            const M3 gf = m3_load(G, V, fwd3[mu] + V3 * t);
+            M3 w = m3_mul_dag(m3_mul(gx, u), gf);
+            if (reunit) m3_reunit(w);
+            m3_store(Um, V, s, w);
+        }
+        {
+            double2 *__restrict__ Um = C.U + (size_t)27 * V;
+            const M3 u = m3_load(Um, V, s);
+            M3 w = m3_mul_dag(m3_mul(gx, u), gn);
+            if (reunit) m3_reunit(w);
+            m3_store(Um, V, s, w);
+        }
+        gx = gn;
     }
+}
+
+// ============================================================ S5 + S1 fused
+// One pass for the link update and the divergence of the updated links:
+//   U'_mu(x) = g(x) U_mu(x) g^dag(x + mu)          (Alg. 1, second loop)
+//   D(x) = sum_nu [U'_nu(x - nu) - U'_nu(x)], Delta = (D - D^dag) - trace/3
+// Old links are read from one buffer and the new ones written to the other,
+// so no block ever reads a link another block has already replaced. The
+// backward neighbours U'_nu(x - nu), nu = x, y, z, are recomputed from the old
+// links; U'_t(x - t) is the U'_t(x) of the previous t-slice, kept in registers
+// (recomputed once at the first slice of a block). Also writes the packed
+// transform fields and the per-block sums for F (of the new links) and theta.
+// RU: the variant for iterations that also project the new links to SU(3)
+// (reunit_every > 0); each variant returns at once on the other iterations.
+template <typename T2, bool RU>
+__global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restrict__ cfgs,
+                                                             const Batch *__restrict__ B)
+{
+    __shared__ dd red[2 * (kSiteBlock / 64)];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int c = find_cfg(B->off_march, B->n, blk);
+    const Cfg &C = cfgs[c];
+    const Ctrl *ct = C.ctrl;
+    if (ct->done) return;
+    const int V = C.V, V3 = C.V3;
+    const double2 *__restrict__ Uo = ct->cur ? C.U2 : C.U;
+    double2 *__restrict__ Un = ct->cur ? C.U : C.U2;
+    const double2 *__restrict__ G = C.g;
+    const bool reunit = C.reunit_every > 0 && ((ct->iter + 1) % (long long)C.reunit_every) == 0;
+    if (reunit != RU) return;
+    const int lb = blk - B->off_march[c];
+    const int b3 = lb % C.nb3, tc = lb / C.nb3;
+    const int s3 = b3 * kSiteBlock + threadIdx.x;
+    dd fs = {0.0, 0.0}, ts = {0.0, 0.0};
+    if (s3 < V3) {
+        const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
+        const int x = s3 % Lx, r = s3 / Lx, y = r % Ly, z = r / Ly;
+        int fwd3[3], back3[3];
+        fwd3[0] = (x == Lx - 1) ? s3 - (Lx - 1) : s3 + 1;
+        fwd3[1] = (y == Ly - 1) ? s3 - (Ly - 1) * Lx : s3 + Lx;
+        fwd3[2] = (z == Lz - 1) ? s3 - (Lz - 1) * C.V2 : s3 + C.V2;
+        back3[0] = (x == 0) ? s3 + (Lx - 1) : s3 - 1;
+        back3[1] = (y == 0) ? s3 + (Ly - 1) * Lx : s3 - Lx;
+        back3[2] = (z == 0) ? s3 + (Lz - 1) * C.V2 : s3 - C.V2;
+        const int t0 = tc * C.tch;
+        M3 gx = m3_load(G, V, s3 + V3 * t0);
+        M3 utp;  // U'_t(x, t - 1)
+        {
+            const int sp = s3 + V3 * ((t0 == 0) ? Lt - 1 : t0 - 1);
+            utp = m3_mul_dag(m3_mul(m3_load(G, V, sp), m3_load(Uo + (size_t)27 * V, V, sp)), gx);
+            if (RU) m3_reunit(utp);
+        }
+        T2 *__restrict__ f = (T2 *)C.fields;
+        for (int t = t0; t < t0 + C.tch; ++t) {
+            const int s = s3 + V3 * t;
+            M3 D = utp;
+            double fsum = 0.0;
+#pragma unroll
+            for (int mu = 0; mu < 3; ++mu) {
+                const size_t off = (size_t)mu * 9 * V;
+                M3 w = m3_mul_dag(m3_mul(gx, m3_load(Uo + off, V, s)), m3_load(G, V, fwd3[mu] + V3 * t));
+                if (RU) m3_reunit(w);
+                m3_store(Un + off, V, s, w);
+                fsum += w.e[0].x + w.e[4].x + w.e[8].x;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) D.e[k] = csub(D.e[k], w.e[k]);
+                // keep the phases in order: bounds the loads in flight (registers)
+                __builtin_amdgcn_sched_barrier(0);
+                const int sb = back3[mu] + V3 * t;
+                M3 wb = m3_mul_dag(m3_mul(m3_load(G, V, sb), m3_load(Uo + off, V, sb)), gx);
+                if (RU) m3_reunit(wb);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) D.e[k] = cadd(D.e[k], wb.e[k]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            {
+                const int tn = (t + 1 == Lt) ? 0 : t + 1;
+                const M3 gn = m3_load(G, V, s3 + V3 * tn);
+                const size_t off = (size_t)27 * V;
+                M3 w = m3_mul_dag(m3_mul(gx, m3_load(Uo + off, V, s)), gn);
+                if (RU) m3_reunit(w);
+                m3_store(Un + off, V, s, w);
+                fsum += w.e[0].x + w.e[4].x + w.e[8].x;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) D.e[k] = csub(D.e[k], w.e[k]);
+                utp = w;
+                gx = gn;
+            }
+            double2 A[9];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) A[i * 3 + j] = csub(D.e[i * 3 + j], cconj(D.e[j * 3 + i]));
+            const double tr3 = (A[0].y + A[4].y + A[8].y) * (1.0 / 3.0);
+            A[0] = make_double2(0.0, A[0].y - tr3);
+            A[4] = make_double2(0.0, A[4].y - tr3);
+            A[8] = make_double2(0.0, A[8].y - tr3);
+            double tsum = 0.0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) tsum += cnorm2(A[k]);
+            f[s].x = A[1].x;
+            f[s].y = A[1].y;
+            f[(size_t)V + s].x = A[2].x;
+            f[(size_t)V + s].y = A[2].y;
+            f[(size_t)2 * V + s].x = A[5].x;
+            f[(size_t)2 * V + s].y = A[5].y;
+            f[(size_t)3 * V + s].x = A[0].y;
+            f[(size_t)3 * V + s].y = A[4].y;
+            fs = dd_add(fs, dd{fsum, 0.0});
+            ts = dd_add(ts, dd{tsum, 0.0});
+        }
+    }
+    block_sum2(fs, ts, red);
+    if (threadIdx.x == 0) {
+        double *p = C.partials + (size_t)lb * 4;
+        p[0] = fs.hi;
+        p[1] = fs.lo;
+        p[2] = ts.hi;
+        p[3] = ts.lo;
+    }
+}
+
+// Copy the links of configurations whose current buffer is the workspace
+// copy back to the caller's array, and mark the caller's array current.
+__global__ __launch_bounds__(kSiteBlock) void k_links_home(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B)
+{
+    const int blk = blockIdx.x;
+    const int c = find_cfg(B->off_site, B->n, blk);
+    const Cfg &C = cfgs[c];
+    if (!C.ctrl->cur) return;
+    const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
+    if (s >= C.V) return;
+#pragma unroll
+    for (int k = 0; k < 36; ++k) C.U[(size_t)k * C.V + s] = C.U2[(size_t)k * C.V + s];
+}
+
+__global__ void k_links_home_flag(const Cfg *__restrict__ cfgs, int ncfg)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncfg) cfgs[c].ctrl->cur = 0;
 }
 
 // ============================================================ differentiable functional
@@ -725,17 +1189,18 @@ hipError_t launch_arm(const Launch &L, int ncfg, double eps, long long add_iters
 hipError_t launch_delta(const Launch &L, int respect_done, double2 *full_delta)
 {
     if (L.fp32)
-        hipLaunchKernelGGL(k_delta<float2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
+        hipLaunchKernelGGL(k_delta<float2>, dim3(L.total_march_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
                            L.batch, respect_done, full_delta);
     else
-        hipLaunchKernelGGL(k_delta<double2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
+        hipLaunchKernelGGL(k_delta<double2>, dim3(L.total_march_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
                            L.batch, respect_done, full_delta);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce(const Launch &L, int ncfg, int count_iter, int respect_done)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(ncfg), dim3(256), 0, L.stream, L.cfgs, count_iter, respect_done);
+    hipLaunchKernelGGL(k_reduce, dim3(ncfg), dim3(256), 0, L.stream, L.cfgs, count_iter, respect_done,
+                       count_iter ? L.fused : 0);
     return hipGetLastError();
 }
 
@@ -755,6 +1220,113 @@ hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *
     return hipGetLastError();
 }
 
+// 2D pass variants by tile capacity: (elements, work-items).
+#define GF_2D_VARIANTS(X) X(1024, 256) X(2048, 256) X(4096, 512)
+
+template <typename T2>
+static size_t lds2d(int cap, int tw2, int tw_total)
+{
+    (void)tw2;
+    return (size_t)(cap + tw_total) * sizeof(T2);
+}
+
+template <typename T2>
+static hipError_t run_xy(const Launch &L, int cap, dim3 grid, int sign, void *fo, int rd)
+{
+    const size_t sh = lds2d<T2>(cap, L.xy_tw2, L.xy_tw_total);
+#define X(C_, T_)                                                                                                 \
+    if (cap == C_) {                                                                                              \
+        hipLaunchKernelGGL((k_fft_xy<T2, C_, T_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, sign, fo, rd,      \
+                           L.xy_tw2);                                                                             \
+        return hipGetLastError();                                                                                 \
+    }
+    GF_2D_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <typename T2>
+static hipError_t run_zt(const Launch &L, int cap, dim3 grid, int mode, int sign, void *fo, int rd)
+{
+    const size_t sh = lds2d<T2>(cap, L.zt_tw2, L.zt_tw_total);
+#define X(C_, T_)                                                                                                 \
+    if (cap == C_) {                                                                                              \
+        hipLaunchKernelGGL((k_fft_zt<T2, C_, T_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, mode, sign, fo,    \
+                           rd, L.zt_tw2);                                                                         \
+        return hipGetLastError();                                                                                 \
+    }
+    GF_2D_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <typename T2>
+static hipError_t run_xyg(const Launch &L, int cap, int rd, double2 *go)
+{
+    const size_t sh = lds2d<T2>(cap, L.xy_tw2, L.xy_tw_total);
+#define X(C_, T_)                                                                                                 \
+    if (cap == C_) {                                                                                              \
+        hipLaunchKernelGGL((k_fft_xy_inv_gauge<T2, C_, T_>), dim3(L.total_xy_tiles), dim3(T_), sh, L.stream, L.cfgs, \
+                           L.batch, rd, go, L.xy_tw2);                                                            \
+        return hipGetLastError();                                                                                 \
+    }
+    GF_2D_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done)
+{
+    const dim3 grid(L.total_xy_tiles, nfields);
+    return L.fp32 ? run_xy<float2>(L, L.xy_cap, grid, sign, fields_override, respect_done)
+                  : run_xy<double2>(L, L.xy_cap, grid, sign, fields_override, respect_done);
+}
+
+hipError_t launch_fft_zt(const Launch &L, int mode, int sign, void *fields_override, int nfields, int respect_done)
+{
+    const dim3 grid(L.total_zt_tiles, nfields);
+    return L.fp32 ? run_zt<float2>(L, L.zt_cap, grid, mode, sign, fields_override, respect_done)
+                  : run_zt<double2>(L, L.zt_cap, grid, mode, sign, fields_override, respect_done);
+}
+
+hipError_t launch_fft_zt_scale(const Launch &L, int respect_done)
+{
+    return launch_fft_zt(L, 1, -1, nullptr, kFields, respect_done);
+}
+
+hipError_t launch_fft_xy_inv_gauge(const Launch &L, int respect_done, double2 *g_override)
+{
+    return L.fp32 ? run_xyg<float2>(L, L.xy_cap, respect_done, g_override)
+                  : run_xyg<double2>(L, L.xy_cap, respect_done, g_override);
+}
+
+template <typename T2>
+static hipError_t set_lds_t()
+{
+    const int bytes = (int)lds2d<T2>(4096, 256, 512);
+    hipError_t e = hipSuccess;
+#define X(C_, T_)                                                                                              \
+    if (e == hipSuccess)                                                                                       \
+        e = hipFuncSetAttribute((const void *)k_fft_xy<T2, C_, T_>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                bytes);                                                                        \
+    if (e == hipSuccess)                                                                                       \
+        e = hipFuncSetAttribute((const void *)k_fft_zt<T2, C_, T_>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                bytes);                                                                        \
+    if (e == hipSuccess)                                                                                       \
+        e = hipFuncSetAttribute((const void *)k_fft_xy_inv_gauge<T2, C_, T_>,                                  \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    GF_2D_VARIANTS(X)
+#undef X
+    return e;
+}
+
+hipError_t set_lds_limits()
+{
+    hipError_t e = set_lds_t<double2>();
+    if (e != hipSuccess) return e;
+    return set_lds_t<float2>();
+}
+
 hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override)
 {
     if (L.fp32)
@@ -766,9 +1338,30 @@ hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override)
     return hipGetLastError();
 }
 
+hipError_t launch_update_delta(const Launch &L)
+{
+    const dim3 grid(L.total_march_blocks), blk(kSiteBlock);
+    if (L.fp32) {
+        hipLaunchKernelGGL((k_update_delta<float2, false>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+        if (L.any_reunit) hipLaunchKernelGGL((k_update_delta<float2, true>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+    } else {
+        hipLaunchKernelGGL((k_update_delta<double2, false>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+        if (L.any_reunit)
+            hipLaunchKernelGGL((k_update_delta<double2, true>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_links_home(const Launch &L)
+{
+    hipLaunchKernelGGL(k_links_home, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs, L.batch);
+    hipLaunchKernelGGL(k_links_home_flag, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.ncfg);
+    return hipGetLastError();
+}
+
 hipError_t launch_update(const Launch &L, int respect_done, const double2 *g_override)
 {
-    hipLaunchKernelGGL(k_update, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs, L.batch,
+    hipLaunchKernelGGL(k_update, dim3(L.total_march_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs, L.batch,
                        respect_done, g_override, g_override ? 0 : 1);
     return hipGetLastError();
 }

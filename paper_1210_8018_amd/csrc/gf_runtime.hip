@@ -3,8 +3,10 @@
 // history and per-kernel timing. The library allocates no device memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -36,6 +38,9 @@ bool valid_length(int L)
     return L == 1;
 }
 
+bool xy_feasible(const int dims[4]) { return dims[0] * dims[1] <= kTileElems2D; }
+bool zt_feasible(const int dims[4]) { return dims[2] * dims[3] <= kTileElems2D; }
+
 bool valid_params(const gf_params *p)
 {
     if (!p) return false;
@@ -46,6 +51,9 @@ bool valid_params(const gf_params *p)
     if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return false;
     if (p->fft_prec != 0 && p->fft_prec != 1) return false;
     if (p->reunit_every < 0 || p->chunk < 0 || p->chunk > kHist) return false;
+    if (p->fft_schedule < 0 || p->fft_schedule >= kSchedCount) return false;
+    if (p->fft_schedule == kSchedXY1D && !xy_feasible(p->dims)) return false;
+    if (p->fft_schedule == kSchedXYZT && !(xy_feasible(p->dims) && zt_feasible(p->dims))) return false;
     return true;
 }
 
@@ -57,6 +65,41 @@ int largest_divisor_at_most(int n, int cap)
     return 1;
 }
 
+// Blocks of the t-marching kernels: kSiteBlock consecutive (x, y, z) sites
+// times `tch` t-slices. More slices per block save the re-read of the
+// t-neighbour at the first slice; fewer give more blocks.
+int plan_tchunk(const int dims[4])
+{
+    const int V3 = dims[0] * dims[1] * dims[2];
+    const int nb3 = (V3 + kSiteBlock - 1) / kSiteBlock;
+    const char *env = getenv("GF_TCHUNK");
+    if (env) {
+        const int t = atoi(env);
+        if (t >= 1 && dims[3] % t == 0) return t;
+    }
+    const int target = 1024;  // blocks wanted for 256 CUs
+    for (int nT = 1; nT <= dims[3]; ++nT)
+        if (dims[3] % nT == 0 && nb3 * nT >= target) return dims[3] / nT;
+    return 1;
+}
+
+// xy tiles: Q consecutive xy-planes, Q * Lx * Ly <= target elements.
+int plan_xyQ(const int dims[4], int target)
+{
+    const int V2 = dims[0] * dims[1];
+    return largest_divisor_at_most(dims[2] * dims[3], (target < kTileElems2D ? target : kTileElems2D) / V2);
+}
+
+// zt tiles: P consecutive xy-sites times the (z, t) plane; P is a power of
+// two dividing Lx * Ly (so it divides the block size).
+int plan_ztP(const int dims[4])
+{
+    const int V2 = dims[0] * dims[1], cap = kTileElems2D / (dims[2] * dims[3]);
+    int P = 1;
+    while (V2 % (2 * P) == 0 && 2 * P <= cap && 2 * P <= 256) P *= 2;
+    return P;
+}
+
 FftAxis plan_axis(const int dims[4], int mu)
 {
     FftAxis a{};
@@ -65,10 +108,13 @@ FftAxis plan_axis(const int dims[4], int mu)
     a.S = 1;
     for (int nu = 0; nu < mu; ++nu) a.S *= dims[nu];
     const int cap = kTileElems / a.L;
-    if (mu == 0)
+    if (mu == 0) {
         a.P = largest_divisor_at_most(V / a.L, cap);
-    else
-        a.P = largest_divisor_at_most(a.S, cap);
+    } else {
+        // rows of P consecutive elements, P a power of two dividing S and the block
+        a.P = 1;
+        while (a.S % (2 * a.P) == 0 && 2 * a.P <= cap && 2 * a.P <= kFftThreads) a.P *= 2;
+    }
     a.ntile = V / (a.P * a.L);
     a.inner_chunks = (mu == 0) ? 1 : a.S / a.P;
     int L = a.L, n = 0;
@@ -87,13 +133,16 @@ FftAxis plan_axis(const int dims[4], int mu)
 }
 
 struct Layout {
-    size_t fields, g, partials, sin2, tw, total;
+    size_t fields, g, partials, sin2, tw, links2, total;
 };
 
 Layout layout_for(const gf_params &p, size_t start)
 {
     const size_t V = (size_t)p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
-    const size_t nblk = (V + kSiteBlock - 1) / kSiteBlock;
+    const size_t nblk_site = (V + kSiteBlock - 1) / kSiteBlock;
+    const size_t V3 = (size_t)p.dims[0] * p.dims[1] * p.dims[2];
+    const size_t nblk_march = ((V3 + kSiteBlock - 1) / kSiteBlock) * (size_t)p.dims[3];  // upper bound (tch = 1)
+    const size_t nblk = nblk_site > nblk_march ? nblk_site : nblk_march;
     const size_t csz = p.fft_prec ? 8 : 16;
     const size_t sumL = (size_t)p.dims[0] + p.dims[1] + p.dims[2] + p.dims[3];
     Layout l;
@@ -108,6 +157,8 @@ Layout layout_for(const gf_params &p, size_t start)
     o = align_up(o + sumL * sizeof(double));
     l.tw = o;
     o = align_up(o + sumL * csz);
+    l.links2 = o;  // second link buffer of the fused update + divergence pass
+    o = align_up(o + 36 * V * 16);
     l.total = o;
     return l;
 }
@@ -148,14 +199,20 @@ struct gf_ctx_s {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    int sched = kSched1D;
+    int xy_target = 4096;
 };
 
 namespace {
 
-enum KId { K_DELTA, K_REDUCE, K_FFT0, K_FFT1, K_FFT2, K_FFT3S, K_IFFT2, K_IFFT1, K_IFFT0, K_GAUGE, K_UPDATE, K_N };
-const char *kNames[K_N] = {"delta_reduce_partials", "reduce_stop", "fft_x_fwd",  "fft_y_fwd",
-                           "fft_z_fwd",             "fft_t_scale", "fft_z_inv",  "fft_y_inv",
-                           "fft_x_inv",             "gauge_reunit", "link_update"};
+enum KId {
+    K_DELTA, K_REDUCE, K_FFT0, K_FFT1, K_FFT2, K_FFT3S, K_IFFT2, K_IFFT1, K_IFFT0, K_GAUGE, K_UPDATE,
+    K_FFTXY, K_FFTZT_S, K_IFFTXY_GAUGE, K_UPDATE_DELTA, K_N
+};
+const char *kNames[K_N] = {"delta_reduce_partials", "reduce_stop",  "fft_x_fwd",        "fft_y_fwd",
+                           "fft_z_fwd",             "fft_t_scale",  "fft_z_inv",        "fft_y_inv",
+                           "fft_x_inv",             "gauge_reunit", "link_update",      "fft_xy_fwd",
+                           "fft_zt_scale",          "fft_xy_inv_gauge", "link_update_delta"};
 
 gf_status fail_hip(gf_ctx c, hipError_t e, const char *where)
 {
@@ -210,25 +267,60 @@ gf_status collect_timing(gf_ctx c)
     return GF_OK;
 }
 
+// Transform of the four fields, scaling, inverse transform and g, as the
+// schedule in use arranges them (respect_done: skip finished configurations;
+// g_override: write g there instead of the workspace).
+hipError_t enqueue_gauge_steps(gf_ctx c, hipStream_t s, int respect_done, double2 *g_override)
+{
+    Launch L = c->L;
+    L.stream = s;
+    hipError_t e;
+    const int nf = kFields, rd = respect_done;
+#define GF_TRY(kid, call)                                                            \
+    if ((e = timed(c, kid, s, [&] { return call; })) != hipSuccess) return e;
+    switch (c->sched) {
+    case kSchedXYZT:
+        GF_TRY(K_FFTXY, launch_fft_xy(L, -1, nullptr, nf, rd));
+        GF_TRY(K_FFTZT_S, launch_fft_zt_scale(L, rd));
+        GF_TRY(K_IFFTXY_GAUGE, launch_fft_xy_inv_gauge(L, rd, g_override));
+        break;
+    case kSchedXY1D:
+        GF_TRY(K_FFTXY, launch_fft_xy(L, -1, nullptr, nf, rd));
+        GF_TRY(K_FFT2, launch_fft_axis(L, 2, -1, 0, nullptr, nf, rd));
+        GF_TRY(K_FFT3S, launch_fft_axis(L, 3, -1, 1, nullptr, nf, rd));
+        GF_TRY(K_IFFT2, launch_fft_axis(L, 2, +1, 0, nullptr, nf, rd));
+        GF_TRY(K_IFFTXY_GAUGE, launch_fft_xy_inv_gauge(L, rd, g_override));
+        break;
+    default:
+        GF_TRY(K_FFT0, launch_fft_axis(L, 0, -1, 0, nullptr, nf, rd));
+        GF_TRY(K_FFT1, launch_fft_axis(L, 1, -1, 0, nullptr, nf, rd));
+        GF_TRY(K_FFT2, launch_fft_axis(L, 2, -1, 0, nullptr, nf, rd));
+        GF_TRY(K_FFT3S, launch_fft_axis(L, 3, -1, 1, nullptr, nf, rd));
+        GF_TRY(K_IFFT2, launch_fft_axis(L, 2, +1, 0, nullptr, nf, rd));
+        GF_TRY(K_IFFT1, launch_fft_axis(L, 1, +1, 0, nullptr, nf, rd));
+        GF_TRY(K_IFFT0, launch_fft_axis(L, 0, +1, 0, nullptr, nf, rd));
+        GF_TRY(K_GAUGE, launch_gauge(L, rd, g_override));
+        break;
+    }
+    return hipSuccess;
+}
+
 // Alg. 1 inner loop body: transform, scale, transform back, g, link update,
 // re-measurement. Every kernel returns at once for configurations that are done.
 hipError_t enqueue_iteration(gf_ctx c, hipStream_t s)
 {
     Launch L = c->L;
     L.stream = s;
-    hipError_t e;
-    const int nf = kFields;
-    if ((e = timed(c, K_FFT0, s, [&] { return launch_fft_axis(L, 0, -1, 0, nullptr, nf, 1); })) != hipSuccess) return e;
-    if ((e = timed(c, K_FFT1, s, [&] { return launch_fft_axis(L, 1, -1, 0, nullptr, nf, 1); })) != hipSuccess) return e;
-    if ((e = timed(c, K_FFT2, s, [&] { return launch_fft_axis(L, 2, -1, 0, nullptr, nf, 1); })) != hipSuccess) return e;
-    if ((e = timed(c, K_FFT3S, s, [&] { return launch_fft_axis(L, 3, -1, 1, nullptr, nf, 1); })) != hipSuccess) return e;
-    if ((e = timed(c, K_IFFT2, s, [&] { return launch_fft_axis(L, 2, +1, 0, nullptr, nf, 1); })) != hipSuccess) return e;
-    if ((e = timed(c, K_IFFT1, s, [&] { return launch_fft_axis(L, 1, +1, 0, nullptr, nf, 1); })) != hipSuccess) return e;
-    if ((e = timed(c, K_IFFT0, s, [&] { return launch_fft_axis(L, 0, +1, 0, nullptr, nf, 1); })) != hipSuccess) return e;
-    if ((e = timed(c, K_GAUGE, s, [&] { return launch_gauge(L, 1, nullptr); })) != hipSuccess) return e;
-    if ((e = timed(c, K_UPDATE, s, [&] { return launch_update(L, 1, nullptr); })) != hipSuccess) return e;
-    if ((e = timed(c, K_DELTA, s, [&] { return launch_delta(L, 1, nullptr); })) != hipSuccess) return e;
-    if ((e = timed(c, K_REDUCE, s, [&] { return launch_reduce(L, c->ncfg, 1, 1); })) != hipSuccess) return e;
+    hipError_t e = enqueue_gauge_steps(c, s, 1, nullptr);
+    if (e != hipSuccess) return e;
+    if (L.fused) {
+        GF_TRY(K_UPDATE_DELTA, launch_update_delta(L));
+    } else {
+        GF_TRY(K_UPDATE, launch_update(L, 1, nullptr));
+        GF_TRY(K_DELTA, launch_delta(L, 1, nullptr));
+    }
+    GF_TRY(K_REDUCE, launch_reduce(L, c->ncfg, 1, 1));
+#undef GF_TRY
     return hipSuccess;
 }
 
@@ -248,7 +340,7 @@ gf_status build_graph(gf_ctx c)
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return fail_hip(c, e, "capture iteration");
     }
     HIPCHK(c, e2);
@@ -281,8 +373,22 @@ gf_status read_ctrl(gf_ctx c)
     return GF_OK;
 }
 
-// Run graph chunks until every configuration is done.
+gf_status run_chunks(gf_ctx c);
+
+// Run graph chunks until every configuration is done, then bring the links
+// back to the caller's array where the last update left them in the copy.
 gf_status run_until_done(gf_ctx c)
+{
+    gf_status st = run_chunks(c);
+    if (st != GF_OK) return st;
+    if (c->L.fused) {
+        HIPCHK(c, launch_links_home(c->L));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return GF_OK;
+}
+
+gf_status run_chunks(gf_ctx c)
 {
     if (c->timing) {
         // one iteration at a time, every kernel bracketed by events; polling
@@ -340,6 +446,156 @@ void fill_tables(const gf_params &p, std::vector<double> &sin2, std::vector<char
     }
 }
 
+// Tile shapes of the 2D passes for every configuration, and the launch
+// totals; uploads the configuration table.
+gf_status apply_schedule(gf_ctx c, int sched, int xy_target)
+{
+    Batch &b = c->bmap;
+    for (int k = 0; k < c->ncfg; ++k) {
+        Cfg &C = c->cfg[k];
+        C.xyQ = xy_feasible(C.dims) ? plan_xyQ(C.dims, xy_target) : 1;
+        C.nxy = xy_feasible(C.dims) ? (C.dims[2] * C.dims[3]) / C.xyQ : 0;
+        C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims) : 1;
+        C.nzt = zt_feasible(C.dims) ? C.V2 / C.ztP : 0;
+        b.off_xy[k + 1] = b.off_xy[k] + C.nxy;
+        b.off_zt[k + 1] = b.off_zt[k] + C.nzt;
+    }
+    c->L.total_xy_tiles = b.off_xy[c->ncfg];
+    c->L.total_zt_tiles = b.off_zt[c->ncfg];
+    int xy_max = 0, zt_max = 0, mx = 0, my = 0, mz = 0, mt = 0;
+    for (int k = 0; k < c->ncfg; ++k) {
+        const Cfg &C = c->cfg[k];
+        if (C.nxy) xy_max = std::max(xy_max, C.xyQ * C.V2);
+        if (C.nzt) zt_max = std::max(zt_max, C.ztP * C.dims[2] * C.dims[3]);
+        mx = std::max(mx, C.dims[0]);
+        my = std::max(my, C.dims[1]);
+        mz = std::max(mz, C.dims[2]);
+        mt = std::max(mt, C.dims[3]);
+    }
+    auto cap_for = [](int n) { return n <= 1024 ? 1024 : (n <= 2048 ? 2048 : 4096); };
+    c->L.xy_cap = cap_for(xy_max);
+    c->L.zt_cap = cap_for(zt_max);
+    c->L.xy_tw2 = mx;
+    c->L.xy_tw_total = mx + my;
+    c->L.zt_tw2 = mz;
+    c->L.zt_tw_total = mz + mt;
+    c->sched = sched;
+    c->xy_target = xy_target;
+    HIPCHK(c, hipMemcpyAsync(c->d_cfgs, c->cfg.data(), sizeof(Cfg) * c->ncfg, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_batch, &c->bmap, sizeof(Batch), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    return GF_OK;
+}
+
+bool sched_feasible(gf_ctx c, int sched)
+{
+    for (int k = 0; k < c->ncfg; ++k) {
+        const int *d = c->cfg[k].dims;
+        if (sched == kSchedXY1D && !xy_feasible(d)) return false;
+        if (sched == kSchedXYZT && !(xy_feasible(d) && zt_feasible(d))) return false;
+    }
+    return true;
+}
+
+std::string tune_key(gf_ctx c)
+{
+    std::string k = c->L.fp32 ? "c64" : "c128";
+    for (int i = 0; i < c->ncfg; ++i) {
+        char buf[64];
+        snprintf(buf, sizeof buf, ":%dx%dx%dx%d", c->cfg[i].dims[0], c->cfg[i].dims[1], c->cfg[i].dims[2],
+                 c->cfg[i].dims[3]);
+        k += buf;
+    }
+    return k;
+}
+
+std::vector<std::pair<std::string, std::pair<int, int>>> &tune_cache()
+{
+    static std::vector<std::pair<std::string, std::pair<int, int>>> cache;
+    static bool loaded = false;
+    if (!loaded) {
+        loaded = true;
+        const char *path = getenv("GF_AUTOTUNE_CACHE");
+        if (path) {
+            FILE *f = fopen(path, "r");
+            if (f) {
+                char key[4096];
+                int s, q;
+                while (fscanf(f, "%4095s %d %d", key, &s, &q) == 3) cache.push_back({key, {s, q}});
+                fclose(f);
+            }
+        }
+    }
+    return cache;
+}
+
+// Pick the transform schedule: the requested one, or (0) the fastest of the
+// feasible candidates timed on this context's fields, cached per shape.
+gf_status choose_schedule(gf_ctx c, int requested)
+{
+    if (requested != kSchedAuto) {
+        const char *env = getenv("GF_XY_TARGET");
+        return apply_schedule(c, requested, env ? atoi(env) : 1024);
+    }
+    const std::string key = tune_key(c);
+    for (auto &e : tune_cache())
+        if (e.first == key && sched_feasible(c, e.second.first))
+            return apply_schedule(c, e.second.first, e.second.second);
+    struct Cand {
+        int sched, xy;
+    };
+    std::vector<Cand> cands = {{kSched1D, 4096}};
+    for (int xy : {1024, 4096}) {
+        if (sched_feasible(c, kSchedXY1D)) cands.push_back({kSchedXY1D, xy});
+        if (sched_feasible(c, kSchedXYZT)) cands.push_back({kSchedXYZT, xy});
+    }
+    double best = 1e300;
+    Cand pick = cands[0];
+    hipEvent_t e0 = take_event(c), e1 = take_event(c);
+    if (!e0 || !e1) return GF_ERR_HIP;
+    const bool timing = c->timing;
+    c->timing = false;
+    for (const Cand &cd : cands) {
+        gf_status st = apply_schedule(c, cd.sched, cd.xy);
+        if (st != GF_OK) return st;
+        HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, nullptr));  // warm-up
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int r = 0; r < 3; ++r) HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, nullptr));
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            pick = cd;
+        }
+    }
+    c->timing = timing;
+    c->ev_used = 0;
+    // the fields were transformed in place: measure again so they hold Delta
+    HIPCHK(c, enqueue_measure(c));
+    gf_status st = apply_schedule(c, pick.sched, pick.xy);
+    if (st != GF_OK) return st;
+    tune_cache().push_back({key, {pick.sched, pick.xy}});
+    const char *path = getenv("GF_AUTOTUNE_CACHE");
+    if (path) {
+        FILE *f = fopen(path, "a");
+        if (f) {
+            fprintf(f, "%s %d %d\n", key.c_str(), pick.sched, pick.xy);
+            fclose(f);
+        }
+    }
+    return GF_OK;
+}
+
 gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links, void *d_ws, size_t ws_bytes,
                 void *stream)
 {
@@ -382,8 +638,14 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         Cfg &C = c->cfg[k];
         for (int mu = 0; mu < 4; ++mu) C.dims[mu] = p.dims[mu];
         C.V = p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
+        C.V2 = p.dims[0] * p.dims[1];
+        C.V3 = C.V2 * p.dims[2];
         C.nblk_site = (C.V + kSiteBlock - 1) / kSiteBlock;
+        C.nb3 = (C.V3 + kSiteBlock - 1) / kSiteBlock;
+        C.tch = plan_tchunk(p.dims);
+        C.nblk_march = C.nb3 * (p.dims[3] / C.tch);
         C.U = (double2 *)links[k];
+        C.U2 = (double2 *)(c->ws + l.links2);
         C.fields = c->ws + l.fields;
         C.g = (double2 *)(c->ws + l.g);
         C.partials = (double *)(c->ws + l.partials);
@@ -406,6 +668,7 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
             if (e > max_lds) max_lds = e;
         }
         b.off_site[k + 1] = b.off_site[k] + C.nblk_site;
+        b.off_march[k + 1] = b.off_march[k] + C.nblk_march;
         for (int mu = 0; mu < 4; ++mu) b.off_fft[mu][k + 1] = b.off_fft[mu][k] + C.ax[mu].ntile;
         o = l.total;
     }
@@ -413,13 +676,17 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         c->err = "workspace too small";
         return GF_ERR_SHAPE;
     }
-    b.max_lds_elems = max_lds;
     c->L.cfgs = c->d_cfgs;
     c->L.batch = c->d_batch;
     c->L.total_site_blocks = b.off_site[ncfg];
+    c->L.total_march_blocks = b.off_march[ncfg];
     for (int mu = 0; mu < 4; ++mu) c->L.total_fft_tiles[mu] = b.off_fft[mu][ncfg];
     c->L.max_lds_elems = max_lds;
     c->L.fp32 = params[0].fft_prec;
+    c->L.fused = getenv("GF_NOFUSE") ? 0 : 1;
+    c->L.any_reunit = 0;
+    for (int k = 0; k < ncfg; ++k) c->L.any_reunit |= params[k].reunit_every > 0;
+    c->L.ncfg = ncfg;
     c->L.stream = c->stream;
 
     HIPCHK(c, hipMemcpyAsync(c->d_cfgs, c->cfg.data(), sizeof(Cfg) * ncfg, hipMemcpyHostToDevice, c->stream));
@@ -430,9 +697,12 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         HIPCHK(c, hipMemcpyAsync((void *)c->cfg[k].tw, tws[k].data(), tws[k].size(), hipMemcpyHostToDevice,
                                  c->stream));
     }
+    HIPCHK(c, set_lds_limits());
     HIPCHK(c, launch_arm(c->L, ncfg, 0.0, 0, 1));
     HIPCHK(c, enqueue_measure(c));
-    return read_ctrl(c);
+    gf_status st = read_ctrl(c);
+    if (st != GF_OK) return st;
+    return choose_schedule(c, params[0].fft_schedule);
 }
 
 size_t workspace_total(int ncfg, const gf_params *params)
@@ -470,7 +740,9 @@ size_t gf_workspace_bytes_batch(int32_t n_cfg, const gf_params *params)
 {
     if (n_cfg < 1 || n_cfg > kMaxCfg || !params) return 0;
     for (int k = 0; k < n_cfg; ++k)
-        if (params[k].fft_prec != params[0].fft_prec || params[k].chunk != params[0].chunk) return 0;
+        if (params[k].fft_prec != params[0].fft_prec || params[k].chunk != params[0].chunk ||
+            params[k].fft_schedule != params[0].fft_schedule)
+            return 0;
     return workspace_total(n_cfg, params);
 }
 
@@ -614,16 +886,8 @@ gf_status gf_gauge(gf_ctx c, void *d_g)
 {
     if (!c || !d_g) return GF_ERR_ARG;
     if (c->batch) return GF_ERR_STATE;
-    Launch L = c->L;
-    HIPCHK(c, launch_delta(L, 0, nullptr));
-    HIPCHK(c, launch_fft_axis(L, 0, -1, 0, nullptr, kFields, 0));
-    HIPCHK(c, launch_fft_axis(L, 1, -1, 0, nullptr, kFields, 0));
-    HIPCHK(c, launch_fft_axis(L, 2, -1, 0, nullptr, kFields, 0));
-    HIPCHK(c, launch_fft_axis(L, 3, -1, 1, nullptr, kFields, 0));
-    HIPCHK(c, launch_fft_axis(L, 2, +1, 0, nullptr, kFields, 0));
-    HIPCHK(c, launch_fft_axis(L, 1, +1, 0, nullptr, kFields, 0));
-    HIPCHK(c, launch_fft_axis(L, 0, +1, 0, nullptr, kFields, 0));
-    HIPCHK(c, launch_gauge(L, 0, (double2 *)d_g));
+    HIPCHK(c, launch_delta(c->L, 0, nullptr));
+    HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, (double2 *)d_g));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return GF_OK;
 }
@@ -642,7 +906,20 @@ gf_status gf_fft(gf_ctx c, void *d_fields, int32_t nfields, int32_t sign)
 {
     if (!c || !d_fields || nfields < 1 || nfields > 65535 || (sign != 1 && sign != -1)) return GF_ERR_ARG;
     if (c->batch) return GF_ERR_STATE;
-    for (int mu = 0; mu < 4; ++mu) HIPCHK(c, launch_fft_axis(c->L, mu, sign, 0, d_fields, nfields, 0));
+    const Launch &L = c->L;
+    switch (c->sched) {
+    case kSchedXYZT:
+        HIPCHK(c, launch_fft_xy(L, sign, d_fields, nfields, 0));
+        HIPCHK(c, launch_fft_zt(L, 0, sign, d_fields, nfields, 0));
+        break;
+    case kSchedXY1D:
+        HIPCHK(c, launch_fft_xy(L, sign, d_fields, nfields, 0));
+        HIPCHK(c, launch_fft_axis(L, 2, sign, 0, d_fields, nfields, 0));
+        HIPCHK(c, launch_fft_axis(L, 3, sign, 0, d_fields, nfields, 0));
+        break;
+    default:
+        for (int mu = 0; mu < 4; ++mu) HIPCHK(c, launch_fft_axis(L, mu, sign, 0, d_fields, nfields, 0));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return GF_OK;
 }
@@ -676,11 +953,11 @@ gf_status gf_functional_g_backward(gf_ctx c, const double *d_omega, double grad_
 gf_status gf_destroy(gf_ctx c)
 {
     if (!c) return GF_ERR_ARG;
-    if (c->gexec) hipGraphExecDestroy(c->gexec);
-    if (c->graph) hipGraphDestroy(c->graph);
-    for (auto e : c->ev_pool) hipEventDestroy(e);
-    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-    if (c->h_ctrl) hipHostFree(c->h_ctrl);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
     delete c;
     return GF_OK;
 }
@@ -709,6 +986,8 @@ gf_status gf_set_timing(gf_ctx c, int32_t on)
 }
 
 int32_t gf_kernel_count(gf_ctx c) { return c ? (int32_t)c->kt.size() : 0; }
+
+int32_t gf_fft_schedule(gf_ctx c) { return c ? c->sched : 0; }
 
 const char *gf_kernel_name(gf_ctx c, int32_t k)
 {

@@ -25,7 +25,7 @@ class gf_params(ctypes.Structure):
         ("fft_prec", ctypes.c_int32),
         ("reunit_every", ctypes.c_int32),
         ("chunk", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fft_schedule", ctypes.c_int32),
     ]
 
 
@@ -79,6 +79,7 @@ def lib():
             "gf_kernel_name": (ctypes.c_char_p, [P, I32]),
             "gf_kernel_time": (st, [P, I32, PD, PI64]),
             "gf_reset_timing": (st, [P]),
+            "gf_fft_schedule": (I32, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -99,7 +100,7 @@ def _check(status: int, where: str, ctx=None, ok=(GF_OK,)):
     return status
 
 
-def make_params(dims, alpha=0.08, fft_prec=0, reunit_every=0, chunk=0) -> gf_params:
+def make_params(dims, alpha=0.08, fft_prec=0, reunit_every=0, chunk=0, fft_schedule=0) -> gf_params:
     p = gf_params()
     for k in range(4):
         p.dims[k] = int(dims[k])
@@ -107,7 +108,7 @@ def make_params(dims, alpha=0.08, fft_prec=0, reunit_every=0, chunk=0) -> gf_par
     p.fft_prec = int(fft_prec)
     p.reunit_every = int(reunit_every)
     p.chunk = int(chunk)
-    p.reserved = 0
+    p.fft_schedule = int(fft_schedule)
     return p
 
 
@@ -243,6 +244,10 @@ def gf_kernel_times(ctx):
         _check(lib().gf_kernel_time(ctx, k, ctypes.byref(ms), ctypes.byref(n)), "gf_kernel_time", ctx)
         out[lib().gf_kernel_name(ctx, k).decode()] = (ms.value, n.value)
     return out
+
+
+def gf_fft_schedule(ctx) -> int:
+    return int(lib().gf_fft_schedule(ctx))
 
 
 def gf_reset_timing(ctx):

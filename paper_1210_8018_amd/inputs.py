@@ -28,6 +28,8 @@ Links are returned in structure-of-arrays form, complex128 of shape
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 __all__ = [
@@ -68,23 +70,132 @@ def gell_mann() -> np.ndarray:
     return l
 
 
-def haar_su3(rng: np.random.Generator, n: int) -> np.ndarray:
-    """``n`` Haar-distributed SU(3) matrices, shape (n, 3, 3) (Mezzadri 2007)."""
-    z = rng.standard_normal((n, 3, 3, 2))
+def _workers() -> int:
+    return max(1, min(16, int(os.environ.get("GF_GEN_PROCS", os.cpu_count() or 1))))
+
+
+_POOL_MIN = 1 << 20  # sites from which the per-matrix arithmetic is spread over processes
+
+
+def _shm_put(arr, owned):
+    from multiprocessing import shared_memory
+
+    shm = shared_memory.SharedMemory(create=True, size=max(1, arr.nbytes))
+    owned.append(shm)
+    np.ndarray(arr.shape, arr.dtype, buffer=shm.buf)[...] = arr
+    return (shm.name, arr.shape, arr.dtype.str)
+
+
+def _shm_get(desc, keep):
+    from multiprocessing import resource_tracker, shared_memory
+
+    name, shape, dt = desc
+    shape = tuple(shape)
+    shm = shared_memory.SharedMemory(name=name)
+    # the parent owns (and unlinks) every block; do not let this process's
+    # resource tracker claim it
+    try:
+        resource_tracker.unregister(shm._name, "shared_memory")
+    except Exception:
+        pass
+    keep.append(shm)
+    return np.ndarray(shape, np.dtype(dt), buffer=shm.buf)
+
+
+def _worker_main():
+    """Entry of a generator worker process: one slice of one per-matrix job.
+
+    Reads a JSON job from stdin: the shared-memory blocks of the inputs and
+    the output, the slice [a, b) and eps.
+    """
+    import json
+    import sys
+
+    job = json.loads(sys.stdin.read())
+    keep = []
+    try:
+        arrs = [_shm_get(tuple(d), keep) for d in job["descs"]]
+        a, b = job["a"], job["b"]
+        if job["kind"] == "haar":
+            z, out = arrs
+            out[a:b] = _haar_from_ginibre(z[a:b])
+        else:
+            h, w, fwd, out = arrs
+            out[a:b] = _link_block(h[a:b], job["eps"] * w[a:b], h[fwd[a:b]])
+    finally:
+        for m in keep:
+            m.close()
+
+
+def _parallel(kind, n, inputs, out_shape, eps=0.0):
+    """Per-matrix arithmetic of `kind` over n matrices in worker processes.
+
+    Each worker is a fresh interpreter that reads its slice of the inputs and
+    writes its slice of the output in shared memory, so the result is bitwise
+    the serial one.
+    """
+    import json
+    import subprocess
+    import sys
+
+    owned = []
+    procs = []
+    try:
+        descs = [_shm_put(x, owned) for x in inputs]
+        out_desc = _shm_put(np.zeros(out_shape, np.complex128), owned)
+        nw = _workers()
+        bounds = np.linspace(0, n, nw + 1).astype(int)
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        code = "from paper_1210_8018_amd.inputs import _worker_main; _worker_main()"
+        for k in range(nw):
+            job = json.dumps({"kind": kind, "a": int(bounds[k]), "b": int(bounds[k + 1]), "eps": float(eps),
+                              "descs": [list(d) for d in descs + [out_desc]]})
+            p = subprocess.Popen([sys.executable, "-c", code], stdin=subprocess.PIPE, cwd=root)
+            p.stdin.write(job.encode())
+            p.stdin.close()
+            procs.append(p)
+        for p in procs:
+            if p.wait(timeout=1800) != 0:
+                raise RuntimeError(f"input generator worker failed with status {p.returncode}")
+        return np.array(np.ndarray(out_shape, np.complex128, buffer=owned[-1].buf))
+    finally:
+        for p in procs:
+            if p.poll() is None:
+                p.kill()
+                p.wait()
+        for m in owned:
+            m.close()
+            m.unlink()
+
+
+def _haar_from_ginibre(z: np.ndarray) -> np.ndarray:
     g = (z[..., 0] + 1j * z[..., 1]) / np.sqrt(2.0)
     q, r = np.linalg.qr(g)
     d = np.diagonal(r, axis1=-2, axis2=-1)
     ph = d / np.abs(d)
     q = q * ph[:, None, :]
     det = np.linalg.det(q)
-    q = q / (det ** (1.0 / 3.0))[:, None, None]
-    return q
+    return q / (det ** (1.0 / 3.0))[:, None, None]
+
+
+def haar_su3(rng: np.random.Generator, n: int) -> np.ndarray:
+    """``n`` Haar-distributed SU(3) matrices, shape (n, 3, 3) (Mezzadri 2007)."""
+    z = rng.standard_normal((n, 3, 3, 2))
+    if n >= _POOL_MIN and _workers() > 1:
+        return _parallel("haar", n, [z], (n, 3, 3))
+    return _haar_from_ginibre(z)
 
 
 def _expi_hermitian(h: np.ndarray) -> np.ndarray:
     """exp(i h) for a stack of hermitian matrices, via eigendecomposition."""
     w, v = np.linalg.eigh(h)
     return (v * np.exp(1j * w)[..., None, :]) @ np.conj(np.swapaxes(v, -1, -2))
+
+
+def _link_block(hx, ew, hf):
+    """h(x) exp(i sum_a lambda_a ew_a) h^dag(x + mu) for a block of sites."""
+    herm = np.einsum("va,aij->vij", ew, gell_mann())
+    return hx @ _expi_hermitian(herm) @ np.conj(np.swapaxes(hf, -1, -2))
 
 
 def _neighbour_forward(dims, mu: int) -> np.ndarray:
@@ -126,14 +237,14 @@ def random_links(dims, eps: float, seed: int, *, rng: np.random.Generator | None
     else:
         h = haar_su3(rng, V)
     w = rng.standard_normal((4, V, 8))
-    lam = gell_mann()
     u = np.empty((4, V, 3, 3), dtype=np.complex128)
+    hc = np.ascontiguousarray(h)
     for mu in range(4):
-        herm = np.einsum("va,aij->vij", eps * w[mu], lam)
-        vmu = _expi_hermitian(herm)
         fwd = _neighbour_forward(dims, mu)
-        u[mu] = h @ vmu @ np.conj(np.swapaxes(h[fwd], -1, -2))
-        del herm, vmu
+        if V >= _POOL_MIN and _workers() > 1:
+            u[mu] = _parallel("link", V, [hc, w[mu], fwd], (V, 3, 3), eps=eps)
+        else:
+            u[mu] = _link_block(hc, eps * w[mu], hc[fwd])
     return aos_to_soa(u, dims)
 
 

@@ -53,13 +53,18 @@ def test_delta_and_functional(dims):
     assert rel(F, Fr) < 1e-14 and rel(th, thr) < 1e-14
 
 
+SCHEDULES = [1, 2, 3]  # 1D passes; (x,y) + 1D z, t; (x,y) + (z,t)
+
+
 @pytest.mark.parametrize("dims", SHAPES)
 @pytest.mark.parametrize("prec", [0, 1])
-def test_fft_matches_oracle(dims, prec):
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_fft_matches_oracle(dims, prec, sched):
     V = int(np.prod(dims))
     rng = np.random.default_rng(42)
     f = rng.standard_normal((3, V)) + 1j * rng.standard_normal((3, V))
-    fx = GaugeFixer(dev(random_links(dims, 0.3, 1)), fft_prec=prec)
+    fx = GaugeFixer(dev(random_links(dims, 0.3, 1)), fft_prec=prec, fft_schedule=sched)
+    assert gf.gf_fft_schedule(fx.ctx) == sched
     ct = torch.complex64 if prec else torch.complex128
     tol = 3e-6 if prec else 1e-13
     for sign in (-1, +1):
@@ -72,9 +77,10 @@ def test_fft_matches_oracle(dims, prec):
 
 @pytest.mark.parametrize("dims", SHAPES)
 @pytest.mark.parametrize("prec", [0, 1])
-def test_gauge_vector_matches_oracle(dims, prec):
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_gauge_vector_matches_oracle(dims, prec, sched):
     U = random_links(dims, 0.4, 43)
-    fx = GaugeFixer(dev(U), fft_prec=prec)
+    fx = GaugeFixer(dev(U), fft_prec=prec, fft_schedule=sched)
     g = host(fx.gauge())
     gref = oracle.gauge_from_delta(dims, oracle.delta(dims, U), ALPHA)
     assert np.max(np.abs(g - gref)) < (2e-6 if prec else 1e-13)
@@ -118,11 +124,12 @@ def compare_trajectory(F, T, Fr, Tr, V):
 
 
 @pytest.mark.parametrize("dims,eps,seed", [((8, 8, 8, 8), 0.3, 1), ((12, 8, 6, 4), 0.3, 3), ((6, 6, 6, 2), 0.35, 4)])
-def test_trajectory_matches_oracle(dims, eps, seed):
+@pytest.mark.parametrize("sched", [0] + SCHEDULES)
+def test_trajectory_matches_oracle(dims, eps, seed, sched):
     U = random_links(dims, eps, seed)
     n_ref, U_ref, Fr, Tr = oracle.fix(dims, U, alpha=ALPHA, eps=EPS, max_iter=5000)
     Ud = dev(U)
-    fx = GaugeFixer(Ud)
+    fx = GaugeFixer(Ud, fft_schedule=sched)
     it, F, th = fx.fix_until(EPS, 5000)
     Fh, Th = fx.history()
     assert abs(it - n_ref) <= max(0, int(0.01 * n_ref)), (it, n_ref)
@@ -224,6 +231,18 @@ def test_nonfinite_and_maxiter_statuses():
     assert e.value.status == gf.GF_ERR_NONFINITE
 
 
+def test_wide_planes_fall_back_to_1d_passes():
+    """Lx*Ly > 4096: the 2D (x, y) pass does not fit; the autotuner keeps 1D passes."""
+    dims = (96, 48, 2, 2)
+    assert gf.gf_workspace_bytes(gf.make_params(dims, fft_schedule=2)) == 0
+    U = random_links(dims, 0.3, 45)
+    fx = GaugeFixer(dev(U))
+    assert gf.gf_fft_schedule(fx.ctx) == 1
+    g = host(fx.gauge())
+    gref = oracle.gauge_from_delta(dims, oracle.delta(dims, U), ALPHA)
+    assert np.max(np.abs(g - gref)) < 1e-13
+
+
 def test_invalid_shapes_rejected():
     assert gf.gf_workspace_bytes(gf.make_params((5, 8, 8, 8))) == 0
     assert gf.gf_workspace_bytes(gf.make_params((1, 8, 8, 8))) == 0
@@ -231,18 +250,18 @@ def test_invalid_shapes_rejected():
     assert gf.gf_workspace_bytes(gf.make_params((8, 8, 8, 8), alpha=-1)) == 0
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_batch_equals_single_runs(prec):
+@pytest.mark.parametrize("prec,sched", [(0, 1), (0, 3), (1, 2), (1, 3)])
+def test_batch_equals_single_runs(prec, sched):
     """Each configuration of a batch evolves bitwise as in its own context."""
     cases = [((8, 8, 8, 8), 0.3, 1), ((6, 4, 8, 4), 0.25, 2), ((12, 8, 6, 4), 0.45, 3), ((4, 4, 4, 4), 0.2, 4)]
     Us = [random_links(d, e, s) for d, e, s in cases]
     single = []
     for U in Us:
         Ud = dev(U)
-        fx = GaugeFixer(Ud, fft_prec=prec)
+        fx = GaugeFixer(Ud, fft_prec=prec, fft_schedule=sched)
         single.append((fx.fix_until(EPS, 20000), host(Ud)))
     Ubs = [dev(U) for U in Us]
-    bx = BatchGaugeFixer(Ubs, fft_prec=prec)
+    bx = BatchGaugeFixer(Ubs, fft_prec=prec, fft_schedule=sched)
     its, Fs, ths = bx.fix_until(EPS, 20000)
     for k in range(len(cases)):
         (it, F, th), Uf = single[k]
