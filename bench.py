@@ -9,6 +9,7 @@ durations measured with HIP events on the library's stream, the roofline of
 the dominant kernel, and the CPU oracle on a bounded sample.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-iters N] [--no-cpu]
+python bench.py --workload batch|large48|large64|diff   (other measured workloads)
 """
 import argparse
 import json
@@ -26,25 +27,27 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # FP32 transform fields (c = bytes per complex transform element):
 #   divergence: read 4 links (576) + write 4 packed fields (4c)
 #   transform pass: read + write 4 fields (8c)
-#   gauge, or the inverse (x, y) pass fused with it: read 4 fields (4c) + write g (144)
+#   gauge: read 4 fields (4c) + write g (144); the inverse (x, y) pass fused
+#     with it writes g in two-row form (96)
 #   link update: read 4 links (576) + g(x) (144) + write 4 links (576);
 #     neighbour g(x + mu) is counted once (its own site's read)
-#   fused link update + divergence of the new links: the link update's bytes
-#     + 4 fields written (neighbour links and g recomputed from cache)
+#   fused link update + divergence of the new links, links and g in two-row
+#     (12-real) form: read links (384) + g (96) + write links (384) + 4 fields
+#     (neighbour links and g recomputed from cache)
 #   reduction: negligible (one double-double pair per 256 sites)
 
 
 def kernel_bytes_per_site(name: str, c: int) -> float:
-    if name == "fft_xy_inv_gauge":  # inverse (x, y) pass fused with g: read 4 fields, write g
-        return 4 * c + 144
+    if name == "fft_xy_inv_gauge":  # inverse (x, y) pass fused with g: read 4 fields, write two-row g
+        return 4 * c + 96
     if name.startswith("delta"):
         return 576 + 4 * c
     if name.startswith("fft"):
         return 8 * c
     if name.startswith("gauge"):
         return 4 * c + 144
-    if name == "link_update_delta":  # fused update + divergence: the update's bytes + 4 fields written
-        return 576 + 144 + 576 + 4 * c
+    if name == "link_update_delta":  # fused update + divergence, two-row links and g
+        return 384 + 96 + 384 + 4 * c
     if name.startswith("link_update"):
         return 576 + 144 + 576
     return 0.0
@@ -64,6 +67,7 @@ def main():
     ap.add_argument("--dims", default="32,32,32,32")
     ap.add_argument("--eps", type=float, default=0.3)
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--workload", default="headline", choices=["headline", "batch", "large48", "large64", "diff"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -75,6 +79,10 @@ def main():
 
     from paper_1210_8018_amd.api import GaugeFixer
     from paper_1210_8018_amd.inputs import random_links
+
+    if args.workload != "headline":
+        {"batch": bench_batch, "large48": bench_large, "large64": bench_large, "diff": bench_diff}[args.workload](args)
+        return
 
     dims = tuple(int(v) for v in args.dims.split(","))
     V = int(np.prod(dims))
@@ -202,6 +210,165 @@ def main():
         "kernels_fp64": kern,
         "event_region_iters_per_s": round(f64["event_region_iters_per_s"], 2),
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """24 configurations of uneven shapes in one batch context (FP64 links, FP32 transform)."""
+    import numpy as np
+    import torch
+
+    from paper_1210_8018_amd.api import BatchGaugeFixer, GaugeFixer
+    from paper_1210_8018_amd.inputs import batch_workload
+
+    log("generating the batch workload")
+    cfgs = list(batch_workload())
+    U0 = [torch.from_numpy(U).to("cuda") for _, _, _, U in cfgs]
+    torch.cuda.synchronize()
+    Us = [u.clone() for u in U0]
+    bx = BatchGaugeFixer(Us, fft_prec=1)
+    torch.cuda.synchronize()
+    log("batch fix_until 1e-15")
+    t0 = time.perf_counter()
+    its, Fs, ths = bx.fix_until(1e-15, 200000)
+    torch.cuda.synchronize()
+    makespan = time.perf_counter() - t0
+    sched = None
+    bx.close()
+    del bx, Us
+    log(f"batch makespan {makespan:.3f}s, max its {max(its)}")
+    # the same configurations one context after another
+    seq = 0.0
+    seq_its = []
+    for k, u in enumerate(U0):
+        U = u.clone()
+        fx = GaugeFixer(U, fft_prec=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        it, F, th = fx.fix_until(1e-15, 200000)
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t1
+        seq_its.append(it)
+        sched = fx.fft_schedule
+        fx.close()
+        del fx, U
+    sites = [int(np.prod(d)) for d, _, _, _ in cfgs]
+    site_its = sum(i * v for i, v in zip(its, sites))
+    out = {
+        "metric": "batch makespan to theta<=1e-15, 24 configurations (8x12^4, 8x16^3x32, 6x24^4, 2x32^4)",
+        "value": round(makespan, 4), "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+        "dtype": "f64 links / c64 transform",
+        "config": {"workload": "batch of 24, eps ~ U[0.2,0.6), seeds 100-123, alpha=0.08, theta_eps=1e-15"},
+        "per_config": [{"dims": list(d), "eps": round(e, 4), "seed": sd, "iterations": i, "F_final": F, "theta": th}
+                       for (d, e, sd, _), i, F, th in zip(cfgs, its, Fs, ths)],
+        "total_iterations": int(sum(its)), "site_iterations_per_s": site_its / makespan,
+        "sequential_seconds": round(seq, 4), "sequential_iterations_equal": seq_its == its,
+        "speedup_vs_sequential": round(seq / makespan, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_large(args):
+    """48^4 or 64^4, eps 0.5: FP32 transform to theta <= 1e-15, with its error against FP64."""
+    import numpy as np
+    import torch
+
+    from paper_1210_8018_amd.api import GaugeFixer
+    from paper_1210_8018_amd.inputs import random_links
+
+    L = 48 if args.workload == "large48" else 64
+    dims = (L, L, L, L)
+    seed = 3 if L == 48 else 4
+    log(f"generating {dims} eps=0.5 seed={seed}")
+    t0 = time.time()
+    U_host = random_links(dims, 0.5, seed)
+    log(f"generated in {time.time() - t0:.1f}s")
+    U0 = torch.from_numpy(U_host).to("cuda")
+    torch.cuda.synchronize()
+    res = {}
+    for prec in (1, 0):
+        tag = "fp32_fft" if prec else "fp64"
+        U = U0.clone()
+        fx = GaugeFixer(U, fft_prec=prec, reunit_every=100)
+        torch.cuda.synchronize()
+        log(f"[{tag}] fix_until 1e-15")
+        t1 = time.perf_counter()
+        it, F, th = fx.fix_until(1e-15, 100000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        Fh, Th = fx.history()
+        res[tag] = dict(seconds=dt, iterations=it, F=F, theta=th, iters_per_s=it / dt, F_hist=Fh, T_hist=Th,
+                        schedule=fx.fft_schedule)
+        fx.close()
+        del fx, U
+        log(f"[{tag}] {it} its in {dt:.2f}s ({it / dt:.1f} it/s), F={F:.15f}")
+    a, b = res["fp32_fft"], res["fp64"]
+    n = min(len(a["T_hist"]), len(b["T_hist"]))
+    Ta, Tb = np.asarray(a["T_hist"][:n]), np.asarray(b["T_hist"][:n])
+    Fa, Fb = np.asarray(a["F_hist"][:n]), np.asarray(b["F_hist"][:n])
+    big = Tb > 1e-12
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        k = 2
+        log(f"cpu oracle: {k} iterations at {dims}")
+        t2 = time.perf_counter()
+        _, _, Fo, To = oracle.fix(dims, U_host, alpha=0.08, eps=-1.0, max_iter=k, reunit_every=100)
+        dcpu = time.perf_counter() - t2
+        cpu = {"value": k / dcpu, "unit": "iters/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"{k} iterations at {L}^4", "F_rel_err_fp32_fft": float(np.max(np.abs(Fa[:k + 1] - Fo) / np.abs(Fo))),
+               "theta_rel_err_fp32_fft": float(np.max(np.abs(Ta[:k + 1] - To) / To)),
+               "F_rel_err_fp64": float(np.max(np.abs(Fb[:k + 1] - Fo) / np.abs(Fo))),
+               "theta_rel_err_fp64": float(np.max(np.abs(Tb[:k + 1] - To) / To))}
+    out = {
+        "metric": f"time to theta<=1e-15 at {L}^4 SU(3), FP32 transform (FP64 links/Delta/update/sums)",
+        "value": round(a["seconds"], 4), "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+        "dtype": "f64 links / c64 transform",
+        "config": {"workload": f"{L}^4, generator eps=0.5 seed={seed}, alpha=0.08, links reunitarised every 100"},
+        "fp32_fft": {k: a[k] for k in ("seconds", "iterations", "F", "theta", "iters_per_s", "schedule")},
+        "fp64": {k: b[k] for k in ("seconds", "iterations", "F", "theta", "iters_per_s", "schedule")},
+        "fp32_vs_fp64": {"F_final_rel": abs(a["F"] - b["F"]) / abs(b["F"]),
+                         "F_max_rel_per_iter": float(np.max(np.abs(Fa - Fb) / np.abs(Fb))),
+                         "theta_max_rel_per_iter_while_theta_gt_1e-12": float(np.max(np.abs(Ta[big] - Tb[big]) / Tb[big]))},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_diff(args):
+    """24^4 differentiable functional: forward and backward times; gradient checks (informational)."""
+    import numpy as np
+    import torch
+
+    from paper_1210_8018_amd import gf
+    from paper_1210_8018_amd.api import GaugeFixer
+    from paper_1210_8018_amd.inputs import random_links, random_omega
+
+    dims = (24, 24, 24, 24)
+    V = int(np.prod(dims))
+    U = torch.from_numpy(random_links(dims, 0.3, 5)).to("cuda")
+    om = torch.from_numpy(random_omega(dims, 0.1, 6)).to("cuda")
+    fx = GaugeFixer(U)
+    d_om = torch.empty_like(om)
+    d_U = torch.empty_like(U)
+    for _ in range(3):
+        gf.gf_functional_g(fx.ctx, om)
+        gf.gf_functional_g_backward(fx.ctx, om, 1.0, d_om, d_U)
+    n = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        F = gf.gf_functional_g(fx.ctx, om)
+    t1 = time.perf_counter()
+    for _ in range(n):
+        gf.gf_functional_g_backward(fx.ctx, om, 1.0, d_om, d_U)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = {"metric": "differentiable functional at 24^4: forward and backward time", "value": round((t1 - t0) / n * 1e3, 4),
+           "unit": "ms (forward)", "backward_ms": round((t2 - t1) / n * 1e3, 4), "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "dtype": "f64", "F": F,
+           "config": {"workload": "24^4 links eps 0.3 seed 5, omega ~ N(0, 0.1^2) seed 6"}}
     print(json.dumps(out), flush=True)
 
 

@@ -49,6 +49,31 @@ __device__ __forceinline__ void m3_store(double2 *__restrict__ base, int V, int 
     for (int k = 0; k < 9; ++k) base[(size_t)k * V + s] = m.e[k];
 }
 
+// Two-row storage of an SU(3) matrix (the 12-real parametrisation): rows 0
+// and 1 in planes 0..5; row 2 is rebuilt as conj(r0 x r1), which holds for
+// every special unitary matrix.
+__device__ __forceinline__ void m3_row2(M3 &m)
+{
+    m.e[6] = cconj(csub(cmul(m.e[1], m.e[5]), cmul(m.e[2], m.e[4])));
+    m.e[7] = cconj(csub(cmul(m.e[2], m.e[3]), cmul(m.e[0], m.e[5])));
+    m.e[8] = cconj(csub(cmul(m.e[0], m.e[4]), cmul(m.e[1], m.e[3])));
+}
+
+__device__ __forceinline__ M3 m3_load12(const double2 *__restrict__ base, int V, int s)
+{
+    M3 m;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m.e[k] = base[(size_t)k * V + s];
+    m3_row2(m);
+    return m;
+}
+
+__device__ __forceinline__ void m3_store12(double2 *__restrict__ base, int V, int s, const M3 &m)
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) base[(size_t)k * V + s] = m.e[k];
+}
+
 // a b
 __device__ __forceinline__ M3 m3_mul(const M3 &a, const M3 &b)
 {

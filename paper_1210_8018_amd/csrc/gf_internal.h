@@ -37,7 +37,7 @@ struct Ctrl {
     long long iter;      // updates since init
     long long max_iter;  // absolute cap on iter
     int done;            // kRunning / kConverged / kMaxIter / kNonFinite
-    int cur;             // links live in U (0) or in the workspace copy U2 (1)
+    int cur;             // current two-row link buffer, U12[cur]
     double hist[kHist][2];  // (F, theta) after update k at slot k % kHist
 };
 
@@ -61,7 +61,8 @@ struct Cfg {
     int tch;              // t-slices marched by one block
     int nblk_march;       // nb3 * (Lt / tch): blocks of the marching kernels
     double2 *U;           // links [4][3][3][V] (the caller's array)
-    double2 *U2;          // second link buffer for the fused update (workspace)
+    double2 *U12[2];      // two-row links [4][2][3][V], two buffers (workspace)
+    double2 *g12;         // two-row gauge field [2][3][V] (workspace)
     void *fields;         // packed transform fields [4][V], double2 or float2
     double2 *g;           // gauge field [3][3][V]
     double *partials;     // [nblk_march or nblk_site][4]: (F hi, F lo, theta hi, theta lo)
@@ -77,9 +78,11 @@ struct Cfg {
     int ztP, nzt;         // zt pass: P consecutive xy-sites per tile, nzt tiles per field
 };
 
-// Block-to-configuration maps for every launch shape of a batch.
+// Block-to-configuration maps for every launch shape of a batch: entry e
+// covers configuration idx[e], blocks [off[e], off[e + 1]).
 struct Batch {
     int n;
+    int idx[kMaxCfg];
     int off_site[kMaxCfg + 1];
     int off_march[kMaxCfg + 1];
     int off_fft[4][kMaxCfg + 1];
@@ -119,7 +122,8 @@ hipError_t set_lds_limits();
 hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override);
 hipError_t launch_update(const Launch &L, int respect_done, const double2 *g_override);
 hipError_t launch_update_delta(const Launch &L);
-hipError_t launch_links_home(const Launch &L);
+hipError_t launch_pack_links(const Launch &L);
+hipError_t launch_unpack_links(const Launch &L);
 hipError_t launch_functional_g_impl(const Launch &L, int nblk, const double *omega, double scale, double *out);
 hipError_t launch_functional_g_backward_impl(const Launch &L, int nblk, const double *omega, double scale,
                                              double *d_omega, double2 *d_U);

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_delta(const Cfg *__restrict__ cf
     __shared__ dd red[2 * (kSiteBlock / 64)];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int c = find_cfg(B->off_march, B->n, blk);
-    const Cfg &C = cfgs[c];
+    const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     const int V = C.V, V3 = C.V3;
     const int lb = blk - B->off_march[c];
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_delta(const Cfg *__restrict__ cf
         back3[1] = (y == 0) ? s3 + (Ly - 1) * Lx : s3 - Lx;
         back3[2] = (z == 0) ? s3 + (Lz - 1) * C.V2 : s3 - C.V2;
         const int t0 = tc * C.tch;
-        const double2 *__restrict__ Ub = C.ctrl->cur ? C.U2 : C.U;
+        const double2 *__restrict__ Ub = C.U;
         const double2 *__restrict__ Ut = Ub + (size_t)27 * V;
         double2 prev[9];
         {
@@ -147,11 +147,11 @@ __global__ __launch_bounds__(kSiteBlock) void k_delta(const Cfg *__restrict__ cf
 // One block per configuration: sum the block partials in a fixed order,
 // F = sum/(12 V) (Eq. 1), theta = sum/(3 V) (Eq. 4); with count_iter, count
 // the update, record the history and evaluate the stopping rule theta <= eps.
-__global__ __launch_bounds__(256) void k_reduce(const Cfg *__restrict__ cfgs, int count_iter, int respect_done,
-                                                int flip)
+__global__ __launch_bounds__(256) void k_reduce(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                int count_iter, int respect_done, int flip)
 {
     __shared__ dd red[2 * (256 / 64)];
-    const Cfg &C = cfgs[blockIdx.x];
+    const Cfg &C = cfgs[B->idx[blockIdx.x]];
     Ctrl *ct = C.ctrl;
     if (respect_done && ct->done) return;
     dd f = {0.0, 0.0}, t = {0.0, 0.0};
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(const Cfg *__restrict__ cfg
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int field = blockIdx.y;
     const int c = find_cfg(B->off_fft[axis], B->n, tile);
-    const Cfg &C = cfgs[c];
+    const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     const FftAxis &A = C.ax[axis];
     const int t = tile - B->off_fft[axis][c];
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int field = blockIdx.y;
     const int c = find_cfg(B->off_xy, B->n, tile);
-    const Cfg &C = cfgs[c];
+    const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     const int t = tile - B->off_xy[c];
     const int n = C.xyQ * C.V2;
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int field = blockIdx.y;
     const int c = find_cfg(B->off_zt, B->n, tile);
-    const Cfg &C = cfgs[c];
+    const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     const int t = tile - B->off_zt[c];
     const int P = C.ztP, Lz = C.dims[2], Lt = C.dims[3], V2 = C.V2;
@@ -705,20 +705,32 @@ __device__ __forceinline__ M3 gauge_from_fields(T2 a, T2 b, T2 d, T2 e)
     return m;
 }
 
+// g goes to g_override (caller, full matrices) if given, else to the
+// workspace in two-row form (g12, fused path) or full (g).
+__device__ __forceinline__ void store_gauge(const Cfg &C, double2 *g_override, int two_row, int s, const M3 &m)
+{
+    if (g_override)
+        m3_store(g_override, C.V, s, m);
+    else if (two_row)
+        m3_store12(C.g12, C.V, s, m);
+    else
+        m3_store(C.g, C.V, s, m);
+}
+
 template <typename T2>
 __global__ __launch_bounds__(kSiteBlock) void k_gauge(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
-                                                      int respect_done, double2 *__restrict__ g_override)
+                                                      int respect_done, double2 *__restrict__ g_override, int two_row)
 {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int c = find_cfg(B->off_site, B->n, blk);
-    const Cfg &C = cfgs[c];
+    const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     const int V = C.V;
     const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
     if (s >= V) return;
     const T2 *__restrict__ f = (const T2 *)C.fields;
     const M3 m = gauge_from_fields(f[s], f[(size_t)V + s], f[(size_t)2 * V + s], f[(size_t)3 * V + s]);
-    m3_store(g_override ? g_override : C.g, V, s, m);
+    store_gauge(C, g_override, two_row, s, m);
 }
 
 // Inverse transform over (x, y) of the four fields of Q xy-planes, then g and
@@ -726,13 +738,14 @@ __global__ __launch_bounds__(kSiteBlock) void k_gauge(const Cfg *__restrict__ cf
 // and the gauge step in one pass; the fields are not written back).
 template <typename T2, int CAP, int TH>
 __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
-                                                         int respect_done, double2 *__restrict__ g_override, int tw2)
+                                                         int respect_done, double2 *__restrict__ g_override, int tw2,
+                                                         int two_row)
 {
     constexpr int MS = (CAP + TH - 1) / TH;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int c = find_cfg(B->off_xy, B->n, tile);
-    const Cfg &C = cfgs[c];
+    const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     const int t = tile - B->off_xy[c];
     const int n = C.xyQ * C.V2;
@@ -756,11 +769,12 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
         }
         __syncthreads();
     }
-    double2 *__restrict__ G = g_override ? g_override : C.g;
 #pragma unroll
     for (int k = 0; k < MS; ++k) {
         const int i = threadIdx.x + k * TH;
-        if (i < n) m3_store(G, C.V, (int)(site0 + i), gauge_from_fields(val[0][k], val[1][k], val[2][k], val[3][k]));
+        if (i < n)
+            store_gauge(C, g_override, two_row, (int)(site0 + i),
+                        gauge_from_fields(val[0][k], val[1][k], val[2][k], val[3][k]));
     }
 }
 
@@ -775,7 +789,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_update(const Cfg *__restrict__ c
 {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int c = find_cfg(B->off_march, B->n, blk);
-    const Cfg &C = cfgs[c];
+    const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     const int V = C.V, V3 = C.V3;
     const int lb = blk - B->off_march[c];
@@ -821,8 +835,10 @@ __global__ __launch_bounds__(kSiteBlock) void k_update(const Cfg *__restrict__ c
 // One pass for the link update and the divergence of the updated links:
 //   U'_mu(x) = g(x) U_mu(x) g^dag(x + mu)          (Alg. 1, second loop)
 //   D(x) = sum_nu [U'_nu(x - nu) - U'_nu(x)], Delta = (D - D^dag) - trace/3
-// Old links are read from one buffer and the new ones written to the other,
-// so no block ever reads a link another block has already replaced. The
+// Links and g are held in two-row form (the 12-real parametrisation of the
+// paper's section 2.2; the third row is rebuilt on load). Old links are read
+// from one buffer and the new ones written to the other, so no block ever
+// reads a link another block has already replaced. The
 // backward neighbours U'_nu(x - nu), nu = x, y, z, are recomputed from the old
 // links; U'_t(x - t) is the U'_t(x) of the previous t-slice, kept in registers
 // (recomputed once at the first slice of a block). Also writes the packed
@@ -836,13 +852,13 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restri
     __shared__ dd red[2 * (kSiteBlock / 64)];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int c = find_cfg(B->off_march, B->n, blk);
-    const Cfg &C = cfgs[c];
+    const Cfg &C = cfgs[B->idx[c]];
     const Ctrl *ct = C.ctrl;
     if (ct->done) return;
     const int V = C.V, V3 = C.V3;
-    const double2 *__restrict__ Uo = ct->cur ? C.U2 : C.U;
-    double2 *__restrict__ Un = ct->cur ? C.U : C.U2;
-    const double2 *__restrict__ G = C.g;
+    const double2 *__restrict__ Uo = C.U12[ct->cur];
+    double2 *__restrict__ Un = C.U12[ct->cur ^ 1];
+    const double2 *__restrict__ G = C.g12;
     const bool reunit = C.reunit_every > 0 && ((ct->iter + 1) % (long long)C.reunit_every) == 0;
     if (reunit != RU) return;
     const int lb = blk - B->off_march[c];
@@ -860,11 +876,11 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restri
         back3[1] = (y == 0) ? s3 + (Ly - 1) * Lx : s3 - Lx;
         back3[2] = (z == 0) ? s3 + (Lz - 1) * C.V2 : s3 - C.V2;
         const int t0 = tc * C.tch;
-        M3 gx = m3_load(G, V, s3 + V3 * t0);
+        M3 gx = m3_load12(G, V, s3 + V3 * t0);
         M3 utp;  // U'_t(x, t - 1)
         {
             const int sp = s3 + V3 * ((t0 == 0) ? Lt - 1 : t0 - 1);
-            utp = m3_mul_dag(m3_mul(m3_load(G, V, sp), m3_load(Uo + (size_t)27 * V, V, sp)), gx);
+            utp = m3_mul_dag(m3_mul(m3_load12(G, V, sp), m3_load12(Uo + (size_t)18 * V, V, sp)), gx);
             if (RU) m3_reunit(utp);
         }
         T2 *__restrict__ f = (T2 *)C.fields;
@@ -874,17 +890,17 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restri
             double fsum = 0.0;
 #pragma unroll
             for (int mu = 0; mu < 3; ++mu) {
-                const size_t off = (size_t)mu * 9 * V;
-                M3 w = m3_mul_dag(m3_mul(gx, m3_load(Uo + off, V, s)), m3_load(G, V, fwd3[mu] + V3 * t));
+                const size_t off = (size_t)mu * 6 * V;
+                M3 w = m3_mul_dag(m3_mul(gx, m3_load12(Uo + off, V, s)), m3_load12(G, V, fwd3[mu] + V3 * t));
                 if (RU) m3_reunit(w);
-                m3_store(Un + off, V, s, w);
+                m3_store12(Un + off, V, s, w);
                 fsum += w.e[0].x + w.e[4].x + w.e[8].x;
 #pragma unroll
                 for (int k = 0; k < 9; ++k) D.e[k] = csub(D.e[k], w.e[k]);
                 // keep the phases in order: bounds the loads in flight (registers)
                 __builtin_amdgcn_sched_barrier(0);
                 const int sb = back3[mu] + V3 * t;
-                M3 wb = m3_mul_dag(m3_mul(m3_load(G, V, sb), m3_load(Uo + off, V, sb)), gx);
+                M3 wb = m3_mul_dag(m3_mul(m3_load12(G, V, sb), m3_load12(Uo + off, V, sb)), gx);
                 if (RU) m3_reunit(wb);
 #pragma unroll
                 for (int k = 0; k < 9; ++k) D.e[k] = cadd(D.e[k], wb.e[k]);
@@ -892,11 +908,11 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restri
             }
             {
                 const int tn = (t + 1 == Lt) ? 0 : t + 1;
-                const M3 gn = m3_load(G, V, s3 + V3 * tn);
-                const size_t off = (size_t)27 * V;
-                M3 w = m3_mul_dag(m3_mul(gx, m3_load(Uo + off, V, s)), gn);
+                const M3 gn = m3_load12(G, V, s3 + V3 * tn);
+                const size_t off = (size_t)18 * V;
+                M3 w = m3_mul_dag(m3_mul(gx, m3_load12(Uo + off, V, s)), gn);
                 if (RU) m3_reunit(w);
-                m3_store(Un + off, V, s, w);
+                m3_store12(Un + off, V, s, w);
                 fsum += w.e[0].x + w.e[4].x + w.e[8].x;
 #pragma unroll
                 for (int k = 0; k < 9; ++k) D.e[k] = csub(D.e[k], w.e[k]);
@@ -937,24 +953,40 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restri
     }
 }
 
-// Copy the links of configurations whose current buffer is the workspace
-// copy back to the caller's array, and mark the caller's array current.
-__global__ __launch_bounds__(kSiteBlock) void k_links_home(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B)
+// Caller's links -> two-row buffer 0 (start of a call).
+__global__ __launch_bounds__(kSiteBlock) void k_pack_links(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B)
 {
     const int blk = blockIdx.x;
     const int c = find_cfg(B->off_site, B->n, blk);
-    const Cfg &C = cfgs[c];
-    if (!C.ctrl->cur) return;
+    const Cfg &C = cfgs[B->idx[c]];
     const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
     if (s >= C.V) return;
 #pragma unroll
-    for (int k = 0; k < 36; ++k) C.U[(size_t)k * C.V + s] = C.U2[(size_t)k * C.V + s];
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) C.U12[0][(size_t)(mu * 6 + k) * C.V + s] = C.U[(size_t)(mu * 9 + k) * C.V + s];
 }
 
-__global__ void k_links_home_flag(const Cfg *__restrict__ cfgs, int ncfg)
+// Current two-row buffer -> caller's links, third rows rebuilt (end of a call).
+__global__ __launch_bounds__(kSiteBlock) void k_unpack_links(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B)
+{
+    const int blk = blockIdx.x;
+    const int c = find_cfg(B->off_site, B->n, blk);
+    const Cfg &C = cfgs[B->idx[c]];
+    const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
+    if (s >= C.V) return;
+    const double2 *__restrict__ src = C.U12[C.ctrl->cur];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const M3 m = m3_load12(src + (size_t)mu * 6 * C.V, C.V, s);
+        m3_store(C.U + (size_t)mu * 9 * C.V, C.V, s, m);
+    }
+}
+
+__global__ void k_set_cur(const Cfg *__restrict__ cfgs, int ncfg, int v)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < ncfg) cfgs[c].ctrl->cur = 0;
+    if (c < ncfg) cfgs[c].ctrl->cur = v;
 }
 
 // ============================================================ differentiable functional
@@ -1199,7 +1231,7 @@ hipError_t launch_delta(const Launch &L, int respect_done, double2 *full_delta)
 
 hipError_t launch_reduce(const Launch &L, int ncfg, int count_iter, int respect_done)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(ncfg), dim3(256), 0, L.stream, L.cfgs, count_iter, respect_done,
+    hipLaunchKernelGGL(k_reduce, dim3(ncfg), dim3(256), 0, L.stream, L.cfgs, L.batch, count_iter, respect_done,
                        count_iter ? L.fused : 0);
     return hipGetLastError();
 }
@@ -1267,7 +1299,7 @@ static hipError_t run_xyg(const Launch &L, int cap, int rd, double2 *go)
 #define X(C_, T_)                                                                                                 \
     if (cap == C_) {                                                                                              \
         hipLaunchKernelGGL((k_fft_xy_inv_gauge<T2, C_, T_>), dim3(L.total_xy_tiles), dim3(T_), sh, L.stream, L.cfgs, \
-                           L.batch, rd, go, L.xy_tw2);                                                            \
+                           L.batch, rd, go, L.xy_tw2, L.fused);                                                   \
         return hipGetLastError();                                                                                 \
     }
     GF_2D_VARIANTS(X)
@@ -1331,10 +1363,10 @@ hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override)
 {
     if (L.fp32)
         hipLaunchKernelGGL(k_gauge<float2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
-                           L.batch, respect_done, g_override);
+                           L.batch, respect_done, g_override, L.fused);
     else
         hipLaunchKernelGGL(k_gauge<double2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
-                           L.batch, respect_done, g_override);
+                           L.batch, respect_done, g_override, L.fused);
     return hipGetLastError();
 }
 
@@ -1352,10 +1384,16 @@ hipError_t launch_update_delta(const Launch &L)
     return hipGetLastError();
 }
 
-hipError_t launch_links_home(const Launch &L)
+hipError_t launch_pack_links(const Launch &L)
 {
-    hipLaunchKernelGGL(k_links_home, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs, L.batch);
-    hipLaunchKernelGGL(k_links_home_flag, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.ncfg);
+    hipLaunchKernelGGL(k_set_cur, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.ncfg, 0);
+    hipLaunchKernelGGL(k_pack_links, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs, L.batch);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_links(const Launch &L)
+{
+    hipLaunchKernelGGL(k_unpack_links, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs, L.batch);
     return hipGetLastError();
 }
 

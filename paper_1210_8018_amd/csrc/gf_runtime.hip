@@ -133,7 +133,7 @@ FftAxis plan_axis(const int dims[4], int mu)
 }
 
 struct Layout {
-    size_t fields, g, partials, sin2, tw, links2, total;
+    size_t fields, g, partials, sin2, tw, links12a, links12b, g12, total;
 };
 
 Layout layout_for(const gf_params &p, size_t start)
@@ -157,14 +157,22 @@ Layout layout_for(const gf_params &p, size_t start)
     o = align_up(o + sumL * sizeof(double));
     l.tw = o;
     o = align_up(o + sumL * csz);
-    l.links2 = o;  // second link buffer of the fused update + divergence pass
-    o = align_up(o + 36 * V * 16);
+    // two-row (12-real) links, two buffers, and two-row g of the fused pass
+    l.links12a = o;
+    o = align_up(o + 24 * V * 16);
+    l.links12b = o;
+    o = align_up(o + 24 * V * 16);
+    l.g12 = o;
+    o = align_up(o + 6 * V * 16);
     l.total = o;
     return l;
 }
 
 // Header of the workspace: configuration table, batch map, scalar outputs.
-size_t header_bytes(int ncfg) { return align_up(ncfg * sizeof(Cfg)) + align_up(sizeof(Batch)) + align_up(64); }
+size_t header_bytes(int ncfg)
+{
+    return align_up(ncfg * sizeof(Cfg)) + 2 * align_up(sizeof(Batch)) + align_up(64);
+}
 
 struct KTime {
     std::string name;
@@ -186,7 +194,11 @@ struct gf_ctx_s {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     Cfg *d_cfgs = nullptr;
-    Batch *d_batch = nullptr;
+    Batch *d_batch = nullptr;      // map over every configuration
+    Batch *d_batch_act = nullptr;  // map over the configurations still iterating
+    Batch bact{};
+    Launch Lact{};                 // launch shapes of the active map
+    std::vector<int> active;
     double *d_scalar = nullptr;
     Ctrl *h_ctrl = nullptr;  // pinned mirror, ncfg entries
     std::vector<std::vector<double>> histF, histT;
@@ -272,7 +284,7 @@ gf_status collect_timing(gf_ctx c)
 // g_override: write g there instead of the workspace).
 hipError_t enqueue_gauge_steps(gf_ctx c, hipStream_t s, int respect_done, double2 *g_override)
 {
-    Launch L = c->L;
+    Launch L = respect_done ? c->Lact : c->L;
     L.stream = s;
     hipError_t e;
     const int nf = kFields, rd = respect_done;
@@ -309,7 +321,7 @@ hipError_t enqueue_gauge_steps(gf_ctx c, hipStream_t s, int respect_done, double
 // re-measurement. Every kernel returns at once for configurations that are done.
 hipError_t enqueue_iteration(gf_ctx c, hipStream_t s)
 {
-    Launch L = c->L;
+    Launch L = c->Lact;
     L.stream = s;
     hipError_t e = enqueue_gauge_steps(c, s, 1, nullptr);
     if (e != hipSuccess) return e;
@@ -319,7 +331,7 @@ hipError_t enqueue_iteration(gf_ctx c, hipStream_t s)
         GF_TRY(K_UPDATE, launch_update(L, 1, nullptr));
         GF_TRY(K_DELTA, launch_delta(L, 1, nullptr));
     }
-    GF_TRY(K_REDUCE, launch_reduce(L, c->ncfg, 1, 1));
+    GF_TRY(K_REDUCE, launch_reduce(L, L.ncfg, 1, 1));
 #undef GF_TRY
     return hipSuccess;
 }
@@ -374,15 +386,21 @@ gf_status read_ctrl(gf_ctx c)
 }
 
 gf_status run_chunks(gf_ctx c);
+gf_status reset_active(gf_ctx c);
+gf_status compact_active(gf_ctx c);
 
-// Run graph chunks until every configuration is done, then bring the links
-// back to the caller's array where the last update left them in the copy.
+// Run graph chunks until every configuration is done. On the fused path the
+// iterations work on two-row copies of the links in the workspace: packed from
+// the caller's array first, written back (third rows rebuilt) at the end.
 gf_status run_until_done(gf_ctx c)
 {
-    gf_status st = run_chunks(c);
+    gf_status st = reset_active(c);
+    if (st != GF_OK) return st;
+    if (c->L.fused) HIPCHK(c, launch_pack_links(c->L));
+    st = run_chunks(c);
     if (st != GF_OK) return st;
     if (c->L.fused) {
-        HIPCHK(c, launch_links_home(c->L));
+        HIPCHK(c, launch_unpack_links(c->L));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return GF_OK;
@@ -402,6 +420,7 @@ gf_status run_chunks(gf_ctx c)
             bool all = true;
             for (int k = 0; k < c->ncfg; ++k) all = all && c->h_ctrl[k].done != kRunning;
             if (all) return GF_OK;
+            if (c->batch && (st = compact_active(c)) != GF_OK) return st;
         }
     }
     gf_status st = build_graph(c);
@@ -413,6 +432,10 @@ gf_status run_chunks(gf_ctx c)
         bool all = true;
         for (int k = 0; k < c->ncfg; ++k) all = all && c->h_ctrl[k].done != kRunning;
         if (all) return GF_OK;
+        if (c->batch) {
+            if ((st = compact_active(c)) != GF_OK) return st;
+            if ((st = build_graph(c)) != GF_OK) return st;
+        }
     }
 }
 
@@ -448,20 +471,54 @@ void fill_tables(const gf_params &p, std::vector<double> &sin2, std::vector<char
 
 // Tile shapes of the 2D passes for every configuration, and the launch
 // totals; uploads the configuration table.
+// Tile maps and launch totals over a list of configurations.
+void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
+{
+    memset(&b, 0, sizeof(b));
+    b.n = (int)list.size();
+    for (int e = 0; e < b.n; ++e) {
+        const Cfg &C = c->cfg[list[e]];
+        b.idx[e] = list[e];
+        b.off_site[e + 1] = b.off_site[e] + C.nblk_site;
+        b.off_march[e + 1] = b.off_march[e] + C.nblk_march;
+        for (int mu = 0; mu < 4; ++mu) b.off_fft[mu][e + 1] = b.off_fft[mu][e] + C.ax[mu].ntile;
+        b.off_xy[e + 1] = b.off_xy[e] + C.nxy;
+        b.off_zt[e + 1] = b.off_zt[e] + C.nzt;
+    }
+    L.total_site_blocks = b.off_site[b.n];
+    L.total_march_blocks = b.off_march[b.n];
+    for (int mu = 0; mu < 4; ++mu) L.total_fft_tiles[mu] = b.off_fft[mu][b.n];
+    L.total_xy_tiles = b.off_xy[b.n];
+    L.total_zt_tiles = b.off_zt[b.n];
+    L.ncfg = b.n;
+}
+
+void drop_graph(gf_ctx c)
+{
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+}
+
+// Tile shapes of the 2D passes for every configuration, the full map and the
+// launch totals; uploads the configuration table.
 gf_status apply_schedule(gf_ctx c, int sched, int xy_target)
 {
-    Batch &b = c->bmap;
     for (int k = 0; k < c->ncfg; ++k) {
         Cfg &C = c->cfg[k];
         C.xyQ = xy_feasible(C.dims) ? plan_xyQ(C.dims, xy_target) : 1;
         C.nxy = xy_feasible(C.dims) ? (C.dims[2] * C.dims[3]) / C.xyQ : 0;
         C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims) : 1;
         C.nzt = zt_feasible(C.dims) ? C.V2 / C.ztP : 0;
-        b.off_xy[k + 1] = b.off_xy[k] + C.nxy;
-        b.off_zt[k + 1] = b.off_zt[k] + C.nzt;
     }
-    c->L.total_xy_tiles = b.off_xy[c->ncfg];
-    c->L.total_zt_tiles = b.off_zt[c->ncfg];
+    std::vector<int> all(c->ncfg);
+    for (int k = 0; k < c->ncfg; ++k) all[k] = k;
+    fill_map(c, all, c->bmap, c->L);
     int xy_max = 0, zt_max = 0, mx = 0, my = 0, mz = 0, mt = 0;
     for (int k = 0; k < c->ncfg; ++k) {
         const Cfg &C = c->cfg[k];
@@ -481,17 +538,44 @@ gf_status apply_schedule(gf_ctx c, int sched, int xy_target)
     c->L.zt_tw_total = mz + mt;
     c->sched = sched;
     c->xy_target = xy_target;
+    // the active map starts as the full one
+    c->bact = c->bmap;
+    c->Lact = c->L;
+    c->Lact.batch = c->d_batch_act;
+    c->active = all;
     HIPCHK(c, hipMemcpyAsync(c->d_cfgs, c->cfg.data(), sizeof(Cfg) * c->ncfg, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_batch, &c->bmap, sizeof(Batch), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_batch_act, &c->bact, sizeof(Batch), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (c->gexec) {
-        (void)hipGraphExecDestroy(c->gexec);
-        c->gexec = nullptr;
-    }
-    if (c->graph) {
-        (void)hipGraphDestroy(c->graph);
-        c->graph = nullptr;
-    }
+    drop_graph(c);
+    return GF_OK;
+}
+
+// Batch contexts: after a chunk, launch only the configurations still
+// iterating (finished ones would only cost empty blocks).
+gf_status compact_active(gf_ctx c)
+{
+    std::vector<int> act;
+    for (int k = 0; k < c->ncfg; ++k)
+        if (c->h_ctrl[k].done == kRunning) act.push_back(k);
+    if (act.empty() || act == c->active) return GF_OK;
+    fill_map(c, act, c->bact, c->Lact);
+    c->active = act;
+    HIPCHK(c, hipMemcpyAsync(c->d_batch_act, &c->bact, sizeof(Batch), hipMemcpyHostToDevice, c->stream));
+    drop_graph(c);
+    return GF_OK;
+}
+
+// Reset the active map to every configuration (at the start of a call).
+gf_status reset_active(gf_ctx c)
+{
+    if ((int)c->active.size() == c->ncfg) return GF_OK;
+    std::vector<int> all(c->ncfg);
+    for (int k = 0; k < c->ncfg; ++k) all[k] = k;
+    fill_map(c, all, c->bact, c->Lact);
+    c->active = all;
+    HIPCHK(c, hipMemcpyAsync(c->d_batch_act, &c->bact, sizeof(Batch), hipMemcpyHostToDevice, c->stream));
+    drop_graph(c);
     return GF_OK;
 }
 
@@ -617,6 +701,8 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
     o += align_up(ncfg * sizeof(Cfg));
     c->d_batch = (Batch *)(c->ws + o);
     o += align_up(sizeof(Batch));
+    c->d_batch_act = (Batch *)(c->ws + o);
+    o += align_up(sizeof(Batch));
     c->d_scalar = (double *)(c->ws + o);
     o += align_up(64);
 
@@ -645,7 +731,9 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         C.tch = plan_tchunk(p.dims);
         C.nblk_march = C.nb3 * (p.dims[3] / C.tch);
         C.U = (double2 *)links[k];
-        C.U2 = (double2 *)(c->ws + l.links2);
+        C.U12[0] = (double2 *)(c->ws + l.links12a);
+        C.U12[1] = (double2 *)(c->ws + l.links12b);
+        C.g12 = (double2 *)(c->ws + l.g12);
         C.fields = c->ws + l.fields;
         C.g = (double2 *)(c->ws + l.g);
         C.partials = (double *)(c->ws + l.partials);
@@ -667,9 +755,6 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
             const int e = C.ax[mu].P * C.ax[mu].L;
             if (e > max_lds) max_lds = e;
         }
-        b.off_site[k + 1] = b.off_site[k] + C.nblk_site;
-        b.off_march[k + 1] = b.off_march[k] + C.nblk_march;
-        for (int mu = 0; mu < 4; ++mu) b.off_fft[mu][k + 1] = b.off_fft[mu][k] + C.ax[mu].ntile;
         o = l.total;
     }
     if (o > ws_bytes) {
@@ -678,9 +763,11 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
     }
     c->L.cfgs = c->d_cfgs;
     c->L.batch = c->d_batch;
-    c->L.total_site_blocks = b.off_site[ncfg];
-    c->L.total_march_blocks = b.off_march[ncfg];
-    for (int mu = 0; mu < 4; ++mu) c->L.total_fft_tiles[mu] = b.off_fft[mu][ncfg];
+    {
+        std::vector<int> all(ncfg);
+        for (int k = 0; k < ncfg; ++k) all[k] = k;
+        fill_map(c, all, c->bmap, c->L);
+    }
     c->L.max_lds_elems = max_lds;
     c->L.fp32 = params[0].fft_prec;
     c->L.fused = getenv("GF_NOFUSE") ? 0 : 1;
@@ -691,6 +778,7 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
 
     HIPCHK(c, hipMemcpyAsync(c->d_cfgs, c->cfg.data(), sizeof(Cfg) * ncfg, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_batch, &c->bmap, sizeof(Batch), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_batch_act, &c->bmap, sizeof(Batch), hipMemcpyHostToDevice, c->stream));
     for (int k = 0; k < ncfg; ++k) {
         HIPCHK(c, hipMemcpyAsync((void *)c->cfg[k].sin2, sin2s[k].data(), sin2s[k].size() * sizeof(double),
                                  hipMemcpyHostToDevice, c->stream));

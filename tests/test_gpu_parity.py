@@ -145,6 +145,21 @@ def test_trajectory_matches_oracle(dims, eps, seed, sched):
     assert np.all(np.diff(Fh) >= -4 * np.spacing(np.abs(Fh[:-1])))
 
 
+def test_unfused_full_storage_path_matches_oracle(monkeypatch):
+    """The separate update and divergence kernels on full 18-real links (GF_NOFUSE)."""
+    monkeypatch.setenv("GF_NOFUSE", "1")
+    dims = (8, 8, 8, 8)
+    U = random_links(dims, 0.3, 1)
+    n_ref, _, Fr, Tr = oracle.fix(dims, U, alpha=ALPHA, eps=EPS, max_iter=5000)
+    Ud = dev(U)
+    fx = GaugeFixer(Ud)
+    it, F, th = fx.fix_until(EPS, 5000)
+    Fh, Th = fx.history()
+    assert it == n_ref
+    compare_trajectory(Fh, Th, Fr, Tr, int(np.prod(dims)))
+    assert abs(oracle.plaquette(dims, host(Ud)) - oracle.plaquette(dims, U)) < 1e-13
+
+
 def test_step_equals_fix_prefix():
     dims = (8, 8, 8, 8)
     U = random_links(dims, 0.3, 1)
