@@ -38,6 +38,8 @@ struct Ctrl {
     long long max_iter;  // absolute cap on iter
     int done;            // kRunning / kConverged / kMaxIter / kNonFinite
     int cur;             // current two-row link buffer, U12[cur]
+    int ru_now;          // this iteration also projects the new links (set before the fused pass)
+    int pad2;
     double hist[kHist][2];  // (F, theta) after update k at slot k % kHist
 };
 
@@ -76,6 +78,8 @@ struct Cfg {
     FftAxis ax[4];
     int xyQ, nxy;         // xy pass: Q consecutive xy-planes per tile, nxy tiles per field
     int ztP, nzt;         // zt pass: P consecutive xy-sites per tile, nzt tiles per field
+    int xyPad;            // LDS elements added to every x-row of an xy tile (bank spreading)
+    int ztPad;            // LDS elements added to every t-plane of a zt tile
 };
 
 // Block-to-configuration maps for every launch shape of a batch: entry e

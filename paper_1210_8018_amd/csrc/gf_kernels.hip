@@ -147,15 +147,15 @@ __global__ __launch_bounds__(kSiteBlock) void k_delta(const Cfg *__restrict__ cf
 // One block per configuration: sum the block partials in a fixed order,
 // F = sum/(12 V) (Eq. 1), theta = sum/(3 V) (Eq. 4); with count_iter, count
 // the update, record the history and evaluate the stopping rule theta <= eps.
-__global__ __launch_bounds__(256) void k_reduce(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
-                                                int count_iter, int respect_done, int flip)
+// Sum the block partials of one configuration in a fixed order (the whole
+// block takes part), F = sum/(12 V) (Eq. 1), theta = sum/(3 V) (Eq. 4); with
+// count_iter, count the update, record the history, flip the link buffer if
+// asked and evaluate the stopping rule theta <= eps.
+__device__ void finalize_config(const Cfg &C, int nparts, int count_iter, int flip, dd *red)
 {
-    __shared__ dd red[2 * (256 / 64)];
-    const Cfg &C = cfgs[B->idx[blockIdx.x]];
     Ctrl *ct = C.ctrl;
-    if (respect_done && ct->done) return;
     dd f = {0.0, 0.0}, t = {0.0, 0.0};
-    for (int i = threadIdx.x; i < C.nblk_march; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
         const double *p = C.partials + (size_t)i * 4;
         f = dd_add(f, dd{p[0], p[1]});
         t = dd_add(t, dd{p[2], p[3]});
@@ -185,6 +185,17 @@ __global__ __launch_bounds__(256) void k_reduce(const Cfg *__restrict__ cfgs, co
             ct->done = d;
         }
     }
+}
+
+// One block per configuration entry: finalize_config over the partials of
+// the divergence kernel.
+__global__ __launch_bounds__(256) void k_reduce(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                int count_iter, int respect_done, int flip)
+{
+    __shared__ dd red[2 * (256 / 64)];
+    const Cfg &C = cfgs[B->idx[blockIdx.x]];
+    if (respect_done && C.ctrl->done) return;
+    finalize_config(C, C.nblk_march, count_iter, flip, red);
 }
 
 // ============================================================ transform tiles
@@ -397,6 +408,28 @@ __device__ __forceinline__ void tile_load_contig(T2 *buf, const T2 *__restrict__
 }
 
 template <typename T2, int CAP, int TH>
+__device__ __forceinline__ void tile_load_padded(T2 *buf, const T2 *__restrict__ g, int n, int rowlen, int pad)
+{
+    constexpr int NL = (CAP + TH - 1) / TH;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * TH;
+        if (i < n) buf[i + pad * (i / rowlen)] = g[i];
+    }
+}
+
+template <typename T2, int CAP, int TH>
+__device__ __forceinline__ void tile_store_padded(T2 *__restrict__ g, const T2 *buf, int n, int rowlen, int pad)
+{
+    constexpr int NL = (CAP + TH - 1) / TH;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * TH;
+        if (i < n) g[i] = buf[i + pad * (i / rowlen)];
+    }
+}
+
+template <typename T2, int CAP, int TH>
 __device__ __forceinline__ void tile_store_contig(T2 *__restrict__ g, const T2 *buf, int n)
 {
     constexpr int NL = (CAP + TH - 1) / TH;
@@ -418,6 +451,34 @@ __device__ __forceinline__ void tile_load_rows(T2 *buf, const T2 *__restrict__ g
     for (int k = 0; k < NL; ++k) {
         const int r = r0 + k * dr;
         if (r < rows) buf[r * P + p] = g[(size_t)r * rs + p];
+    }
+}
+
+// As tile_load_rows / tile_store_rows, with `pad` LDS elements after every
+// `rpp` rows (row r at LDS r * P + pad * (r / rpp)).
+template <typename T2, int CAP, int TH>
+__device__ __forceinline__ void tile_load_rows_padded(T2 *buf, const T2 *__restrict__ g, int P, int rows, size_t rs,
+                                                      int rpp, int pad)
+{
+    constexpr int NL = (CAP + TH - 1) / TH;
+    const int p = threadIdx.x % P, r0 = threadIdx.x / P, dr = TH / P;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int r = r0 + k * dr;
+        if (r < rows) buf[r * P + p + pad * (r / rpp)] = g[(size_t)r * rs + p];
+    }
+}
+
+template <typename T2, int CAP, int TH>
+__device__ __forceinline__ void tile_store_rows_padded(T2 *__restrict__ g, const T2 *buf, int P, int rows, size_t rs,
+                                                       int rpp, int pad)
+{
+    constexpr int NL = (CAP + TH - 1) / TH;
+    const int p = threadIdx.x % P, r0 = threadIdx.x / P, dr = TH / P;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int r = r0 + k * dr;
+        if (r < rows) g[(size_t)r * rs + p] = buf[r * P + p + pad * (r / rpp)];
     }
 }
 
@@ -589,15 +650,21 @@ __device__ __forceinline__ void load_twiddles(T2 *dst, const Cfg &C, int axis)
 }
 
 // 2D transform over (x, y) of Q consecutive xy-planes of one field, in LDS.
+// Element (x, y, q) sits at x + Xp (y + Ly q), Xp = Lx + xyPad: the padding
+// keeps neighbouring lanes, which work on neighbouring pencils, off the same
+// LDS banks in both directions.
 template <typename T2, int CAP, int TH>
 __device__ __forceinline__ void xy_transform(T2 *buf, const T2 *twx, const T2 *twy, const Cfg &C, int Q, int sign)
 {
-    const int Lx = C.dims[0], Ly = C.dims[1];
-    // x: pencils k = (y, q), start k * Lx, unit stride
-    fft_axis_ip<T2, CAP, TH>(buf, twx, C.ax[0], Ly * Q, Ly * Q, Lx, 0, 1, sign, false);
-    // y: pencils k = (x, q), start x + V2 q, stride Lx
-    fft_axis_ip<T2, CAP, TH>(buf, twy, C.ax[1], Lx * Q, Lx, 1, C.V2, Lx, sign, true);
+    const int Lx = C.dims[0], Ly = C.dims[1], Xp = Lx + C.xyPad;
+    // x: pencils k = (y, q), start k * Xp, unit stride
+    fft_axis_ip<T2, CAP, TH>(buf, twx, C.ax[0], Ly * Q, Ly * Q, Xp, 0, 1, sign, true);
+    // y: pencils k = (x, q), start x + Xp Ly q, stride Xp
+    fft_axis_ip<T2, CAP, TH>(buf, twy, C.ax[1], Lx * Q, Lx, 1, Xp * Ly, Xp, sign, true);
 }
+
+// LDS index of element i of an xy tile in global (unpadded) order.
+__device__ __forceinline__ int xy_lds(const Cfg &C, int i) { return i + C.xyPad * (i / C.dims[0]); }
 
 // Pass over (x, y): tile = Q consecutive xy-planes of one field. LDS: CAP
 // data elements, then the twiddles of x (tw2 entries reserved) and y.
@@ -614,15 +681,15 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int t = tile - B->off_xy[c];
     const int n = C.xyQ * C.V2;
     T2 *buf = (T2 *)smem;
-    T2 *twx = buf + CAP;
+    T2 *twx = buf + CAP + CAP / 8;
     T2 *twy = twx + tw2;
     load_twiddles(twx, C, 0);
     load_twiddles(twy, C, 1);
     T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)field * C.V + (size_t)t * n;
-    tile_load_contig<T2, CAP, TH>(buf, g, n);
+    tile_load_padded<T2, CAP, TH>(buf, g, n, C.dims[0], C.xyPad);
     __syncthreads();
     xy_transform<T2, CAP, TH>(buf, twx, twy, C, C.xyQ, sign);
-    tile_store_contig<T2, CAP, TH>(g, buf, n);
+    tile_store_padded<T2, CAP, TH>(g, buf, n, C.dims[0], C.xyPad);
 }
 
 // Pass over (z, t): tile = P consecutive xy-sites times the whole (z, t) plane
@@ -645,18 +712,20 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int n = P * Lz * Lt;
     const int i0 = t * P;
     T2 *buf = (T2 *)smem;
-    T2 *twz = buf + CAP;
+    T2 *twz = buf + CAP + CAP / 8;
     T2 *twt = twz + tw2;
     load_twiddles(twz, C, 2);
     load_twiddles(twt, C, 3);
     T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)field * C.V + i0;
-    tile_load_rows<T2, CAP, TH>(buf, g, P, Lz * Lt, V2);
+    // LDS layout [t][z][p] with t-planes Tp = P Lz + ztPad elements apart
+    const int Tp = P * Lz + C.ztPad;
+    tile_load_rows_padded<T2, CAP, TH>(buf, g, P, Lz * Lt, V2, Lz, C.ztPad);
     __syncthreads();
     const int s0 = (mode == 1) ? -1 : sign;
-    // z: pencils k = (p, t), start p + P Lz t, stride P
-    fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, P * Lz, P, s0, true);
-    // t: pencils k = (p, z), start k, stride P Lz
-    fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, P * Lz, s0, true);
+    // z: pencils k = (p, t), start p + Tp t, stride P
+    fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, s0, true);
+    // t: pencils k = (p, z), start k, stride Tp
+    fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, s0, true);
     if (mode == 1) {
         const double *s2 = C.sin2;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -667,16 +736,17 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
             const double p2 = s2[C.sin2_off[0] + nx] + s2[C.sin2_off[1] + ny] + s2[C.sin2_off[2] + nz] +
                               s2[C.sin2_off[3] + nt];
             const T k_t = (T)((p2 > 0.0) ? C.kfac / p2 : 0.0);
-            T2 v = buf[i];
+            const int li = p + P * nz + Tp * nt;
+            T2 v = buf[li];
             v.x *= k_t;
             v.y *= k_t;
-            buf[i] = v;
+            buf[li] = v;
         }
         __syncthreads();
-        fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, P * Lz, +1, true);
-        fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, P * Lz, P, +1, true);
+        fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, +1, true);
+        fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, +1, true);
     }
-    tile_store_rows<T2, CAP, TH>(g, buf, P, Lz * Lt, V2);
+    tile_store_rows_padded<T2, CAP, TH>(g, buf, P, Lz * Lt, V2, Lz, C.ztPad);
 }
 
 // ============================================================ S4: g = 1 + Delta~, projected
@@ -751,7 +821,7 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
     const int n = C.xyQ * C.V2;
     const size_t site0 = (size_t)t * n;
     T2 *buf = (T2 *)smem;
-    T2 *twx = buf + CAP;
+    T2 *twx = buf + CAP + CAP / 8;
     T2 *twy = twx + tw2;
     load_twiddles(twx, C, 0);
     load_twiddles(twy, C, 1);
@@ -759,13 +829,13 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
 #pragma unroll
     for (int f = 0; f < kFields; ++f) {
         const T2 *__restrict__ src = (const T2 *)C.fields + (size_t)f * C.V + site0;
-        tile_load_contig<T2, CAP, TH>(buf, src, n);
+        tile_load_padded<T2, CAP, TH>(buf, src, n, C.dims[0], C.xyPad);
         __syncthreads();
         xy_transform<T2, CAP, TH>(buf, twx, twy, C, C.xyQ, +1);
 #pragma unroll
         for (int k = 0; k < MS; ++k) {
             const int i = threadIdx.x + k * TH;
-            if (i < n) val[f][k] = buf[i];
+            if (i < n) val[f][k] = buf[xy_lds(C, i)];
         }
         __syncthreads();
     }
@@ -859,7 +929,9 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restri
     const double2 *__restrict__ Uo = C.U12[ct->cur];
     double2 *__restrict__ Un = C.U12[ct->cur ^ 1];
     const double2 *__restrict__ G = C.g12;
-    const bool reunit = C.reunit_every > 0 && ((ct->iter + 1) % (long long)C.reunit_every) == 0;
+    // decided before this iteration's fused launches, so that the two
+    // variants agree whatever runs in between
+    const bool reunit = C.reunit_every > 0 && ct->ru_now;
     if (reunit != RU) return;
     const int lb = blk - B->off_march[c];
     const int b3 = lb % C.nb3, tc = lb / C.nb3;
@@ -981,6 +1053,16 @@ __global__ __launch_bounds__(kSiteBlock) void k_unpack_links(const Cfg *__restri
         const M3 m = m3_load12(src + (size_t)mu * 6 * C.V, C.V, s);
         m3_store(C.U + (size_t)mu * 9 * C.V, C.V, s, m);
     }
+}
+
+// Whether the coming iteration of each running configuration projects its links.
+__global__ void k_mark_reunit(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B->n) return;
+    const Cfg &C = cfgs[B->idx[e]];
+    Ctrl *ct = C.ctrl;
+    ct->ru_now = C.reunit_every > 0 && ((ct->iter + 1) % (long long)C.reunit_every) == 0;
 }
 
 __global__ void k_set_cur(const Cfg *__restrict__ cfgs, int ncfg, int v)
@@ -1255,11 +1337,12 @@ hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *
 // 2D pass variants by tile capacity: (elements, work-items).
 #define GF_2D_VARIANTS(X) X(1024, 256) X(2048, 256) X(4096, 512)
 
+// LDS of a 2D tile: CAP elements plus CAP/8 for row padding, then twiddles.
 template <typename T2>
 static size_t lds2d(int cap, int tw2, int tw_total)
 {
     (void)tw2;
-    return (size_t)(cap + tw_total) * sizeof(T2);
+    return (size_t)(cap + cap / 8 + tw_total) * sizeof(T2);
 }
 
 template <typename T2>
@@ -1373,6 +1456,7 @@ hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override)
 hipError_t launch_update_delta(const Launch &L)
 {
     const dim3 grid(L.total_march_blocks), blk(kSiteBlock);
+    if (L.any_reunit) hipLaunchKernelGGL(k_mark_reunit, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.batch);
     if (L.fp32) {
         hipLaunchKernelGGL((k_update_delta<float2, false>), grid, blk, 0, L.stream, L.cfgs, L.batch);
         if (L.any_reunit) hipLaunchKernelGGL((k_update_delta<float2, true>), grid, blk, 0, L.stream, L.cfgs, L.batch);

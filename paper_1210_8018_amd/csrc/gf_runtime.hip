@@ -77,7 +77,7 @@ int plan_tchunk(const int dims[4])
         const int t = atoi(env);
         if (t >= 1 && dims[3] % t == 0) return t;
     }
-    const int target = 1024;  // blocks wanted for 256 CUs
+    const int target = 512;  // blocks wanted: two per CU
     for (int nT = 1; nT <= dims[3]; ++nT)
         if (dims[3] % nT == 0 && nb3 * nT >= target) return dims[3] / nT;
     return 1;
@@ -515,6 +515,13 @@ gf_status apply_schedule(gf_ctx c, int sched, int xy_target)
         C.nxy = xy_feasible(C.dims) ? (C.dims[2] * C.dims[3]) / C.xyQ : 0;
         C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims) : 1;
         C.nzt = zt_feasible(C.dims) ? C.V2 / C.ztP : 0;
+        // bank-spreading pads, kept inside the 1/8 slack of the LDS tile
+        const char *np = getenv("GF_NO_LDS_PAD");
+        const int xycap = C.xyQ * C.V2 <= 1024 ? 1024 : (C.xyQ * C.V2 <= 2048 ? 2048 : 4096);
+        C.xyPad = (!np && C.dims[1] * C.xyQ <= xycap / 8) ? 1 : 0;
+        const int ztn = C.ztP * C.dims[2] * C.dims[3];
+        const int ztcap = ztn <= 1024 ? 1024 : (ztn <= 2048 ? 2048 : 4096);
+        C.ztPad = (!np && 4 * C.dims[3] <= ztcap / 8) ? 4 : 0;
     }
     std::vector<int> all(c->ncfg);
     for (int k = 0; k < c->ncfg; ++k) all[k] = k;
