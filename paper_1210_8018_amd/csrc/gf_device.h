@@ -238,6 +238,10 @@ __device__ __forceinline__ void block_sum2(dd &a, dd &b, dd *lds)
     }
 }
 
+// ---------------------------------------------------------------- integers
+__device__ __forceinline__ bool is_p2(int v) { return (v & (v - 1)) == 0; }
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+
 // ---------------------------------------------------------------- mapping
 // Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8).
 // Renumber them so each XCD walks a contiguous range of tiles: neighbouring
@@ -255,6 +259,31 @@ __device__ __forceinline__ int find_cfg(const int *off, int n, int blk)
     int c = 0;
     while (c + 1 < n && blk >= off[c + 1]) ++c;
     return c;
+}
+
+// (x, y, z) of work-item `tid` of block `b3` of the marching kernels, and
+// whether it is inside the volume. Linear mode: kSiteBlock consecutive sites
+// of the (x, y, z) volume; tile mode: a tile[0] x tile[1] x tile[2] box.
+__device__ __forceinline__ bool march_xyz(const Cfg &C, int b3, int tid, int &x, int &y, int &z)
+{
+    const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2];
+    if (C.tile[0] == 0) {
+        const int s3 = b3 * kSiteBlock + tid;
+        x = s3 % Lx;
+        const int r = s3 / Lx;
+        y = r % Ly;
+        z = r / Ly;
+        return s3 < C.V3;
+    }
+    const int tx = C.tile[0], ty = C.tile[1];
+    const int bx = b3 % C.ntile[0], rb = b3 / C.ntile[0];
+    const int by = rb % C.ntile[1], bz = rb / C.ntile[1];
+    const int ix = tid % tx, rt = tid / tx;
+    const int iy = rt % ty, iz = rt / ty;
+    x = bx * tx + ix;
+    y = by * ty + iy;
+    z = bz * C.tile[2] + iz;
+    return iz < C.tile[2] && x < Lx && y < Ly && z < Lz;
 }
 
 struct Site {

@@ -59,7 +59,9 @@ struct Cfg {
     int V2;               // Lx * Ly
     int V3;               // Lx * Ly * Lz
     int nblk_site;        // site blocks of kSiteBlock
-    int nb3;              // blocks of kSiteBlock over the (x, y, z) volume
+    int nb3;              // blocks over the (x, y, z) volume
+    int tile[3];          // (x, y, z) extent of one block's sites; tile[0] = 0: kSiteBlock consecutive sites
+    int ntile[3];         // tiles along x, y, z (tile mode)
     int tch;              // t-slices marched by one block
     int nblk_march;       // nb3 * (Lt / tch): blocks of the marching kernels
     double2 *U;           // links [4][3][3][V] (the caller's array)
@@ -74,6 +76,7 @@ struct Cfg {
     const void *tw;       // twiddles exp(-2 pi i e / L_mu), axis mu at tw + tw_off[mu]
     int tw_off[4];
     double kfac;          // (alpha / 2) * p2max / V
+    void *kmom;           // K(p) per momentum site [V], double (FP64 transform) or float (FP32)
     int reunit_every;
     FftAxis ax[4];
     int xyQ, nxy;         // xy pass: Q consecutive xy-planes per tile, nxy tiles per field
@@ -103,6 +106,8 @@ struct Launch {
     int total_xy_tiles;
     int total_zt_tiles;
     int xy_cap, zt_cap;            // 2D tile capacity variant (1024, 2048 or 4096 elements)
+    int xy_th, zt_th;              // work-group size of the 2D passes (capacity / elements per work-item)
+    int xy_p2, zt_p2;              // every configuration has power-of-two extents in that pass
     int xy_tw2, xy_tw_total;       // LDS twiddle layout of the xy pass: y table offset, entries
     int zt_tw2, zt_tw_total;       // same for the zt pass
     int max_lds_elems;    // 1D passes: largest P * L
@@ -127,6 +132,7 @@ hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override);
 hipError_t launch_update(const Launch &L, int respect_done, const double2 *g_override);
 hipError_t launch_update_delta(const Launch &L);
 hipError_t launch_pack_links(const Launch &L);
+hipError_t launch_momentum_table(const Launch &L);
 hipError_t launch_unpack_links(const Launch &L);
 hipError_t launch_functional_g_impl(const Launch &L, int nblk, const double *omega, double scale, double *out);
 hipError_t launch_functional_g_backward_impl(const Launch &L, int nblk, const double *omega, double scale,

@@ -45,9 +45,9 @@ __global__ void k_arm(const Cfg *__restrict__ cfgs, int ncfg, double eps, long l
 // Im Delta_00 + i Im Delta_11), which carry all 8 real degrees of freedom of
 // the traceless anti-hermitian Delta, and per-block compensated partial sums
 // of sum_mu Re Tr U_mu(x) (Eq. 1 at g = 1) and |Delta|^2 (Eq. 4).
-// A block owns kSiteBlock consecutive sites of the (x, y, z) volume and walks
-// `tch` consecutive t-slices; U_t(x - t) of each slice is the U_t(x) loaded
-// for the previous slice, kept in registers.
+// A block owns a set of (x, y, z) sites (kSiteBlock consecutive ones, or a
+// box; see march_xyz) and walks `tch` consecutive t-slices; U_t(x - t) of
+// each slice is the U_t(x) loaded for the previous slice, kept in registers.
 template <typename T2>
 __global__ __launch_bounds__(kSiteBlock) void k_delta(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
                                                       int respect_done, double2 *__restrict__ full)
@@ -60,11 +60,12 @@ __global__ __launch_bounds__(kSiteBlock) void k_delta(const Cfg *__restrict__ cf
     const int V = C.V, V3 = C.V3;
     const int lb = blk - B->off_march[c];
     const int b3 = lb % C.nb3, tc = lb / C.nb3;
-    const int s3 = b3 * kSiteBlock + threadIdx.x;
+    int x, y, z;
+    const bool inside = march_xyz(C, b3, threadIdx.x, x, y, z);
     dd fs = {0.0, 0.0}, ts = {0.0, 0.0};
-    if (s3 < V3) {
+    if (inside) {
         const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
-        const int x = s3 % Lx, r = s3 / Lx, y = r % Ly, z = r / Ly;
+        const int s3 = x + Lx * (y + Ly * z);
         int back3[3];
         back3[0] = (x == 0) ? s3 + (Lx - 1) : s3 - 1;
         back3[1] = (y == 0) ? s3 + (Ly - 1) * Lx : s3 - Lx;
@@ -407,10 +408,20 @@ __device__ __forceinline__ void tile_load_contig(T2 *buf, const T2 *__restrict__
     }
 }
 
+// Rows of `rowlen` elements with `pad` LDS elements after each row.
 template <typename T2, int CAP, int TH>
 __device__ __forceinline__ void tile_load_padded(T2 *buf, const T2 *__restrict__ g, int n, int rowlen, int pad)
 {
     constexpr int NL = (CAP + TH - 1) / TH;
+    if (is_p2(rowlen)) {
+        const int lr = ilog2(rowlen);
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = threadIdx.x + k * TH;
+            if (i < n) buf[i + pad * (i >> lr)] = g[i];
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int i = threadIdx.x + k * TH;
@@ -422,6 +433,15 @@ template <typename T2, int CAP, int TH>
 __device__ __forceinline__ void tile_store_padded(T2 *__restrict__ g, const T2 *buf, int n, int rowlen, int pad)
 {
     constexpr int NL = (CAP + TH - 1) / TH;
+    if (is_p2(rowlen)) {
+        const int lr = ilog2(rowlen);
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = threadIdx.x + k * TH;
+            if (i < n) g[i] = buf[i + pad * (i >> lr)];
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int i = threadIdx.x + k * TH;
@@ -446,7 +466,8 @@ template <typename T2, int CAP, int TH>
 __device__ __forceinline__ void tile_load_rows(T2 *buf, const T2 *__restrict__ g, int P, int rows, size_t rs)
 {
     constexpr int NL = (CAP + TH - 1) / TH;
-    const int p = threadIdx.x % P, r0 = threadIdx.x / P, dr = TH / P;
+    const int lp = ilog2(P);
+    const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int r = r0 + k * dr;
@@ -456,16 +477,24 @@ __device__ __forceinline__ void tile_load_rows(T2 *buf, const T2 *__restrict__ g
 
 // As tile_load_rows / tile_store_rows, with `pad` LDS elements after every
 // `rpp` rows (row r at LDS r * P + pad * (r / rpp)).
+// LDS index of row r, element p, of a row tile with `pad` elements after
+// every 2^lrpp rows (lrpp < 0: after every rpp rows).
+__device__ __forceinline__ int rows_lds(int r, int p, int lp, int rpp, int lrpp, int pad)
+{
+    return (r << lp) + p + pad * (lrpp >= 0 ? (r >> lrpp) : (r / rpp));
+}
+
 template <typename T2, int CAP, int TH>
 __device__ __forceinline__ void tile_load_rows_padded(T2 *buf, const T2 *__restrict__ g, int P, int rows, size_t rs,
                                                       int rpp, int pad)
 {
     constexpr int NL = (CAP + TH - 1) / TH;
-    const int p = threadIdx.x % P, r0 = threadIdx.x / P, dr = TH / P;
+    const int lp = ilog2(P), lrpp = is_p2(rpp) ? ilog2(rpp) : -1;
+    const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int r = r0 + k * dr;
-        if (r < rows) buf[r * P + p + pad * (r / rpp)] = g[(size_t)r * rs + p];
+        if (r < rows) buf[rows_lds(r, p, lp, rpp, lrpp, pad)] = g[(size_t)r * rs + p];
     }
 }
 
@@ -474,11 +503,12 @@ __device__ __forceinline__ void tile_store_rows_padded(T2 *__restrict__ g, const
                                                        int rpp, int pad)
 {
     constexpr int NL = (CAP + TH - 1) / TH;
-    const int p = threadIdx.x % P, r0 = threadIdx.x / P, dr = TH / P;
+    const int lp = ilog2(P), lrpp = is_p2(rpp) ? ilog2(rpp) : -1;
+    const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int r = r0 + k * dr;
-        if (r < rows) g[(size_t)r * rs + p] = buf[r * P + p + pad * (r / rpp)];
+        if (r < rows) g[(size_t)r * rs + p] = buf[rows_lds(r, p, lp, rpp, lrpp, pad)];
     }
 }
 
@@ -486,7 +516,8 @@ template <typename T2, int CAP, int TH>
 __device__ __forceinline__ void tile_store_rows(T2 *__restrict__ g, const T2 *buf, int P, int rows, size_t rs)
 {
     constexpr int NL = (CAP + TH - 1) / TH;
-    const int p = threadIdx.x % P, r0 = threadIdx.x / P, dr = TH / P;
+    const int lp = ilog2(P);
+    const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int r = r0 + k * dr;
@@ -535,20 +566,12 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(const Cfg *__restrict__ cfg
     T2 *src = buf0, *dst = buf1;
     fft_pencils(src, dst, tw, A, ks, ls, mode == 1 ? -1 : sign, k_fast);
     if (mode == 1) {
-        // pencil k is inner site ic*P + k: momenta (nx, ny, nz); l is nt
-        const int ic = t % A.inner_chunks;
-        const double *s2 = C.sin2;
+        // element (l, k) of the tile is momentum site gbase + l S + k
+        const T *__restrict__ Km = (const T *)C.kmom + gbase;
+        const int lp = ilog2(P);
         for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-            const int k = idx % P, l = idx / P;
-            const int in = ic * P + k;
-            const int nx = in % C.dims[0];
-            const int r1 = in / C.dims[0];
-            const int ny = r1 % C.dims[1];
-            const int nz = r1 / C.dims[1];
-            const double p2 = s2[C.sin2_off[0] + nx] + s2[C.sin2_off[1] + ny] + s2[C.sin2_off[2] + nz] +
-                              s2[C.sin2_off[3] + l];
-            const double K = (p2 > 0.0) ? C.kfac / p2 : 0.0;
-            const T k_t = (T)K;
+            const int k = idx & (P - 1), l = idx >> lp;
+            const T k_t = Km[(size_t)l * A.S + k];
             T2 v = src[idx];
             v.x *= k_t;
             v.y *= k_t;
@@ -642,6 +665,78 @@ __device__ void fft_axis_ip(T2 *buf, const T2 *tw, const FftAxis &A, int npen, i
     }
 }
 
+// stage_ip for power-of-two extents (L = 2^lL, npen = 2^lnpen, m1 = 2^lm1,
+// Ns = 2^lNs) with pencils in k-fast order: the index arithmetic is shifts,
+// masks and 24-bit multiplies instead of integer divisions.
+template <int R, typename T2, int MAXE, int TH>
+__device__ __forceinline__ void stage_ip_p2(T2 *buf, const T2 *__restrict__ tw, int lL, int lnpen, int lm1, int a1,
+                                            int a2, int ls, int lNs, int sign)
+{
+    static_assert(R == 2 || R == 4 || R == 8, "power-of-two radix");
+    constexpr int lR = (R == 2) ? 1 : (R == 4) ? 2 : 3;
+    constexpr int MAXB = (MAXE + R * TH - 1) / (R * TH);
+    const int lnb = lL - lR;
+    const int total = 1 << (lnpen + lnb);
+    const int ltstep = lL - lNs - lR;
+    const int mstride = __mul24(1 << lnb, ls);  // element m of a butterfly: + m * nb * ls
+    const int qstride = ls << lNs;              // output q: + q * Ns * ls
+    T2 v[MAXB][R];
+    int ob[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = threadIdx.x + i * TH;
+        if (b < total) {
+            const int k = b & ((1 << lnpen) - 1), j = b >> lnpen;
+            const int base = __mul24(k & ((1 << lm1) - 1), a1) + __mul24(k >> lm1, a2);
+            const int kk = j & ((1 << lNs) - 1);
+            const int e0 = base + __mul24(j, ls);
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[i][m] = buf[e0 + m * mstride];
+            const int tb = kk << ltstep;
+#pragma unroll
+            for (int m = 1; m < R; ++m) {
+                T2 w = tw[m * tb];
+                if (sign > 0) w.y = -w.y;
+                v[i][m] = t_mul(v[i][m], w);
+            }
+            if constexpr (R == 2)
+                dft2(v[i]);
+            else if constexpr (R == 4)
+                dft4(v[i], sign);
+            else
+                dft8(v[i], sign);
+            ob[i] = base + __mul24(((j - kk) << lR) + kk, ls);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = threadIdx.x + i * TH;
+        if (b < total) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[ob[i] + q * qstride] = v[i][q];
+        }
+    }
+    __syncthreads();
+}
+
+// fft_axis_ip for a power-of-two axis and power-of-two pencil counts.
+template <typename T2, int MAXE, int TH>
+__device__ void fft_axis_ip_p2(T2 *buf, const T2 *tw, const FftAxis &A, int lnpen, int lm1, int a1, int a2, int ls,
+                               int sign)
+{
+    const int lL = ilog2(A.L);
+    int lNs = 0;
+    for (int st = 0; st < A.nstage; ++st) {
+        const int r = A.radix[st];
+        switch (r) {
+        case 2: stage_ip_p2<2, T2, MAXE, TH>(buf, tw, lL, lnpen, lm1, a1, a2, ls, lNs, sign); lNs += 1; break;
+        case 4: stage_ip_p2<4, T2, MAXE, TH>(buf, tw, lL, lnpen, lm1, a1, a2, ls, lNs, sign); lNs += 2; break;
+        default: stage_ip_p2<8, T2, MAXE, TH>(buf, tw, lL, lnpen, lm1, a1, a2, ls, lNs, sign); lNs += 3; break;
+        }
+    }
+}
+
 template <typename T2>
 __device__ __forceinline__ void load_twiddles(T2 *dst, const Cfg &C, int axis)
 {
@@ -653,24 +748,40 @@ __device__ __forceinline__ void load_twiddles(T2 *dst, const Cfg &C, int axis)
 // Element (x, y, q) sits at x + Xp (y + Ly q), Xp = Lx + xyPad: the padding
 // keeps neighbouring lanes, which work on neighbouring pencils, off the same
 // LDS banks in both directions.
-template <typename T2, int CAP, int TH>
+// P2: Lx, Ly and Q are powers of two (the caller checked), shift arithmetic.
+template <typename T2, int CAP, int TH, bool P2>
 __device__ __forceinline__ void xy_transform(T2 *buf, const T2 *twx, const T2 *twy, const Cfg &C, int Q, int sign)
 {
     const int Lx = C.dims[0], Ly = C.dims[1], Xp = Lx + C.xyPad;
-    // x: pencils k = (y, q), start k * Xp, unit stride
-    fft_axis_ip<T2, CAP, TH>(buf, twx, C.ax[0], Ly * Q, Ly * Q, Xp, 0, 1, sign, true);
-    // y: pencils k = (x, q), start x + Xp Ly q, stride Xp
-    fft_axis_ip<T2, CAP, TH>(buf, twy, C.ax[1], Lx * Q, Lx, 1, Xp * Ly, Xp, sign, true);
+    if constexpr (P2) {
+        const int lx = ilog2(Lx), ly = ilog2(Ly), lq = ilog2(Q);
+        // x: pencils k = (y, q), start k * Xp, unit stride
+        fft_axis_ip_p2<T2, CAP, TH>(buf, twx, C.ax[0], ly + lq, ly + lq, Xp, 0, 1, sign);
+        // y: pencils k = (x, q), start x + Xp Ly q, stride Xp
+        fft_axis_ip_p2<T2, CAP, TH>(buf, twy, C.ax[1], lx + lq, lx, 1, Xp * Ly, Xp, sign);
+    } else {
+        fft_axis_ip<T2, CAP, TH>(buf, twx, C.ax[0], Ly * Q, Ly * Q, Xp, 0, 1, sign, true);
+        fft_axis_ip<T2, CAP, TH>(buf, twy, C.ax[1], Lx * Q, Lx, 1, Xp * Ly, Xp, sign, true);
+    }
 }
 
+// Whether a configuration fits the power-of-two instances of the 2D passes.
+__device__ __forceinline__ bool xy_is_p2(const Cfg &C) { return is_p2(C.dims[0]) && is_p2(C.dims[1]) && is_p2(C.xyQ); }
+__device__ __forceinline__ bool zt_is_p2(const Cfg &C) { return is_p2(C.dims[2]) && is_p2(C.dims[3]); }
+
 // LDS index of element i of an xy tile in global (unpadded) order.
-__device__ __forceinline__ int xy_lds(const Cfg &C, int i) { return i + C.xyPad * (i / C.dims[0]); }
+__device__ __forceinline__ int xy_lds(const Cfg &C, int i)
+{
+    const int Lx = C.dims[0];
+    return i + C.xyPad * (is_p2(Lx) ? (i >> ilog2(Lx)) : (i / Lx));
+}
 
 // Pass over (x, y): tile = Q consecutive xy-planes of one field. LDS: CAP
 // data elements, then the twiddles of x (tw2 entries reserved) and y.
-template <typename T2, int CAP, int TH>
-__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_xy(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B, int sign,
-                                               void *fields_override, int respect_done, int tw2)
+template <typename T2, int CAP, int TH, bool P2>
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_xy(
+    const Cfg *__restrict__ cfgs, const Batch *__restrict__ B, int sign, void *fields_override, int respect_done,
+    int tw2)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -678,6 +789,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int c = find_cfg(B->off_xy, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
+    if (P2 && !xy_is_p2(C)) return;
     const int t = tile - B->off_xy[c];
     const int n = C.xyQ * C.V2;
     T2 *buf = (T2 *)smem;
@@ -688,7 +800,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)field * C.V + (size_t)t * n;
     tile_load_padded<T2, CAP, TH>(buf, g, n, C.dims[0], C.xyPad);
     __syncthreads();
-    xy_transform<T2, CAP, TH>(buf, twx, twy, C, C.xyQ, sign);
+    xy_transform<T2, CAP, TH, P2>(buf, twx, twy, C, C.xyQ, sign);
     tile_store_padded<T2, CAP, TH>(g, buf, n, C.dims[0], C.xyPad);
 }
 
@@ -696,9 +808,10 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // of one field, LDS layout [t][z][p]. mode 0: plain transform with `sign`;
 // mode 1: forward, multiplication by K(p) = (alpha/2)(p2max/p2)/V with
 // K(0) = 0 (Eq. 2; 1/V normalises the backward transform), backward.
-template <typename T2, int CAP, int TH>
-__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_zt(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B, int mode,
-                                               int sign, void *fields_override, int respect_done, int tw2)
+template <typename T2, int CAP, int TH, bool P2>
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_zt(
+    const Cfg *__restrict__ cfgs, const Batch *__restrict__ B, int mode, int sign, void *fields_override,
+    int respect_done, int tw2)
 {
     using T = typename Cx<T2>::T;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -707,6 +820,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int c = find_cfg(B->off_zt, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
+    if (P2 && !zt_is_p2(C)) return;
     const int t = tile - B->off_zt[c];
     const int P = C.ztP, Lz = C.dims[2], Lt = C.dims[3], V2 = C.V2;
     const int n = P * Lz * Lt;
@@ -719,34 +833,55 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)field * C.V + i0;
     // LDS layout [t][z][p] with t-planes Tp = P Lz + ztPad elements apart
     const int Tp = P * Lz + C.ztPad;
-    tile_load_rows_padded<T2, CAP, TH>(buf, g, P, Lz * Lt, V2, Lz, C.ztPad);
+    const int rows = Lz * Lt;
+    tile_load_rows_padded<T2, CAP, TH>(buf, g, P, rows, V2, Lz, C.ztPad);
+    // K(p) of this tile's elements, same (row, p) assignment as the tile load
+    constexpr int NL = (CAP + TH - 1) / TH;
+    const int lp = ilog2(P), lz = is_p2(Lz) ? ilog2(Lz) : -1;
+    const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
+    T kreg[NL];
+    if (mode == 1) {
+        const T *__restrict__ Km = (const T *)C.kmom + i0;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int r = r0 + k * dr;
+            kreg[k] = (r < rows) ? Km[(size_t)r * V2 + p] : (T)0;
+        }
+    }
     __syncthreads();
     const int s0 = (mode == 1) ? -1 : sign;
+    const int lt = P2 ? ilog2(Lt) : 0;
     // z: pencils k = (p, t), start p + Tp t, stride P
-    fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, s0, true);
     // t: pencils k = (p, z), start k, stride Tp
-    fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, s0, true);
+    if constexpr (P2) {
+        fft_axis_ip_p2<T2, CAP, TH>(buf, twz, C.ax[2], lp + lt, lp, 1, Tp, P, s0);
+        fft_axis_ip_p2<T2, CAP, TH>(buf, twt, C.ax[3], lp + lz, lp + lz, 1, 0, Tp, s0);
+    } else {
+        fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, s0, true);
+        fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, s0, true);
+    }
     if (mode == 1) {
-        const double *s2 = C.sin2;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const int p = i % P, zt = i / P;
-            const int nz = zt % Lz, nt = zt / Lz;
-            const int i2 = i0 + p;
-            const int nx = i2 % C.dims[0], ny = i2 / C.dims[0];
-            const double p2 = s2[C.sin2_off[0] + nx] + s2[C.sin2_off[1] + ny] + s2[C.sin2_off[2] + nz] +
-                              s2[C.sin2_off[3] + nt];
-            const T k_t = (T)((p2 > 0.0) ? C.kfac / p2 : 0.0);
-            const int li = p + P * nz + Tp * nt;
-            T2 v = buf[li];
-            v.x *= k_t;
-            v.y *= k_t;
-            buf[li] = v;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int r = r0 + k * dr;
+            if (r < rows) {
+                const int li = rows_lds(r, p, lp, Lz, lz, C.ztPad);
+                T2 v = buf[li];
+                v.x *= kreg[k];
+                v.y *= kreg[k];
+                buf[li] = v;
+            }
         }
         __syncthreads();
-        fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, +1, true);
-        fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, +1, true);
+        if constexpr (P2) {
+            fft_axis_ip_p2<T2, CAP, TH>(buf, twt, C.ax[3], lp + lz, lp + lz, 1, 0, Tp, +1);
+            fft_axis_ip_p2<T2, CAP, TH>(buf, twz, C.ax[2], lp + lt, lp, 1, Tp, P, +1);
+        } else {
+            fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, +1, true);
+            fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, +1, true);
+        }
     }
-    tile_store_rows_padded<T2, CAP, TH>(g, buf, P, Lz * Lt, V2, Lz, C.ztPad);
+    tile_store_rows_padded<T2, CAP, TH>(g, buf, P, rows, V2, Lz, C.ztPad);
 }
 
 // ============================================================ S4: g = 1 + Delta~, projected
@@ -806,7 +941,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_gauge(const Cfg *__restrict__ cf
 // Inverse transform over (x, y) of the four fields of Q xy-planes, then g and
 // its projection at every site of the tile (the last steps of the transform
 // and the gauge step in one pass; the fields are not written back).
-template <typename T2, int CAP, int TH>
+template <typename T2, int CAP, int TH, bool P2>
 __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
                                                          int respect_done, double2 *__restrict__ g_override, int tw2,
                                                          int two_row)
@@ -817,6 +952,7 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
     const int c = find_cfg(B->off_xy, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
+    if (P2 && !xy_is_p2(C)) return;
     const int t = tile - B->off_xy[c];
     const int n = C.xyQ * C.V2;
     const size_t site0 = (size_t)t * n;
@@ -831,7 +967,7 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
         const T2 *__restrict__ src = (const T2 *)C.fields + (size_t)f * C.V + site0;
         tile_load_padded<T2, CAP, TH>(buf, src, n, C.dims[0], C.xyPad);
         __syncthreads();
-        xy_transform<T2, CAP, TH>(buf, twx, twy, C, C.xyQ, +1);
+        xy_transform<T2, CAP, TH, P2>(buf, twx, twy, C, C.xyQ, +1);
 #pragma unroll
         for (int k = 0; k < MS; ++k) {
             const int i = threadIdx.x + k * TH;
@@ -851,8 +987,8 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
 // ============================================================ S5: link update
 // U_mu(x) -> g(x) U_mu(x) g^dag(x + mu) for the four links of each site; all
 // g were formed before this launch (the two separate loops of Alg. 1). A block
-// owns kSiteBlock consecutive sites of the (x, y, z) volume and walks `tch`
-// t-slices: g(x + t) of one slice is g(x) of the next, kept in registers.
+// owns a set of (x, y, z) sites (see march_xyz) and walks `tch` t-slices:
+// g(x + t) of one slice is g(x) of the next, kept in registers.
 __global__ __launch_bounds__(kSiteBlock) void k_update(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
                                                        int respect_done, const double2 *__restrict__ g_override,
                                                        int allow_reunit)
@@ -864,13 +1000,13 @@ __global__ __launch_bounds__(kSiteBlock) void k_update(const Cfg *__restrict__ c
     const int V = C.V, V3 = C.V3;
     const int lb = blk - B->off_march[c];
     const int b3 = lb % C.nb3, tc = lb / C.nb3;
-    const int s3 = b3 * kSiteBlock + threadIdx.x;
-    if (s3 >= V3) return;
+    int x, y, z;
+    if (!march_xyz(C, b3, threadIdx.x, x, y, z)) return;
     const double2 *__restrict__ G = g_override ? g_override : C.g;
     const bool reunit =
         allow_reunit && C.reunit_every > 0 && ((C.ctrl->iter + 1) % (long long)C.reunit_every) == 0;
     const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
-    const int x = s3 % Lx, r = s3 / Lx, y = r % Ly, z = r / Ly;
+    const int s3 = x + Lx * (y + Ly * z);
     int fwd3[3];
     fwd3[0] = (x == Lx - 1) ? s3 - (Lx - 1) : s3 + 1;
     fwd3[1] = (y == Ly - 1) ? s3 - (Ly - 1) * Lx : s3 + Lx;
@@ -935,11 +1071,12 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restri
     if (reunit != RU) return;
     const int lb = blk - B->off_march[c];
     const int b3 = lb % C.nb3, tc = lb / C.nb3;
-    const int s3 = b3 * kSiteBlock + threadIdx.x;
+    int x, y, z;
+    const bool inside = march_xyz(C, b3, threadIdx.x, x, y, z);
     dd fs = {0.0, 0.0}, ts = {0.0, 0.0};
-    if (s3 < V3) {
+    if (inside) {
         const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
-        const int x = s3 % Lx, r = s3 / Lx, y = r % Ly, z = r / Ly;
+        const int s3 = x + Lx * (y + Ly * z);
         int fwd3[3], back3[3];
         fwd3[0] = (x == Lx - 1) ? s3 - (Lx - 1) : s3 + 1;
         fwd3[1] = (y == Ly - 1) ? s3 - (Ly - 1) * Lx : s3 + Lx;
@@ -1023,6 +1160,27 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restri
         p[2] = ts.hi;
         p[3] = ts.lo;
     }
+}
+
+// K(p) = (alpha/2)(p2max/p2)/V for every momentum site, K(0) = 0 (Eq. 2; the
+// 1/V normalises the backward transform), with p2 = sum_mu 4 sin^2(pi n_mu /
+// L_mu); stored in the transform precision (an FP32 table holds the FP64
+// value rounded to nearest). Filled once when a context is set up.
+template <typename T>
+__global__ __launch_bounds__(kSiteBlock) void k_momentum_table(const Cfg *__restrict__ cfgs,
+                                                               const Batch *__restrict__ B)
+{
+    const int blk = blockIdx.x;
+    const int c = find_cfg(B->off_site, B->n, blk);
+    const Cfg &C = cfgs[B->idx[c]];
+    const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
+    if (s >= C.V) return;
+    int n[4];
+    site_coords(C.dims, s, n);
+    const double *s2 = C.sin2;
+    const double p2 =
+        s2[C.sin2_off[0] + n[0]] + s2[C.sin2_off[1] + n[1]] + s2[C.sin2_off[2] + n[2]] + s2[C.sin2_off[3] + n[3]];
+    ((T *)C.kmom)[s] = (T)((p2 > 0.0) ? C.kfac / p2 : 0.0);
 }
 
 // Caller's links -> two-row buffer 0 (start of a call).
@@ -1335,7 +1493,11 @@ hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *
 }
 
 // 2D pass variants by tile capacity: (elements, work-items).
-#define GF_2D_VARIANTS(X) X(1024, 256) X(2048, 256) X(4096, 512)
+// (tile capacity, work-group size) instances of the 2D passes: 4 or 8
+// elements per work-item.
+#define GF_2D_SIZES(X, P2) \
+    X(1024, 256, P2) X(1024, 128, P2) X(2048, 512, P2) X(2048, 256, P2) X(4096, 1024, P2) X(4096, 512, P2)
+#define GF_2D_VARIANTS(X) GF_2D_SIZES(X, true) GF_2D_SIZES(X, false)
 
 // LDS of a 2D tile: CAP elements plus CAP/8 for row padding, then twiddles.
 template <typename T2>
@@ -1346,12 +1508,13 @@ static size_t lds2d(int cap, int tw2, int tw_total)
 }
 
 template <typename T2>
-static hipError_t run_xy(const Launch &L, int cap, dim3 grid, int sign, void *fo, int rd)
+static hipError_t run_xy(const Launch &L, dim3 grid, int sign, void *fo, int rd)
 {
-    const size_t sh = lds2d<T2>(cap, L.xy_tw2, L.xy_tw_total);
-#define X(C_, T_)                                                                                                 \
-    if (cap == C_) {                                                                                              \
-        hipLaunchKernelGGL((k_fft_xy<T2, C_, T_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, sign, fo, rd,      \
+    const size_t sh = lds2d<T2>(L.xy_cap, L.xy_tw2, L.xy_tw_total);
+    const bool p2 = L.xy_p2 != 0;
+#define X(C_, T_, P2_)                                                                                            \
+    if (L.xy_cap == C_ && L.xy_th == T_ && p2 == P2_) {                                                           \
+        hipLaunchKernelGGL((k_fft_xy<T2, C_, T_, P2_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, sign, fo, rd, \
                            L.xy_tw2);                                                                             \
         return hipGetLastError();                                                                                 \
     }
@@ -1361,13 +1524,14 @@ static hipError_t run_xy(const Launch &L, int cap, dim3 grid, int sign, void *fo
 }
 
 template <typename T2>
-static hipError_t run_zt(const Launch &L, int cap, dim3 grid, int mode, int sign, void *fo, int rd)
+static hipError_t run_zt(const Launch &L, dim3 grid, int mode, int sign, void *fo, int rd)
 {
-    const size_t sh = lds2d<T2>(cap, L.zt_tw2, L.zt_tw_total);
-#define X(C_, T_)                                                                                                 \
-    if (cap == C_) {                                                                                              \
-        hipLaunchKernelGGL((k_fft_zt<T2, C_, T_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, mode, sign, fo,    \
-                           rd, L.zt_tw2);                                                                         \
+    const size_t sh = lds2d<T2>(L.zt_cap, L.zt_tw2, L.zt_tw_total);
+    const bool p2 = L.zt_p2 != 0;
+#define X(C_, T_, P2_)                                                                                            \
+    if (L.zt_cap == C_ && L.zt_th == T_ && p2 == P2_) {                                                           \
+        hipLaunchKernelGGL((k_fft_zt<T2, C_, T_, P2_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, mode, sign,   \
+                           fo, rd, L.zt_tw2);                                                                     \
         return hipGetLastError();                                                                                 \
     }
     GF_2D_VARIANTS(X)
@@ -1376,13 +1540,14 @@ static hipError_t run_zt(const Launch &L, int cap, dim3 grid, int mode, int sign
 }
 
 template <typename T2>
-static hipError_t run_xyg(const Launch &L, int cap, int rd, double2 *go)
+static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
 {
-    const size_t sh = lds2d<T2>(cap, L.xy_tw2, L.xy_tw_total);
-#define X(C_, T_)                                                                                                 \
-    if (cap == C_) {                                                                                              \
-        hipLaunchKernelGGL((k_fft_xy_inv_gauge<T2, C_, T_>), dim3(L.total_xy_tiles), dim3(T_), sh, L.stream, L.cfgs, \
-                           L.batch, rd, go, L.xy_tw2, L.fused);                                                   \
+    const size_t sh = lds2d<T2>(L.xy_cap, L.xy_tw2, L.xy_tw_total);
+    const bool p2 = L.xy_p2 != 0;
+#define X(C_, T_, P2_)                                                                                            \
+    if (L.xy_cap == C_ && L.xy_th == T_ && p2 == P2_) {                                                           \
+        hipLaunchKernelGGL((k_fft_xy_inv_gauge<T2, C_, T_, P2_>), dim3(L.total_xy_tiles), dim3(T_), sh, L.stream,    \
+                           L.cfgs, L.batch, rd, go, L.xy_tw2, L.fused);                                           \
         return hipGetLastError();                                                                                 \
     }
     GF_2D_VARIANTS(X)
@@ -1393,15 +1558,15 @@ static hipError_t run_xyg(const Launch &L, int cap, int rd, double2 *go)
 hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done)
 {
     const dim3 grid(L.total_xy_tiles, nfields);
-    return L.fp32 ? run_xy<float2>(L, L.xy_cap, grid, sign, fields_override, respect_done)
-                  : run_xy<double2>(L, L.xy_cap, grid, sign, fields_override, respect_done);
+    return L.fp32 ? run_xy<float2>(L, grid, sign, fields_override, respect_done)
+                  : run_xy<double2>(L, grid, sign, fields_override, respect_done);
 }
 
 hipError_t launch_fft_zt(const Launch &L, int mode, int sign, void *fields_override, int nfields, int respect_done)
 {
     const dim3 grid(L.total_zt_tiles, nfields);
-    return L.fp32 ? run_zt<float2>(L, L.zt_cap, grid, mode, sign, fields_override, respect_done)
-                  : run_zt<double2>(L, L.zt_cap, grid, mode, sign, fields_override, respect_done);
+    return L.fp32 ? run_zt<float2>(L, grid, mode, sign, fields_override, respect_done)
+                  : run_zt<double2>(L, grid, mode, sign, fields_override, respect_done);
 }
 
 hipError_t launch_fft_zt_scale(const Launch &L, int respect_done)
@@ -1411,8 +1576,7 @@ hipError_t launch_fft_zt_scale(const Launch &L, int respect_done)
 
 hipError_t launch_fft_xy_inv_gauge(const Launch &L, int respect_done, double2 *g_override)
 {
-    return L.fp32 ? run_xyg<float2>(L, L.xy_cap, respect_done, g_override)
-                  : run_xyg<double2>(L, L.xy_cap, respect_done, g_override);
+    return L.fp32 ? run_xyg<float2>(L, respect_done, g_override) : run_xyg<double2>(L, respect_done, g_override);
 }
 
 template <typename T2>
@@ -1420,15 +1584,15 @@ static hipError_t set_lds_t()
 {
     const int bytes = (int)lds2d<T2>(4096, 256, 512);
     hipError_t e = hipSuccess;
-#define X(C_, T_)                                                                                              \
-    if (e == hipSuccess)                                                                                       \
-        e = hipFuncSetAttribute((const void *)k_fft_xy<T2, C_, T_>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                bytes);                                                                        \
-    if (e == hipSuccess)                                                                                       \
-        e = hipFuncSetAttribute((const void *)k_fft_zt<T2, C_, T_>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                bytes);                                                                        \
-    if (e == hipSuccess)                                                                                       \
-        e = hipFuncSetAttribute((const void *)k_fft_xy_inv_gauge<T2, C_, T_>,                                  \
+#define X(C_, T_, P2_)                                                                                          \
+    if (e == hipSuccess)                                                                                        \
+        e = hipFuncSetAttribute((const void *)k_fft_xy<T2, C_, T_, P2_>,                                        \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);                             \
+    if (e == hipSuccess)                                                                                        \
+        e = hipFuncSetAttribute((const void *)k_fft_zt<T2, C_, T_, P2_>,                                        \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);                             \
+    if (e == hipSuccess)                                                                                        \
+        e = hipFuncSetAttribute((const void *)k_fft_xy_inv_gauge<T2, C_, T_, P2_>,                              \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     GF_2D_VARIANTS(X)
 #undef X
@@ -1472,6 +1636,17 @@ hipError_t launch_pack_links(const Launch &L)
 {
     hipLaunchKernelGGL(k_set_cur, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.ncfg, 0);
     hipLaunchKernelGGL(k_pack_links, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs, L.batch);
+    return hipGetLastError();
+}
+
+hipError_t launch_momentum_table(const Launch &L)
+{
+    if (L.fp32)
+        hipLaunchKernelGGL(k_momentum_table<float>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
+                           L.batch);
+    else
+        hipLaunchKernelGGL(k_momentum_table<double>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
+                           L.batch);
     return hipGetLastError();
 }
 

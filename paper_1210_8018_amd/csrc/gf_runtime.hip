@@ -65,13 +65,37 @@ int largest_divisor_at_most(int n, int cap)
     return 1;
 }
 
-// Blocks of the t-marching kernels: kSiteBlock consecutive (x, y, z) sites
-// times `tch` t-slices. More slices per block save the re-read of the
-// t-neighbour at the first slice; fewer give more blocks.
-int plan_tchunk(const int dims[4])
+// Sites of one block of the t-marching kernels: kSiteBlock consecutive
+// (x, y, z) sites (tile[0] = 0), or a tx x ty x tz box (GF_TILE="tx,ty,tz",
+// tx * ty * tz between 64 and kSiteBlock). Returns the number of blocks over
+// the (x, y, z) volume.
+int plan_tile(const int dims[4], int tile[3], int ntile[3])
 {
-    const int V3 = dims[0] * dims[1] * dims[2];
-    const int nb3 = (V3 + kSiteBlock - 1) / kSiteBlock;
+    tile[0] = tile[1] = tile[2] = 0;
+    ntile[0] = ntile[1] = ntile[2] = 0;
+    const char *env = getenv("GF_TILE");
+    int t[3];
+    if (env && sscanf(env, "%d,%d,%d", &t[0], &t[1], &t[2]) == 3) {
+        bool ok = t[0] * t[1] * t[2] <= kSiteBlock && t[0] * t[1] * t[2] >= 64;
+        for (int a = 0; a < 3; ++a) ok = ok && t[a] >= 1 && t[a] <= dims[a];
+        if (ok) {
+            int n = 1;
+            for (int a = 0; a < 3; ++a) {
+                tile[a] = t[a];
+                ntile[a] = (dims[a] + t[a] - 1) / t[a];
+                n *= ntile[a];
+            }
+            return n;
+        }
+    }
+    return (dims[0] * dims[1] * dims[2] + kSiteBlock - 1) / kSiteBlock;
+}
+
+// Blocks of the t-marching kernels: nb3 site sets times `tch` t-slices. More
+// slices per block save the re-read of the t-neighbour at the first slice;
+// fewer give more blocks.
+int plan_tchunk(const int dims[4], int nb3)
+{
     const char *env = getenv("GF_TCHUNK");
     if (env) {
         const int t = atoi(env);
@@ -90,13 +114,15 @@ int plan_xyQ(const int dims[4], int target)
     return largest_divisor_at_most(dims[2] * dims[3], (target < kTileElems2D ? target : kTileElems2D) / V2);
 }
 
-// zt tiles: P consecutive xy-sites times the (z, t) plane; P is a power of
-// two dividing Lx * Ly (so it divides the block size).
-int plan_ztP(const int dims[4])
+// zt tiles: P consecutive xy-sites times the (z, t) plane, P * Lz * Lt <=
+// target elements; P is a power of two dividing Lx * Ly and at most 128 (so
+// it divides every work-group size of the pass).
+int plan_ztP(const int dims[4], int target)
 {
-    const int V2 = dims[0] * dims[1], cap = kTileElems2D / (dims[2] * dims[3]);
+    const int V2 = dims[0] * dims[1];
+    const int cap = (target < kTileElems2D ? target : kTileElems2D) / (dims[2] * dims[3]);
     int P = 1;
-    while (V2 % (2 * P) == 0 && 2 * P <= cap && 2 * P <= 256) P *= 2;
+    while (V2 % (2 * P) == 0 && 2 * P <= cap && 2 * P <= 128) P *= 2;
     return P;
 }
 
@@ -133,15 +159,15 @@ FftAxis plan_axis(const int dims[4], int mu)
 }
 
 struct Layout {
-    size_t fields, g, partials, sin2, tw, links12a, links12b, g12, total;
+    size_t fields, g, partials, sin2, tw, links12a, links12b, g12, kmom, total;
 };
 
 Layout layout_for(const gf_params &p, size_t start)
 {
     const size_t V = (size_t)p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
     const size_t nblk_site = (V + kSiteBlock - 1) / kSiteBlock;
-    const size_t V3 = (size_t)p.dims[0] * p.dims[1] * p.dims[2];
-    const size_t nblk_march = ((V3 + kSiteBlock - 1) / kSiteBlock) * (size_t)p.dims[3];  // upper bound (tch = 1)
+    int tile[3], ntile[3];
+    const size_t nblk_march = (size_t)plan_tile(p.dims, tile, ntile) * (size_t)p.dims[3];  // upper bound (tch = 1)
     const size_t nblk = nblk_site > nblk_march ? nblk_site : nblk_march;
     const size_t csz = p.fft_prec ? 8 : 16;
     const size_t sumL = (size_t)p.dims[0] + p.dims[1] + p.dims[2] + p.dims[3];
@@ -164,6 +190,9 @@ Layout layout_for(const gf_params &p, size_t start)
     o = align_up(o + 24 * V * 16);
     l.g12 = o;
     o = align_up(o + 6 * V * 16);
+    // K(p) table in the transform's precision
+    l.kmom = o;
+    o = align_up(o + V * (csz / 2));
     l.total = o;
     return l;
 }
@@ -181,6 +210,17 @@ struct KTime {
 };
 
 }  // namespace
+
+// Tile choices of the 2D passes: target elements per tile and elements per
+// work-item (the work-group size is the tile capacity divided by it).
+struct Tiles {
+    int xy_target = 1024, xy_ept = 4;
+    int zt_target = 4096, zt_ept = 8;
+    bool operator==(const Tiles &o) const
+    {
+        return xy_target == o.xy_target && xy_ept == o.xy_ept && zt_target == o.zt_target && zt_ept == o.zt_ept;
+    }
+};
 
 struct gf_ctx_s {
     int ncfg = 0;
@@ -212,7 +252,7 @@ struct gf_ctx_s {
     size_t ev_used = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     int sched = kSched1D;
-    int xy_target = 4096;
+    Tiles tiles;
 };
 
 namespace {
@@ -507,13 +547,13 @@ void drop_graph(gf_ctx c)
 
 // Tile shapes of the 2D passes for every configuration, the full map and the
 // launch totals; uploads the configuration table.
-gf_status apply_schedule(gf_ctx c, int sched, int xy_target)
+gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
 {
     for (int k = 0; k < c->ncfg; ++k) {
         Cfg &C = c->cfg[k];
-        C.xyQ = xy_feasible(C.dims) ? plan_xyQ(C.dims, xy_target) : 1;
+        C.xyQ = xy_feasible(C.dims) ? plan_xyQ(C.dims, tl.xy_target) : 1;
         C.nxy = xy_feasible(C.dims) ? (C.dims[2] * C.dims[3]) / C.xyQ : 0;
-        C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims) : 1;
+        C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims, tl.zt_target) : 1;
         C.nzt = zt_feasible(C.dims) ? C.V2 / C.ztP : 0;
         // bank-spreading pads, kept inside the 1/8 slack of the LDS tile
         const char *np = getenv("GF_NO_LDS_PAD");
@@ -527,10 +567,14 @@ gf_status apply_schedule(gf_ctx c, int sched, int xy_target)
     for (int k = 0; k < c->ncfg; ++k) all[k] = k;
     fill_map(c, all, c->bmap, c->L);
     int xy_max = 0, zt_max = 0, mx = 0, my = 0, mz = 0, mt = 0;
+    bool xy_p2 = true, zt_p2 = true;
+    auto p2 = [](int v) { return (v & (v - 1)) == 0; };
     for (int k = 0; k < c->ncfg; ++k) {
         const Cfg &C = c->cfg[k];
         if (C.nxy) xy_max = std::max(xy_max, C.xyQ * C.V2);
         if (C.nzt) zt_max = std::max(zt_max, C.ztP * C.dims[2] * C.dims[3]);
+        xy_p2 = xy_p2 && p2(C.dims[0]) && p2(C.dims[1]) && p2(C.xyQ);
+        zt_p2 = zt_p2 && p2(C.dims[2]) && p2(C.dims[3]);
         mx = std::max(mx, C.dims[0]);
         my = std::max(my, C.dims[1]);
         mz = std::max(mz, C.dims[2]);
@@ -539,12 +583,16 @@ gf_status apply_schedule(gf_ctx c, int sched, int xy_target)
     auto cap_for = [](int n) { return n <= 1024 ? 1024 : (n <= 2048 ? 2048 : 4096); };
     c->L.xy_cap = cap_for(xy_max);
     c->L.zt_cap = cap_for(zt_max);
+    c->L.xy_th = c->L.xy_cap / tl.xy_ept;
+    c->L.zt_th = c->L.zt_cap / tl.zt_ept;
+    c->L.xy_p2 = xy_p2;
+    c->L.zt_p2 = zt_p2;
     c->L.xy_tw2 = mx;
     c->L.xy_tw_total = mx + my;
     c->L.zt_tw2 = mz;
     c->L.zt_tw_total = mz + mt;
     c->sched = sched;
-    c->xy_target = xy_target;
+    c->tiles = tl;
     // the active map starts as the full one
     c->bact = c->bmap;
     c->Lact = c->L;
@@ -608,9 +656,17 @@ std::string tune_key(gf_ctx c)
     return k;
 }
 
-std::vector<std::pair<std::string, std::pair<int, int>>> &tune_cache()
+struct TuneEntry {
+    std::string key;
+    int sched;
+    Tiles tiles;
+};
+
+// Schedules picked so far in this process, and those of GF_AUTOTUNE_CACHE
+// (lines: key schedule xy_target xy_ept zt_target zt_ept).
+std::vector<TuneEntry> &tune_cache()
 {
-    static std::vector<std::pair<std::string, std::pair<int, int>>> cache;
+    static std::vector<TuneEntry> cache;
     static bool loaded = false;
     if (!loaded) {
         loaded = true;
@@ -619,8 +675,12 @@ std::vector<std::pair<std::string, std::pair<int, int>>> &tune_cache()
             FILE *f = fopen(path, "r");
             if (f) {
                 char key[4096];
-                int s, q;
-                while (fscanf(f, "%4095s %d %d", key, &s, &q) == 3) cache.push_back({key, {s, q}});
+                TuneEntry e;
+                while (fscanf(f, "%4095s %d %d %d %d %d", key, &e.sched, &e.tiles.xy_target, &e.tiles.xy_ept,
+                              &e.tiles.zt_target, &e.tiles.zt_ept) == 6) {
+                    e.key = key;
+                    cache.push_back(e);
+                }
                 fclose(f);
             }
         }
@@ -628,26 +688,57 @@ std::vector<std::pair<std::string, std::pair<int, int>>> &tune_cache()
     return cache;
 }
 
+bool valid_tiles(const Tiles &t)
+{
+    auto ok_target = [](int v) { return v == 1024 || v == 2048 || v == 4096; };
+    return ok_target(t.xy_target) && ok_target(t.zt_target) && (t.xy_ept == 4 || t.xy_ept == 8) &&
+           (t.zt_ept == 4 || t.zt_ept == 8);
+}
+
+// Tile choices of a fixed schedule: defaults, overridden by GF_XY_TARGET,
+// GF_XY_EPT, GF_ZT_TARGET, GF_ZT_EPT.
+Tiles env_tiles()
+{
+    Tiles t;
+    auto rd = [](const char *name, int &v) {
+        const char *e = getenv(name);
+        if (e) v = atoi(e);
+    };
+    rd("GF_XY_TARGET", t.xy_target);
+    rd("GF_XY_EPT", t.xy_ept);
+    rd("GF_ZT_TARGET", t.zt_target);
+    rd("GF_ZT_EPT", t.zt_ept);
+    return valid_tiles(t) ? t : Tiles();
+}
+
 // Pick the transform schedule: the requested one, or (0) the fastest of the
 // feasible candidates timed on this context's fields, cached per shape.
 gf_status choose_schedule(gf_ctx c, int requested)
 {
-    if (requested != kSchedAuto) {
-        const char *env = getenv("GF_XY_TARGET");
-        return apply_schedule(c, requested, env ? atoi(env) : 1024);
-    }
+    if (requested != kSchedAuto) return apply_schedule(c, requested, env_tiles());
     const std::string key = tune_key(c);
     for (auto &e : tune_cache())
-        if (e.first == key && sched_feasible(c, e.second.first))
-            return apply_schedule(c, e.second.first, e.second.second);
+        if (e.key == key && sched_feasible(c, e.sched) && valid_tiles(e.tiles))
+            return apply_schedule(c, e.sched, e.tiles);
     struct Cand {
-        int sched, xy;
+        int sched;
+        Tiles tiles;
     };
-    std::vector<Cand> cands = {{kSched1D, 4096}};
-    for (int xy : {1024, 4096}) {
-        if (sched_feasible(c, kSchedXY1D)) cands.push_back({kSchedXY1D, xy});
-        if (sched_feasible(c, kSchedXYZT)) cands.push_back({kSchedXYZT, xy});
-    }
+    std::vector<Cand> cands = {{kSched1D, Tiles()}};
+    for (int xt : {1024, 4096})
+        for (int xe : {4, 8}) {
+            Tiles t;
+            t.xy_target = xt;
+            t.xy_ept = xe;
+            if (sched_feasible(c, kSchedXY1D)) cands.push_back({kSchedXY1D, t});
+            if (!sched_feasible(c, kSchedXYZT)) continue;
+            for (int zt : {2048, 4096})
+                for (int ze : {4, 8}) {
+                    t.zt_target = zt;
+                    t.zt_ept = ze;
+                    cands.push_back({kSchedXYZT, t});
+                }
+        }
     double best = 1e300;
     Cand pick = cands[0];
     hipEvent_t e0 = take_event(c), e1 = take_event(c);
@@ -655,7 +746,7 @@ gf_status choose_schedule(gf_ctx c, int requested)
     const bool timing = c->timing;
     c->timing = false;
     for (const Cand &cd : cands) {
-        gf_status st = apply_schedule(c, cd.sched, cd.xy);
+        gf_status st = apply_schedule(c, cd.sched, cd.tiles);
         if (st != GF_OK) return st;
         HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, nullptr));  // warm-up
         HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -673,14 +764,15 @@ gf_status choose_schedule(gf_ctx c, int requested)
     c->ev_used = 0;
     // the fields were transformed in place: measure again so they hold Delta
     HIPCHK(c, enqueue_measure(c));
-    gf_status st = apply_schedule(c, pick.sched, pick.xy);
+    gf_status st = apply_schedule(c, pick.sched, pick.tiles);
     if (st != GF_OK) return st;
-    tune_cache().push_back({key, {pick.sched, pick.xy}});
+    tune_cache().push_back({key, pick.sched, pick.tiles});
     const char *path = getenv("GF_AUTOTUNE_CACHE");
     if (path) {
         FILE *f = fopen(path, "a");
         if (f) {
-            fprintf(f, "%s %d %d\n", key.c_str(), pick.sched, pick.xy);
+            fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), pick.sched, pick.tiles.xy_target, pick.tiles.xy_ept,
+                    pick.tiles.zt_target, pick.tiles.zt_ept);
             fclose(f);
         }
     }
@@ -734,8 +826,8 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         C.V2 = p.dims[0] * p.dims[1];
         C.V3 = C.V2 * p.dims[2];
         C.nblk_site = (C.V + kSiteBlock - 1) / kSiteBlock;
-        C.nb3 = (C.V3 + kSiteBlock - 1) / kSiteBlock;
-        C.tch = plan_tchunk(p.dims);
+        C.nb3 = plan_tile(p.dims, C.tile, C.ntile);
+        C.tch = plan_tchunk(p.dims, C.nb3);
         C.nblk_march = C.nb3 * (p.dims[3] / C.tch);
         C.U = (double2 *)links[k];
         C.U12[0] = (double2 *)(c->ws + l.links12a);
@@ -747,6 +839,7 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         C.ctrl = (Ctrl *)(c->ws + ctrl_base) + k;
         C.sin2 = (const double *)(c->ws + l.sin2);
         C.tw = c->ws + l.tw;
+        C.kmom = c->ws + l.kmom;
         int off = 0;
         for (int mu = 0; mu < 4; ++mu) {
             C.sin2_off[mu] = off;
@@ -793,6 +886,7 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
                                  c->stream));
     }
     HIPCHK(c, set_lds_limits());
+    HIPCHK(c, launch_momentum_table(c->L));
     HIPCHK(c, launch_arm(c->L, ncfg, 0.0, 0, 1));
     HIPCHK(c, enqueue_measure(c));
     gf_status st = read_ctrl(c);

@@ -89,6 +89,34 @@ def test_gauge_vector_matches_oracle(dims, prec, sched):
     assert np.max(np.abs(np.linalg.det(M) - 1)) < 1e-13
 
 
+TILE_VARIANTS = [  # (xy target, xy elements per work-item, zt target, zt elements per work-item)
+    (1024, 8, 2048, 4), (4096, 4, 2048, 8), (4096, 8, 4096, 4), (2048, 4, 1024, 8), (1024, 4, 4096, 8)]
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (12, 8, 6, 4), (24, 4, 2, 6), (4, 12, 4, 8), (16, 8, 4, 32)])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("tiles", TILE_VARIANTS)
+def test_2d_tile_variants_match_oracle(monkeypatch, dims, prec, tiles):
+    """Every (tile size, work-group size) instance of the 2D passes: transform and gauge vector."""
+    for name, v in zip(("GF_XY_TARGET", "GF_XY_EPT", "GF_ZT_TARGET", "GF_ZT_EPT"), tiles):
+        monkeypatch.setenv(name, str(v))
+    V = int(np.prod(dims))
+    U = random_links(dims, 0.4, 43)
+    fx = GaugeFixer(dev(U), fft_prec=prec, fft_schedule=3)
+    g = host(fx.gauge())
+    gref = oracle.gauge_from_delta(dims, oracle.delta(dims, U), ALPHA)
+    assert np.max(np.abs(g - gref)) < (2e-6 if prec else 1e-13)
+    rng = np.random.default_rng(7)
+    f = rng.standard_normal((2, V)) + 1j * rng.standard_normal((2, V))
+    ct = torch.complex64 if prec else torch.complex128
+    tol = 3e-6 if prec else 1e-13
+    for sign in (-1, +1):
+        got = host(fx.fft(torch.from_numpy(f).to(ct).to("cuda").contiguous(), sign)).astype(np.complex128)
+        for k in range(2):
+            ref = oracle.fft4d(dims, f[k], sign)
+            assert np.max(np.abs(got[k] - ref)) < tol * np.max(np.abs(ref)), (sign, k)
+
+
 @pytest.mark.parametrize("dims", SHAPES)
 def test_link_update_matches_oracle(dims):
     V = int(np.prod(dims))
@@ -158,6 +186,23 @@ def test_unfused_full_storage_path_matches_oracle(monkeypatch):
     assert it == n_ref
     compare_trajectory(Fh, Th, Fr, Tr, int(np.prod(dims)))
     assert abs(oracle.plaquette(dims, host(Ud)) - oracle.plaquette(dims, U)) < 1e-13
+
+
+@pytest.mark.parametrize("dims,tile,fuse", [((8, 8, 8, 8), "4,4,4", True), ((12, 8, 6, 4), "8,4,4", True),
+                                            ((12, 8, 6, 4), "8,4,4", False), ((6, 6, 6, 2), "4,4,6", True)])
+def test_box_tiles_match_oracle(monkeypatch, dims, tile, fuse):
+    """Marching kernels with box-shaped site sets (GF_TILE), ragged boxes included."""
+    monkeypatch.setenv("GF_TILE", tile)
+    if not fuse:
+        monkeypatch.setenv("GF_NOFUSE", "1")
+    U = random_links(dims, 0.3, 1)
+    n_ref, _, Fr, Tr = oracle.fix(dims, U, alpha=ALPHA, eps=EPS, max_iter=5000)
+    Ud = dev(U)
+    fx = GaugeFixer(Ud)
+    it, F, th = fx.fix_until(EPS, 5000)
+    Fh, Th = fx.history()
+    assert it == n_ref
+    compare_trajectory(Fh, Th, Fr, Tr, int(np.prod(dims)))
 
 
 def test_step_equals_fix_prefix():
