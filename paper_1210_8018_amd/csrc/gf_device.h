@@ -153,6 +153,62 @@ __device__ __forceinline__ M3 m3_identity()
     return c;
 }
 
+// Rows 0 and 1 of a b c^dag, row 2 rebuilt as conj(r0 x r1): the product of
+// special unitary matrices is special unitary, so this is the full product up
+// to rounding, for two thirds of the multiplications.
+__device__ __forceinline__ M3 m3_mul_mul_dag_rows(const M3 &a, const M3 &b, const M3 &c)
+{
+    M3 w;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        double2 ab[3];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            double2 acc = cmul(a.e[i * 3], b.e[l]);
+            acc = cadd(acc, cmul(a.e[i * 3 + 1], b.e[3 + l]));
+            ab[l] = cadd(acc, cmul(a.e[i * 3 + 2], b.e[6 + l]));
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double2 acc = cmulc(ab[0], c.e[j * 3]);
+            acc = cadd(acc, cmulc(ab[1], c.e[j * 3 + 1]));
+            w.e[i * 3 + j] = cadd(acc, cmulc(ab[2], c.e[j * 3 + 2]));
+        }
+    }
+    m3_row2(w);
+    return w;
+}
+
+// Anti-hermitian part M - M^dag of a 3x3 matrix: the upper off-diagonal
+// entries (the lower ones are minus their conjugates) and the imaginary parts
+// of the diagonal (its real parts vanish).
+struct AH {
+    double2 o01, o02, o12;
+    double d0, d1, d2;
+};
+
+__device__ __forceinline__ AH ah_of(const M3 &m)
+{
+    AH a;
+    a.o01 = csub(m.e[1], cconj(m.e[3]));
+    a.o02 = csub(m.e[2], cconj(m.e[6]));
+    a.o12 = csub(m.e[5], cconj(m.e[7]));
+    a.d0 = 2.0 * m.e[0].y;
+    a.d1 = 2.0 * m.e[4].y;
+    a.d2 = 2.0 * m.e[8].y;
+    return a;
+}
+
+__device__ __forceinline__ void ah_acc(AH &a, const AH &b, double sgn)
+{
+    a.o01 = make_double2(a.o01.x + sgn * b.o01.x, a.o01.y + sgn * b.o01.y);
+    a.o02 = make_double2(a.o02.x + sgn * b.o02.x, a.o02.y + sgn * b.o02.y);
+    a.o12 = make_double2(a.o12.x + sgn * b.o12.x, a.o12.y + sgn * b.o12.y);
+    a.d0 += sgn * b.d0;
+    a.d1 += sgn * b.d1;
+    a.d2 += sgn * b.d2;
+}
+
 // Projection to SU(3) by row Gram-Schmidt; the third row is conj(r0 x r1).
 __device__ __forceinline__ void m3_reunit(M3 &m)
 {

@@ -113,6 +113,7 @@ struct Launch {
     int max_lds_elems;    // 1D passes: largest P * L
     int fp32;             // transform precision
     int fused;            // iterations use the fused update + divergence kernel
+    int xchg;             // ... in its LDS neighbour-exchange form
     int any_reunit;       // some configuration projects its links every R updates
     int ncfg;
     hipStream_t stream;

@@ -1162,6 +1162,174 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restri
     }
 }
 
+// The fused pass with neighbour exchange through LDS. Per t-slice each
+// work-item publishes its g(x) (two rows) and, after its forward links,
+// U'_mu(x) - U'_mu(x)^dag for mu = x, y; a neighbour inside the block reads
+// them instead of loading g(x + mu) and recomputing U'_nu(x - nu) from the old
+// links. Neighbours in other blocks (all of z, the block's edge rows in y) are
+// loaded and recomputed as in k_update_delta. The new links are formed by
+// their first two rows (m3_mul_mul_dag_rows), exactly what is stored, so a
+// recomputed backward link equals the one its owner writes. Divergence and
+// sums as in k_update_delta; D is accumulated as its anti-hermitian part.
+__device__ __forceinline__ int block_slot(int b3, int s3n)
+{
+    const int o = s3n - b3 * kSiteBlock;
+    return (o >= 0 && o < kSiteBlock) ? o : -1;
+}
+
+template <typename T2, bool RU>
+__global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__restrict__ cfgs,
+                                                               const Batch *__restrict__ B)
+{
+    __shared__ dd red[2 * (kSiteBlock / 64)];
+    __shared__ double2 sg[6][kSiteBlock];    // g(x), rows 0 and 1, of the block's sites at this slice
+    __shared__ double sa[2][9][kSiteBlock];  // U'_mu(x) - U'_mu(x)^dag (AH order), mu = x, y
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int c = find_cfg(B->off_march, B->n, blk);
+    const Cfg &C = cfgs[B->idx[c]];
+    const Ctrl *ct = C.ctrl;
+    if (ct->done) return;  // the whole block leaves together
+    const int V = C.V, V3 = C.V3;
+    const double2 *__restrict__ Uo = C.U12[ct->cur];
+    double2 *__restrict__ Un = C.U12[ct->cur ^ 1];
+    const double2 *__restrict__ G = C.g12;
+    const bool reunit = C.reunit_every > 0 && ct->ru_now;
+    if (reunit != RU) return;
+    const int lb = blk - B->off_march[c];
+    const int b3 = lb % C.nb3, tc = lb / C.nb3;
+    const int tid = threadIdx.x;
+    int x, y, z;
+    const bool inside = march_xyz(C, b3, tid, x, y, z);
+    const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
+    const int s3 = x + Lx * (y + Ly * z);
+    int fwd3[3], back3[3], sf[2], sb[2];
+    fwd3[0] = (x == Lx - 1) ? s3 - (Lx - 1) : s3 + 1;
+    fwd3[1] = (y == Ly - 1) ? s3 - (Ly - 1) * Lx : s3 + Lx;
+    fwd3[2] = (z == Lz - 1) ? s3 - (Lz - 1) * C.V2 : s3 + C.V2;
+    back3[0] = (x == 0) ? s3 + (Lx - 1) : s3 - 1;
+    back3[1] = (y == 0) ? s3 + (Ly - 1) * Lx : s3 - Lx;
+    back3[2] = (z == 0) ? s3 + (Lz - 1) * C.V2 : s3 - C.V2;
+    const bool lin = C.tile[0] == 0;  // exchange needs the linear site sets
+#pragma unroll
+    for (int mu = 0; mu < 2; ++mu) {
+        sf[mu] = (inside && lin) ? block_slot(b3, fwd3[mu]) : -1;
+        sb[mu] = (inside && lin) ? block_slot(b3, back3[mu]) : -1;
+    }
+    const int t0 = tc * C.tch;
+    dd fs = {0.0, 0.0}, ts = {0.0, 0.0};
+    M3 gx;
+    AH utp;  // U'_t(x - t) - h.c.
+    if (inside) {
+        gx = m3_load12(G, V, s3 + V3 * t0);
+        const int sp = s3 + V3 * ((t0 == 0) ? Lt - 1 : t0 - 1);
+        M3 w = m3_mul_mul_dag_rows(m3_load12(G, V, sp), m3_load12(Uo + (size_t)18 * V, V, sp), gx);
+        if (RU) m3_reunit(w);
+        utp = ah_of(w);
+    }
+    T2 *__restrict__ f = (T2 *)C.fields;
+    for (int t = t0; t < t0 + C.tch; ++t) {
+        const int s = s3 + V3 * t;
+        if (inside) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sg[k][tid] = gx.e[k];
+        }
+        __syncthreads();
+        AH D;
+        M3 gn;
+        double fsum = 0.0;
+        if (inside) {
+            D = utp;
+#pragma unroll
+            for (int mu = 0; mu < 3; ++mu) {
+                const size_t off = (size_t)mu * 6 * V;
+                M3 gf;
+                if (mu < 2 && sf[mu] >= 0) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) gf.e[k] = sg[k][sf[mu]];
+                    m3_row2(gf);
+                } else {
+                    gf = m3_load12(G, V, fwd3[mu] + V3 * t);
+                }
+                M3 w = m3_mul_mul_dag_rows(gx, m3_load12(Uo + off, V, s), gf);
+                if (RU) m3_reunit(w);
+                m3_store12(Un + off, V, s, w);
+                fsum += w.e[0].x + w.e[4].x + w.e[8].x;
+                const AH a = ah_of(w);
+                ah_acc(D, a, -1.0);
+                if (mu < 2) {
+                    sa[mu][0][tid] = a.o01.x;
+                    sa[mu][1][tid] = a.o01.y;
+                    sa[mu][2][tid] = a.o02.x;
+                    sa[mu][3][tid] = a.o02.y;
+                    sa[mu][4][tid] = a.o12.x;
+                    sa[mu][5][tid] = a.o12.y;
+                    sa[mu][6][tid] = a.d0;
+                    sa[mu][7][tid] = a.d1;
+                    sa[mu][8][tid] = a.d2;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            {
+                const int tn = (t + 1 == Lt) ? 0 : t + 1;
+                gn = m3_load12(G, V, s3 + V3 * tn);
+                const size_t off = (size_t)18 * V;
+                M3 w = m3_mul_mul_dag_rows(gx, m3_load12(Uo + off, V, s), gn);
+                if (RU) m3_reunit(w);
+                m3_store12(Un + off, V, s, w);
+                fsum += w.e[0].x + w.e[4].x + w.e[8].x;
+                utp = ah_of(w);
+                ah_acc(D, utp, -1.0);
+            }
+        }
+        __syncthreads();
+        if (inside) {
+#pragma unroll
+            for (int nu = 0; nu < 3; ++nu) {
+                AH a;
+                if (nu < 2 && sb[nu] >= 0) {
+                    const int o = sb[nu];
+                    a.o01 = make_double2(sa[nu][0][o], sa[nu][1][o]);
+                    a.o02 = make_double2(sa[nu][2][o], sa[nu][3][o]);
+                    a.o12 = make_double2(sa[nu][4][o], sa[nu][5][o]);
+                    a.d0 = sa[nu][6][o];
+                    a.d1 = sa[nu][7][o];
+                    a.d2 = sa[nu][8][o];
+                } else {
+                    const int sbk = back3[nu] + V3 * t;
+                    M3 wb = m3_mul_mul_dag_rows(m3_load12(G, V, sbk), m3_load12(Uo + (size_t)nu * 6 * V, V, sbk), gx);
+                    if (RU) m3_reunit(wb);
+                    a = ah_of(wb);
+                }
+                ah_acc(D, a, 1.0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // Delta = A - Tr(A)/3 with A = D - D^dag
+            const double tr3 = (D.d0 + D.d1 + D.d2) * (1.0 / 3.0);
+            const double e0 = D.d0 - tr3, e1 = D.d1 - tr3, e2 = D.d2 - tr3;
+            const double tsum = 2.0 * (cnorm2(D.o01) + cnorm2(D.o02) + cnorm2(D.o12)) + e0 * e0 + e1 * e1 + e2 * e2;
+            f[s].x = D.o01.x;
+            f[s].y = D.o01.y;
+            f[(size_t)V + s].x = D.o02.x;
+            f[(size_t)V + s].y = D.o02.y;
+            f[(size_t)2 * V + s].x = D.o12.x;
+            f[(size_t)2 * V + s].y = D.o12.y;
+            f[(size_t)3 * V + s].x = e0;
+            f[(size_t)3 * V + s].y = e1;
+            fs = dd_add(fs, dd{fsum, 0.0});
+            ts = dd_add(ts, dd{tsum, 0.0});
+            gx = gn;
+        }
+    }
+    block_sum2(fs, ts, red);
+    if (threadIdx.x == 0) {
+        double *p = C.partials + (size_t)lb * 4;
+        p[0] = fs.hi;
+        p[1] = fs.lo;
+        p[2] = ts.hi;
+        p[3] = ts.lo;
+    }
+}
+
 // K(p) = (alpha/2)(p2max/p2)/V for every momentum site, K(0) = 0 (Eq. 2; the
 // 1/V normalises the backward transform), with p2 = sum_mu 4 sin^2(pi n_mu /
 // L_mu); stored in the transform precision (an FP32 table holds the FP64
@@ -1621,6 +1789,18 @@ hipError_t launch_update_delta(const Launch &L)
 {
     const dim3 grid(L.total_march_blocks), blk(kSiteBlock);
     if (L.any_reunit) hipLaunchKernelGGL(k_mark_reunit, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.batch);
+    if (L.xchg) {
+        if (L.fp32) {
+            hipLaunchKernelGGL((k_update_delta_x<float2, false>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+            if (L.any_reunit)
+                hipLaunchKernelGGL((k_update_delta_x<float2, true>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+        } else {
+            hipLaunchKernelGGL((k_update_delta_x<double2, false>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+            if (L.any_reunit)
+                hipLaunchKernelGGL((k_update_delta_x<double2, true>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+        }
+        return hipGetLastError();
+    }
     if (L.fp32) {
         hipLaunchKernelGGL((k_update_delta<float2, false>), grid, blk, 0, L.stream, L.cfgs, L.batch);
         if (L.any_reunit) hipLaunchKernelGGL((k_update_delta<float2, true>), grid, blk, 0, L.stream, L.cfgs, L.batch);

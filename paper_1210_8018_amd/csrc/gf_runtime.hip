@@ -871,6 +871,7 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
     c->L.max_lds_elems = max_lds;
     c->L.fp32 = params[0].fft_prec;
     c->L.fused = getenv("GF_NOFUSE") ? 0 : 1;
+    c->L.xchg = getenv("GF_NOXCHG") ? 0 : 1;
     c->L.any_reunit = 0;
     for (int k = 0; k < ncfg; ++k) c->L.any_reunit |= params[k].reunit_every > 0;
     c->L.ncfg = ncfg;
