@@ -132,6 +132,19 @@ class BatchGaugeFixer:
         it, F, th, _ = gf.gf_fix_until_batch(self.ctx, self.n, theta_eps, max_iter, allow_maxiter)
         return it, F, th
 
+    @property
+    def fft_schedule(self) -> int:
+        return gf.gf_fft_schedule(self.ctx)
+
+    def set_timing(self, on: bool):
+        gf.gf_set_timing(self.ctx, on)
+
+    def kernel_times(self):
+        return gf.gf_kernel_times(self.ctx)
+
+    def reset_timing(self):
+        gf.gf_reset_timing(self.ctx)
+
     def close(self):
         if getattr(self, "ctx", None):
             gf.gf_destroy(self.ctx)

@@ -298,6 +298,32 @@ __device__ __forceinline__ void block_sum2(dd &a, dd &b, dd *lds)
 __device__ __forceinline__ bool is_p2(int v) { return (v & (v - 1)) == 0; }
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
+// Division by an invariant divisor 1 <= d <= 2^20 of numerators
+// 0 <= n < 2^31 by a multiply-high, an add and a shift (Granlund and
+// Montgomery, PLDI 1994): l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
+// n / d = (mulhi(m, n) + n) >> l. m is formed by one FP64 division: unless d
+// is a power of two (then m = 1 exactly) the exact quotient lies at least
+// 1/d from an integer, far more than the 2^-21 rounding error, so the
+// truncation is the exact floor.
+struct FastDiv {
+    uint32_t m;
+    int l;
+};
+
+__device__ __forceinline__ FastDiv fast_div(int d)
+{
+    FastDiv f;
+    f.l = (d <= 1) ? 0 : 32 - __clz(d - 1);
+    const double num = 4294967296.0 * (double)((1 << f.l) - d);
+    f.m = (uint32_t)(num / (double)d) + 1u;
+    return f;
+}
+
+__device__ __forceinline__ int fdiv(int n, FastDiv f)
+{
+    return (int)((__umulhi(f.m, (uint32_t)n) + (uint32_t)n) >> f.l);
+}
+
 // ---------------------------------------------------------------- mapping
 // Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8).
 // Renumber them so each XCD walks a contiguous range of tiles: neighbouring

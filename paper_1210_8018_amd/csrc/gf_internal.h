@@ -107,7 +107,9 @@ struct Launch {
     int total_zt_tiles;
     int xy_cap, zt_cap;            // 2D tile capacity variant (1024, 2048 or 4096 elements)
     int xy_th, zt_th;              // work-group size of the 2D passes (capacity / elements per work-item)
-    int xy_p2, zt_p2;              // every configuration has power-of-two extents in that pass
+    int xy_p2, zt_p2;              // some configuration has power-of-two extents in that pass
+    int xy_gen, zt_gen;            // some configuration has not
+    int ax_p2[4], ax_gen[4];       // same for the 1D passes of each axis
     int xy_tw2, xy_tw_total;       // LDS twiddle layout of the xy pass: y table offset, entries
     int zt_tw2, zt_tw_total;       // same for the zt pass
     int max_lds_elems;    // 1D passes: largest P * L

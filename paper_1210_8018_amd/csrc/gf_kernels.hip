@@ -339,16 +339,17 @@ __device__ __forceinline__ void stage(const T2 *__restrict__ src, T2 *__restrict
     const int nb = L / R;
     const int total = P * nb;
     const int tstep = L / (Ns * R);
+    const FastDiv fP = fast_div(P), fnb = fast_div(nb), fNs = fast_div(Ns);
     for (int b = threadIdx.x; b < total; b += blockDim.x) {
         int k, j;
         if (k_fast) {
-            k = b % P;
-            j = b / P;
+            j = fdiv(b, fP);
+            k = b - j * P;
         } else {
-            j = b % nb;
-            k = b / nb;
+            k = fdiv(b, fnb);
+            j = b - k * nb;
         }
-        const int kk = j % Ns;
+        const int kk = j - fdiv(j, fNs) * Ns;
         T2 a[R];
 #pragma unroll
         for (int m = 0; m < R; ++m) a[m] = src[k * ks + (j + m * nb) * ls];
@@ -394,6 +395,76 @@ __device__ void fft_pencils(T2 *&src, T2 *&dst, const T2 *tw, const FftAxis &A, 
     }
 }
 
+// stage for a power-of-two pencil length L = 2^lL (and, with k_fast, a
+// power-of-two pencil count P = 2^lP): the same butterflies with shifts and
+// masks for the index arithmetic. k_fast: element l of pencil k at k + l P;
+// otherwise at k L + l.
+template <int R, typename T2>
+__device__ __forceinline__ void stage_p2(const T2 *__restrict__ src, T2 *__restrict__ dst, const T2 *__restrict__ tw,
+                                         int lL, int P, int lP, int lNs, int sign, bool k_fast)
+{
+    static_assert(R == 2 || R == 4 || R == 8, "power-of-two radix");
+    constexpr int lR = (R == 2) ? 1 : (R == 4) ? 2 : 3;
+    const int lnb = lL - lR, nb = 1 << lnb;
+    const int total = P << lnb;
+    const int ltstep = lL - lNs - lR;
+    for (int b = threadIdx.x; b < total; b += blockDim.x) {
+        int k, j;
+        if (k_fast) {
+            k = b & (P - 1);
+            j = b >> lP;
+        } else {
+            j = b & (nb - 1);
+            k = b >> lnb;
+        }
+        const int kk = j & ((1 << lNs) - 1);
+        T2 a[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int l = j + m * nb;
+            a[m] = src[k_fast ? k + (l << lP) : (k << lL) + l];
+        }
+        const int tb = kk << ltstep;
+#pragma unroll
+        for (int m = 1; m < R; ++m) {
+            T2 w = tw[m * tb];
+            if (sign > 0) w.y = -w.y;
+            a[m] = t_mul(a[m], w);
+        }
+        if constexpr (R == 2)
+            dft2(a);
+        else if constexpr (R == 4)
+            dft4(a, sign);
+        else
+            dft8(a, sign);
+        const int ob = ((j - kk) << lR) + kk;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int l = ob + (q << lNs);
+            dst[k_fast ? k + (l << lP) : (k << lL) + l] = a[q];
+        }
+    }
+}
+
+template <typename T2>
+__device__ void fft_pencils_p2(T2 *&src, T2 *&dst, const T2 *tw, const FftAxis &A, int sign, bool k_fast)
+{
+    const int lL = ilog2(A.L), lP = k_fast ? ilog2(A.P) : 0;
+    int lNs = 0;
+    for (int st = 0; st < A.nstage; ++st) {
+        const int r = A.radix[st];
+        switch (r) {
+        case 2: stage_p2<2>(src, dst, tw, lL, A.P, lP, lNs, sign, k_fast); lNs += 1; break;
+        case 4: stage_p2<4>(src, dst, tw, lL, A.P, lP, lNs, sign, k_fast); lNs += 2; break;
+        default: stage_p2<8>(src, dst, tw, lL, A.P, lP, lNs, sign, k_fast); lNs += 3; break;
+        }
+        __syncthreads();
+        T2 *t = src;
+        src = dst;
+        dst = t;
+    }
+}
+
 // Global -> LDS copies of a tile. The trip count is bounded at compile time
 // and the loop fully unrolled, so the global loads of a work-item can all be
 // issued before the first LDS store (the two address spaces do not alias).
@@ -422,10 +493,11 @@ __device__ __forceinline__ void tile_load_padded(T2 *buf, const T2 *__restrict__
         }
         return;
     }
+    const FastDiv fr = fast_div(rowlen);
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int i = threadIdx.x + k * TH;
-        if (i < n) buf[i + pad * (i / rowlen)] = g[i];
+        if (i < n) buf[i + pad * fdiv(i, fr)] = g[i];
     }
 }
 
@@ -442,10 +514,11 @@ __device__ __forceinline__ void tile_store_padded(T2 *__restrict__ g, const T2 *
         }
         return;
     }
+    const FastDiv fr = fast_div(rowlen);
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int i = threadIdx.x + k * TH;
-        if (i < n) g[i] = buf[i + pad * (i / rowlen)];
+        if (i < n) g[i] = buf[i + pad * fdiv(i, fr)];
     }
 }
 
@@ -478,10 +551,10 @@ __device__ __forceinline__ void tile_load_rows(T2 *buf, const T2 *__restrict__ g
 // As tile_load_rows / tile_store_rows, with `pad` LDS elements after every
 // `rpp` rows (row r at LDS r * P + pad * (r / rpp)).
 // LDS index of row r, element p, of a row tile with `pad` elements after
-// every 2^lrpp rows (lrpp < 0: after every rpp rows).
-__device__ __forceinline__ int rows_lds(int r, int p, int lp, int rpp, int lrpp, int pad)
+// every 2^lrpp rows (lrpp < 0: after every rpp rows, frpp = fast_div(rpp)).
+__device__ __forceinline__ int rows_lds(int r, int p, int lp, FastDiv frpp, int lrpp, int pad)
 {
-    return (r << lp) + p + pad * (lrpp >= 0 ? (r >> lrpp) : (r / rpp));
+    return (r << lp) + p + pad * (lrpp >= 0 ? (r >> lrpp) : fdiv(r, frpp));
 }
 
 template <typename T2, int CAP, int TH>
@@ -490,11 +563,12 @@ __device__ __forceinline__ void tile_load_rows_padded(T2 *buf, const T2 *__restr
 {
     constexpr int NL = (CAP + TH - 1) / TH;
     const int lp = ilog2(P), lrpp = is_p2(rpp) ? ilog2(rpp) : -1;
+    const FastDiv frpp = fast_div(rpp);
     const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int r = r0 + k * dr;
-        if (r < rows) buf[rows_lds(r, p, lp, rpp, lrpp, pad)] = g[(size_t)r * rs + p];
+        if (r < rows) buf[rows_lds(r, p, lp, frpp, lrpp, pad)] = g[(size_t)r * rs + p];
     }
 }
 
@@ -504,11 +578,12 @@ __device__ __forceinline__ void tile_store_rows_padded(T2 *__restrict__ g, const
 {
     constexpr int NL = (CAP + TH - 1) / TH;
     const int lp = ilog2(P), lrpp = is_p2(rpp) ? ilog2(rpp) : -1;
+    const FastDiv frpp = fast_div(rpp);
     const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int r = r0 + k * dr;
-        if (r < rows) g[(size_t)r * rs + p] = buf[rows_lds(r, p, lp, rpp, lrpp, pad)];
+        if (r < rows) g[(size_t)r * rs + p] = buf[rows_lds(r, p, lp, frpp, lrpp, pad)];
     }
 }
 
@@ -529,7 +604,7 @@ __device__ __forceinline__ void tile_store_rows(T2 *__restrict__ g, const T2 *bu
 // pass with the given sign. mode 1 (last axis only): forward transform,
 // multiplication by K(p) = (alpha/2)(p2max/p2)/V with K(0) = 0 (Eq. 2; the
 // 1/V is the normalisation of the backward transform), backward transform.
-template <typename T2>
+template <typename T2, bool P2>
 __global__ __launch_bounds__(kFftThreads) void k_fft(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
                                                      int axis, int sign, int mode, void *fields_override,
                                                      int respect_done, int lds_elems)
@@ -542,6 +617,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(const Cfg *__restrict__ cfg
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     const FftAxis &A = C.ax[axis];
+    if (P2 != is_p2(A.L)) return;  // the other instance takes it
     const int t = tile - B->off_fft[axis][c];
     const int L = A.L, P = A.P, n = P * L;
     T2 *buf0 = (T2 *)smem;
@@ -564,7 +640,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(const Cfg *__restrict__ cfg
     }
     __syncthreads();
     T2 *src = buf0, *dst = buf1;
-    fft_pencils(src, dst, tw, A, ks, ls, mode == 1 ? -1 : sign, k_fast);
+    if constexpr (P2)
+        fft_pencils_p2(src, dst, tw, A, mode == 1 ? -1 : sign, k_fast);
+    else
+        fft_pencils(src, dst, tw, A, ks, ls, mode == 1 ? -1 : sign, k_fast);
     if (mode == 1) {
         // element (l, k) of the tile is momentum site gbase + l S + k
         const T *__restrict__ Km = (const T *)C.kmom + gbase;
@@ -578,7 +657,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(const Cfg *__restrict__ cfg
             src[idx] = v;
         }
         __syncthreads();
-        fft_pencils(src, dst, tw, A, ks, ls, +1, k_fast);
+        if constexpr (P2)
+            fft_pencils_p2(src, dst, tw, A, +1, k_fast);
+        else
+            fft_pencils(src, dst, tw, A, ks, ls, +1, k_fast);
     }
     if (!k_fast)
         tile_store_contig<T2, 1024, kFftThreads>(g + gbase, src, n);
@@ -600,6 +682,7 @@ __device__ __forceinline__ void stage_ip(T2 *buf, const T2 *__restrict__ tw, int
     const int nb = L / R;
     const int total = npen * nb;
     const int tstep = L / (Ns * R);
+    const FastDiv fnp = fast_div(npen), fnb = fast_div(nb), fm1 = fast_div(m1), fNs = fast_div(Ns);
     T2 v[MAXB][R];
     int ob[MAXB];
 #pragma unroll
@@ -608,14 +691,15 @@ __device__ __forceinline__ void stage_ip(T2 *buf, const T2 *__restrict__ tw, int
         if (b < total) {
             int k, j;
             if (k_fast) {
-                k = b % npen;
-                j = b / npen;
+                j = fdiv(b, fnp);
+                k = b - j * npen;
             } else {
-                j = b % nb;
-                k = b / nb;
+                k = fdiv(b, fnb);
+                j = b - k * nb;
             }
-            const int base = (k % m1) * a1 + (k / m1) * a2;
-            const int kk = j % Ns;
+            const int q1 = fdiv(k, fm1);
+            const int base = (k - q1 * m1) * a1 + q1 * a2;
+            const int kk = j - fdiv(j, fNs) * Ns;
 #pragma unroll
             for (int m = 0; m < R; ++m) v[i][m] = buf[base + (j + m * nb) * ls];
 #pragma unroll
@@ -773,7 +857,7 @@ __device__ __forceinline__ bool zt_is_p2(const Cfg &C) { return is_p2(C.dims[2])
 __device__ __forceinline__ int xy_lds(const Cfg &C, int i)
 {
     const int Lx = C.dims[0];
-    return i + C.xyPad * (is_p2(Lx) ? (i >> ilog2(Lx)) : (i / Lx));
+    return i + C.xyPad * (is_p2(Lx) ? (i >> ilog2(Lx)) : fdiv(i, fast_div(Lx)));
 }
 
 // Pass over (x, y): tile = Q consecutive xy-planes of one field. LDS: CAP
@@ -789,7 +873,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int c = find_cfg(B->off_xy, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
-    if (P2 && !xy_is_p2(C)) return;
+    if (P2 != xy_is_p2(C)) return;  // the other instance takes it
     const int t = tile - B->off_xy[c];
     const int n = C.xyQ * C.V2;
     T2 *buf = (T2 *)smem;
@@ -820,7 +904,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int c = find_cfg(B->off_zt, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
-    if (P2 && !zt_is_p2(C)) return;
+    if (P2 != zt_is_p2(C)) return;  // the other instance takes it
     const int t = tile - B->off_zt[c];
     const int P = C.ztP, Lz = C.dims[2], Lt = C.dims[3], V2 = C.V2;
     const int n = P * Lz * Lt;
@@ -865,7 +949,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
         for (int k = 0; k < NL; ++k) {
             const int r = r0 + k * dr;
             if (r < rows) {
-                const int li = rows_lds(r, p, lp, Lz, lz, C.ztPad);
+                const int li = rows_lds(r, p, lp, fast_div(Lz), lz, C.ztPad);
                 T2 v = buf[li];
                 v.x *= kreg[k];
                 v.y *= kreg[k];
@@ -952,7 +1036,7 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
     const int c = find_cfg(B->off_xy, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
-    if (P2 && !xy_is_p2(C)) return;
+    if (P2 != xy_is_p2(C)) return;  // the other instance takes it
     const int t = tile - B->off_xy[c];
     const int n = C.xyQ * C.V2;
     const size_t site0 = (size_t)t * n;
@@ -1648,19 +1732,27 @@ hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *
                            int respect_done)
 {
     const dim3 grid(L.total_fft_tiles[axis], nfields);
+    // power-of-two and general instances, as for the 2D passes
+    const size_t sh32 = (size_t)(2 * L.max_lds_elems + 256) * sizeof(float2);
+    const size_t sh64 = (size_t)(2 * L.max_lds_elems + 256) * sizeof(double2);
     if (L.fp32) {
-        const size_t sh = (size_t)(2 * L.max_lds_elems + 256) * sizeof(float2);
-        hipLaunchKernelGGL(k_fft<float2>, grid, dim3(kFftThreads), sh, L.stream, L.cfgs, L.batch, axis, sign, mode,
-                           fields_override, respect_done, L.max_lds_elems);
+        if (L.ax_p2[axis])
+            hipLaunchKernelGGL((k_fft<float2, true>), grid, dim3(kFftThreads), sh32, L.stream, L.cfgs, L.batch, axis,
+                               sign, mode, fields_override, respect_done, L.max_lds_elems);
+        if (L.ax_gen[axis])
+            hipLaunchKernelGGL((k_fft<float2, false>), grid, dim3(kFftThreads), sh32, L.stream, L.cfgs, L.batch, axis,
+                               sign, mode, fields_override, respect_done, L.max_lds_elems);
     } else {
-        const size_t sh = (size_t)(2 * L.max_lds_elems + 256) * sizeof(double2);
-        hipLaunchKernelGGL(k_fft<double2>, grid, dim3(kFftThreads), sh, L.stream, L.cfgs, L.batch, axis, sign, mode,
-                           fields_override, respect_done, L.max_lds_elems);
+        if (L.ax_p2[axis])
+            hipLaunchKernelGGL((k_fft<double2, true>), grid, dim3(kFftThreads), sh64, L.stream, L.cfgs, L.batch, axis,
+                               sign, mode, fields_override, respect_done, L.max_lds_elems);
+        if (L.ax_gen[axis])
+            hipLaunchKernelGGL((k_fft<double2, false>), grid, dim3(kFftThreads), sh64, L.stream, L.cfgs, L.batch,
+                               axis, sign, mode, fields_override, respect_done, L.max_lds_elems);
     }
     return hipGetLastError();
 }
 
-// 2D pass variants by tile capacity: (elements, work-items).
 // (tile capacity, work-group size) instances of the 2D passes: 4 or 8
 // elements per work-item.
 #define GF_2D_SIZES(X, P2) \
@@ -1675,52 +1767,55 @@ static size_t lds2d(int cap, int tw2, int tw_total)
     return (size_t)(cap + cap / 8 + tw_total) * sizeof(T2);
 }
 
+// Each 2D pass launches the power-of-two instance if some configuration has
+// power-of-two extents in that pass, and the general one if some has not;
+// each instance leaves the other's configurations at once.
 template <typename T2>
 static hipError_t run_xy(const Launch &L, dim3 grid, int sign, void *fo, int rd)
 {
     const size_t sh = lds2d<T2>(L.xy_cap, L.xy_tw2, L.xy_tw_total);
-    const bool p2 = L.xy_p2 != 0;
+    int launched = 0;
 #define X(C_, T_, P2_)                                                                                            \
-    if (L.xy_cap == C_ && L.xy_th == T_ && p2 == P2_) {                                                           \
+    if (L.xy_cap == C_ && L.xy_th == T_ && (P2_ ? L.xy_p2 : L.xy_gen)) {                                          \
         hipLaunchKernelGGL((k_fft_xy<T2, C_, T_, P2_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, sign, fo, rd, \
                            L.xy_tw2);                                                                             \
-        return hipGetLastError();                                                                                 \
+        ++launched;                                                                                               \
     }
     GF_2D_VARIANTS(X)
 #undef X
-    return hipErrorInvalidValue;
+    return launched ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 template <typename T2>
 static hipError_t run_zt(const Launch &L, dim3 grid, int mode, int sign, void *fo, int rd)
 {
     const size_t sh = lds2d<T2>(L.zt_cap, L.zt_tw2, L.zt_tw_total);
-    const bool p2 = L.zt_p2 != 0;
+    int launched = 0;
 #define X(C_, T_, P2_)                                                                                            \
-    if (L.zt_cap == C_ && L.zt_th == T_ && p2 == P2_) {                                                           \
+    if (L.zt_cap == C_ && L.zt_th == T_ && (P2_ ? L.zt_p2 : L.zt_gen)) {                                          \
         hipLaunchKernelGGL((k_fft_zt<T2, C_, T_, P2_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, mode, sign,   \
                            fo, rd, L.zt_tw2);                                                                     \
-        return hipGetLastError();                                                                                 \
+        ++launched;                                                                                               \
     }
     GF_2D_VARIANTS(X)
 #undef X
-    return hipErrorInvalidValue;
+    return launched ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 template <typename T2>
 static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
 {
     const size_t sh = lds2d<T2>(L.xy_cap, L.xy_tw2, L.xy_tw_total);
-    const bool p2 = L.xy_p2 != 0;
+    int launched = 0;
 #define X(C_, T_, P2_)                                                                                            \
-    if (L.xy_cap == C_ && L.xy_th == T_ && p2 == P2_) {                                                           \
+    if (L.xy_cap == C_ && L.xy_th == T_ && (P2_ ? L.xy_p2 : L.xy_gen)) {                                          \
         hipLaunchKernelGGL((k_fft_xy_inv_gauge<T2, C_, T_, P2_>), dim3(L.total_xy_tiles), dim3(T_), sh, L.stream,    \
                            L.cfgs, L.batch, rd, go, L.xy_tw2, L.fused);                                           \
-        return hipGetLastError();                                                                                 \
+        ++launched;                                                                                               \
     }
     GF_2D_VARIANTS(X)
 #undef X
-    return hipErrorInvalidValue;
+    return launched ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done)

@@ -107,6 +107,17 @@ int plan_tchunk(const int dims[4], int nb3)
     return 1;
 }
 
+// In a batch every configuration's marching blocks take about the same
+// number of t-slices (the largest divisor of Lt up to GF_TCHUNK_BATCH,
+// default 4), so blocks carry equal work whatever lattice they belong to and
+// the XCDs, each of which walks a contiguous range of blocks, stay balanced.
+int plan_tchunk_batch(const int dims[4])
+{
+    const char *env = getenv("GF_TCHUNK_BATCH");
+    const int T = env && atoi(env) >= 1 ? atoi(env) : 4;
+    return largest_divisor_at_most(dims[3], T);
+}
+
 // xy tiles: Q consecutive xy-planes, Q * Lx * Ly <= target elements.
 int plan_xyQ(const int dims[4], int target)
 {
@@ -567,14 +578,15 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
     for (int k = 0; k < c->ncfg; ++k) all[k] = k;
     fill_map(c, all, c->bmap, c->L);
     int xy_max = 0, zt_max = 0, mx = 0, my = 0, mz = 0, mt = 0;
-    bool xy_p2 = true, zt_p2 = true;
+    bool xy_p2 = false, zt_p2 = false, xy_gen = false, zt_gen = false;
     auto p2 = [](int v) { return (v & (v - 1)) == 0; };
     for (int k = 0; k < c->ncfg; ++k) {
         const Cfg &C = c->cfg[k];
         if (C.nxy) xy_max = std::max(xy_max, C.xyQ * C.V2);
         if (C.nzt) zt_max = std::max(zt_max, C.ztP * C.dims[2] * C.dims[3]);
-        xy_p2 = xy_p2 && p2(C.dims[0]) && p2(C.dims[1]) && p2(C.xyQ);
-        zt_p2 = zt_p2 && p2(C.dims[2]) && p2(C.dims[3]);
+        const bool xp = p2(C.dims[0]) && p2(C.dims[1]) && p2(C.xyQ), zp = p2(C.dims[2]) && p2(C.dims[3]);
+        if (C.nxy) (xp ? xy_p2 : xy_gen) = true;
+        if (C.nzt) (zp ? zt_p2 : zt_gen) = true;
         mx = std::max(mx, C.dims[0]);
         my = std::max(my, C.dims[1]);
         mz = std::max(mz, C.dims[2]);
@@ -587,6 +599,8 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
     c->L.zt_th = c->L.zt_cap / tl.zt_ept;
     c->L.xy_p2 = xy_p2;
     c->L.zt_p2 = zt_p2;
+    c->L.xy_gen = xy_gen;
+    c->L.zt_gen = zt_gen;
     c->L.xy_tw2 = mx;
     c->L.xy_tw_total = mx + my;
     c->L.zt_tw2 = mz;
@@ -827,7 +841,7 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         C.V3 = C.V2 * p.dims[2];
         C.nblk_site = (C.V + kSiteBlock - 1) / kSiteBlock;
         C.nb3 = plan_tile(p.dims, C.tile, C.ntile);
-        C.tch = plan_tchunk(p.dims, C.nb3);
+        C.tch = (ncfg > 1) ? plan_tchunk_batch(p.dims) : plan_tchunk(p.dims, C.nb3);
         C.nblk_march = C.nb3 * (p.dims[3] / C.tch);
         C.U = (double2 *)links[k];
         C.U12[0] = (double2 *)(c->ws + l.links12a);
@@ -869,6 +883,13 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         fill_map(c, all, c->bmap, c->L);
     }
     c->L.max_lds_elems = max_lds;
+    for (int mu = 0; mu < 4; ++mu) {
+        c->L.ax_p2[mu] = c->L.ax_gen[mu] = 0;
+        for (int k = 0; k < ncfg; ++k) {
+            const int Lm = params[k].dims[mu];
+            ((Lm & (Lm - 1)) == 0 ? c->L.ax_p2[mu] : c->L.ax_gen[mu]) = 1;
+        }
+    }
     c->L.fp32 = params[0].fft_prec;
     c->L.fused = getenv("GF_NOFUSE") ? 0 : 1;
     c->L.xchg = getenv("GF_NOXCHG") ? 0 : 1;

@@ -205,6 +205,19 @@ def test_box_tiles_match_oracle(monkeypatch, dims, tile, fuse):
     compare_trajectory(Fh, Th, Fr, Tr, int(np.prod(dims)))
 
 
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (12, 8, 6, 4)])
+def test_fused_without_exchange_matches_oracle(monkeypatch, dims):
+    """The fused pass that recomputes every backward link (GF_NOXCHG)."""
+    monkeypatch.setenv("GF_NOXCHG", "1")
+    U = random_links(dims, 0.3, 1)
+    n_ref, _, Fr, Tr = oracle.fix(dims, U, alpha=ALPHA, eps=EPS, max_iter=5000)
+    fx = GaugeFixer(dev(U))
+    it, F, th = fx.fix_until(EPS, 5000)
+    Fh, Th = fx.history()
+    assert it == n_ref
+    compare_trajectory(Fh, Th, Fr, Tr, int(np.prod(dims)))
+
+
 def test_step_equals_fix_prefix():
     dims = (8, 8, 8, 8)
     U = random_links(dims, 0.3, 1)
@@ -311,8 +324,15 @@ def test_invalid_shapes_rejected():
 
 
 @pytest.mark.parametrize("prec,sched", [(0, 1), (0, 3), (1, 2), (1, 3)])
-def test_batch_equals_single_runs(prec, sched):
-    """Each configuration of a batch evolves bitwise as in its own context."""
+def test_batch_equals_single_runs(monkeypatch, prec, sched):
+    """Each configuration of a batch evolves bitwise as in its own context.
+
+    Bitwise equality needs the same decomposition into blocks (the t-slices a
+    marching block walks set where the carried U'_t is recomputed and how the
+    block sums group), so both contexts are given the same t-chunk.
+    """
+    monkeypatch.setenv("GF_TCHUNK", "2")
+    monkeypatch.setenv("GF_TCHUNK_BATCH", "2")
     cases = [((8, 8, 8, 8), 0.3, 1), ((6, 4, 8, 4), 0.25, 2), ((12, 8, 6, 4), 0.45, 3), ((4, 4, 4, 4), 0.2, 4)]
     Us = [random_links(d, e, s) for d, e, s in cases]
     single = []
