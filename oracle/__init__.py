@@ -50,6 +50,8 @@ def lib():
             "or_apply_gauge": (None, [P, P, P]),
             "or_reunit_links": (None, [P, P]),
             "or_fix": (I64, [P, P, D, D, I64, ctypes.c_int, P, P, I64]),
+            "or_fix_f32_storage": (I64, [P, P, D, D, I64, ctypes.c_int, P, P, I64]),
+            "or_store_f32": (None, [P, P, ctypes.c_int]),
             "or_plaquette": (D, [P, P]),
             "or_polyakov": (None, [P, P, P, P]),
             "or_eigh3": (None, [P, P, P]),
@@ -163,18 +165,31 @@ def reunit_links(dims, U):
     return U
 
 
-def fix(dims, U, alpha=0.08, eps=1e-15, max_iter=100000, reunit_every=0, hist_cap=None):
-    """Alg. 1 on a copy of U. Returns (iters, U_final, F_hist, theta_hist)."""
+def fix(dims, U, alpha=0.08, eps=1e-15, max_iter=100000, reunit_every=0, hist_cap=None, f32_storage=False):
+    """Alg. 1 on a copy of U. Returns (iters, U_final, F_hist, theta_hist).
+
+    f32_storage: links and g kept in single-precision 12-real storage
+    (or_fix_f32_storage); U_final is then the stored links.
+    """
     U = np.array(U, dtype=np.complex128, copy=True)
     d = _dims(dims)
     cap = int(max_iter) + 1 if hist_cap is None else int(hist_cap)
     cap = min(cap, 10_000_000)
     Fh = np.zeros(cap, dtype=np.float64)
     Th = np.zeros(cap, dtype=np.float64)
-    n = lib().or_fix(_p(d), _p(U), float(alpha), float(eps), int(max_iter), int(reunit_every),
-                     _p(Fh), _p(Th), cap)
+    f = lib().or_fix_f32_storage if f32_storage else lib().or_fix
+    n = f(_p(d), _p(U), float(alpha), float(eps), int(max_iter), int(reunit_every), _p(Fh), _p(Th), cap)
     k = min(n + 1, cap)
     return int(n), U, Fh[:k].copy(), Th[:k].copy()
+
+
+def store_f32(dims, M):
+    """Single-precision 12-real storage (or_store_f32) of a copy of the matrix fields M [n][3][3][V]."""
+    M = np.array(M, dtype=np.complex128, copy=True)
+    d = _dims(dims)
+    n = M.size // (9 * int(np.prod(dims)))
+    lib().or_store_f32(_p(d), _p(M), n)
+    return M
 
 
 def plaquette(dims, U):

@@ -402,6 +402,33 @@ void or_reunit_links(const int L[4], cplx *U)
 }
 
 /*
+ * Single-precision storage of the 12-real representation of an SU(3) matrix
+ * (section 2.2; the paper's single-precision mode stores its links this
+ * way): the real and imaginary parts of rows 0 and 1 are rounded to the
+ * nearest binary32 value, row 2 is rebuilt in FP64 as conj(r0 x r1).
+ * Applied in place to nmat matrix fields [nmat][3][3][V].
+ */
+void or_store_f32(const int L[4], cplx *M, int nmat)
+{
+    const int64_t V = vol(L);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < V; ++s)
+        for (int mu = 0; mu < nmat; ++mu) {
+            mat3 m;
+            get_link(M, V, mu, s, m);
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    const float re = (float)creal(m[i][j]), im = (float)cimag(m[i][j]);
+                    m[i][j] = (double)re + I * (double)im;
+                }
+            m[2][0] = conj(m[0][1] * m[1][2] - m[0][2] * m[1][1]);
+            m[2][1] = conj(m[0][2] * m[1][0] - m[0][0] * m[1][2]);
+            m[2][2] = conj(m[0][0] * m[1][1] - m[0][1] * m[1][0]);
+            put_link(M, V, mu, s, m);
+        }
+}
+
+/*
  * Alg. 1. Computes Delta, F, theta; then while theta > eps and fewer than
  * max_iter updates were made: gauge vector from Delta, link update,
  * (optional link reunitarisation when reunit_every > 0 and the update count
@@ -410,6 +437,52 @@ void or_reunit_links(const int L[4], cplx *U)
  * after k updates (k = 0: the input). Returns the number of updates made.
  * eps < 0 runs exactly max_iter updates.
  */
+/*
+ * Alg. 1 with single-precision storage of links and g (or_store_f32): the
+ * arithmetic stays FP64, every g is stored before it is applied, every new
+ * link is stored after its update (and projection), and Delta, F, theta of an
+ * iteration are those of the new links before their storage. The starting
+ * Delta is that of the input links, which are then stored. On return U holds
+ * the stored links. Histories and return value as or_fix.
+ */
+int64_t or_fix_f32_storage(const int L[4], cplx *U, double alpha, double eps, int64_t max_iter, int reunit_every,
+                           double *F_hist, double *theta_hist, int64_t hist_cap)
+{
+    const int64_t V = vol(L);
+    cplx *Delta = malloc(sizeof(cplx) * 9 * V);
+    cplx *g = malloc(sizeof(cplx) * 9 * V);
+    cplx *Ux = malloc(sizeof(cplx) * 36 * V); /* new links before storage */
+    double F, theta;
+    memcpy(Ux, U, sizeof(cplx) * 36 * V);
+    or_measure(L, Ux, &F, &theta);
+    or_store_f32(L, U, 4);
+    if (hist_cap > 0) {
+        F_hist[0] = F;
+        theta_hist[0] = theta;
+    }
+    int64_t it = 0;
+    while (!(theta <= eps) && it < max_iter) {
+        or_delta(L, Ux, Delta);
+        or_gauge_from_delta(L, Delta, alpha, g);
+        or_store_f32(L, g, 1);
+        memcpy(Ux, U, sizeof(cplx) * 36 * V);
+        or_apply_gauge(L, Ux, g);
+        ++it;
+        if (reunit_every > 0 && it % reunit_every == 0) or_reunit_links(L, Ux);
+        or_measure(L, Ux, &F, &theta);
+        memcpy(U, Ux, sizeof(cplx) * 36 * V);
+        or_store_f32(L, U, 4);
+        if (it < hist_cap) {
+            F_hist[it] = F;
+            theta_hist[it] = theta;
+        }
+    }
+    free(Delta);
+    free(g);
+    free(Ux);
+    return it;
+}
+
 int64_t or_fix(const int L[4], cplx *U, double alpha, double eps, int64_t max_iter, int reunit_every,
                double *F_hist, double *theta_hist, int64_t hist_cap)
 {

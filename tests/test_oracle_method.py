@@ -234,3 +234,57 @@ def test_link_reunitarisation_option(orc):
     assert abs(F0[-1] - F1[-1]) < 1e-13
     e, d = unitarity_error(links_aos(U1))
     assert e < 1e-14 and d < 1e-14
+
+
+def test_single_precision_storage_map(orc):
+    """The 12-real single-precision storage (section 2.2): rows 0, 1 exactly
+    binary32, row 2 their conjugate cross product, idempotent, special
+    unitary to the binary32 rounding, within a few binary32 ulps of the input."""
+    dims = (4, 4, 4, 2)
+    U = random_links(dims, 0.7, 31)
+    S = orc.store_f32(dims, U)
+    S2 = orc.store_f32(dims, S)
+    assert np.array_equal(S, S2)
+    A = links_aos(S)
+    rows = A[..., :2, :]
+    assert np.array_equal(rows.real.astype(np.float32).astype(np.float64), rows.real)
+    assert np.array_equal(rows.imag.astype(np.float32).astype(np.float64), rows.imag)
+    r2 = np.conj(np.cross(A[..., 0, :], A[..., 1, :]))
+    assert np.max(np.abs(r2 - A[..., 2, :])) < 1e-15
+    e, d = unitarity_error(A)
+    assert e < 4e-7 and d < 4e-7
+    assert np.max(np.abs(S - U)) < 8 * 2.0**-24
+    assert np.max(np.abs(S - U)) > 0  # the storage does round
+
+
+def test_single_precision_storage_iteration(orc):
+    """Alg. 1 with single-precision storage tracks the FP64 iteration to the
+    storage rounding and reaches theta <= 1e-10; an FP64 refinement started
+    from its stored links reaches theta <= 1e-15. Storage rounding is not a
+    gauge transformation: it moves the configuration off its gauge orbit by
+    ~1e-7 (the plaquette shifts by that much), so the refined F agrees with
+    the FP64 run's to that level, not to 1e-12."""
+    dims = (8, 8, 8, 8)
+    U = random_links(dims, 0.3, 1)
+    n64, U64, F64, T64 = orc.fix(dims, U, eps=EPS)
+    n32, U32, F32, T32 = orc.fix(dims, U, eps=1e-10, max_iter=200, f32_storage=True)
+    assert T32[-1] <= 1e-10 and n32 <= n64
+    k = min(len(T32), len(T64))
+    big = T64[:k] > 1e-8
+    assert np.max(np.abs(T32[:k][big] - T64[:k][big]) / T64[:k][big]) < 1e-4
+    assert np.max(np.abs(F32[:k] - F64[:k])) < 1e-6
+    # the stored links stay special unitary up to the accumulated storage
+    # rounding (about 1e-7 per update, a random walk over the updates)
+    e, d = unitarity_error(links_aos(U32))
+    assert e < 1e-7 * 4 * np.sqrt(n32) and d < 1e-7 * 4 * np.sqrt(n32)
+    # refinement in FP64 from the stored links
+    n2, U2, F2, T2 = orc.fix(dims, U32, eps=EPS)
+    assert T2[-1] <= EPS
+    assert abs(F2[-1] - F64[-1]) < 1e-6
+    assert abs(orc.plaquette(dims, U2) - orc.plaquette(dims, U)) < 1e-6
+    assert abs(orc.plaquette(dims, U2) - orc.plaquette(dims, U32)) < 1e-13  # refinement is a gauge transformation
+    assert n32 + n2 <= n64 + 10
+    # with unit links nothing changes and nothing is rounded away
+    one = unit_links(dims)
+    n1, U1, _, T1 = orc.fix(dims, one, eps=EPS, f32_storage=True)
+    assert n1 == 0 and np.array_equal(U1, one)
