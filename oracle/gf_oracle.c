@@ -408,7 +408,7 @@ void or_reunit_links(const int L[4], cplx *U)
  * nearest binary32 value, row 2 is rebuilt in FP64 as conj(r0 x r1).
  * Applied in place to nmat matrix fields [nmat][3][3][V].
  */
-void or_store_f32(const int L[4], cplx *M, int nmat)
+static void two_row_field(const int L[4], cplx *M, int nmat, int round_f32)
 {
     const int64_t V = vol(L);
 #pragma omp parallel for schedule(static)
@@ -416,17 +416,20 @@ void or_store_f32(const int L[4], cplx *M, int nmat)
         for (int mu = 0; mu < nmat; ++mu) {
             mat3 m;
             get_link(M, V, mu, s, m);
-            for (int i = 0; i < 2; ++i)
-                for (int j = 0; j < 3; ++j) {
-                    const float re = (float)creal(m[i][j]), im = (float)cimag(m[i][j]);
-                    m[i][j] = (double)re + I * (double)im;
-                }
+            if (round_f32)
+                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        const float re = (float)creal(m[i][j]), im = (float)cimag(m[i][j]);
+                        m[i][j] = (double)re + I * (double)im;
+                    }
             m[2][0] = conj(m[0][1] * m[1][2] - m[0][2] * m[1][1]);
             m[2][1] = conj(m[0][2] * m[1][0] - m[0][0] * m[1][2]);
             m[2][2] = conj(m[0][0] * m[1][1] - m[0][1] * m[1][0]);
             put_link(M, V, mu, s, m);
         }
 }
+
+void or_store_f32(const int L[4], cplx *M, int nmat) { two_row_field(L, M, nmat, 1); }
 
 /*
  * Alg. 1. Computes Delta, F, theta; then while theta > eps and fewer than
@@ -441,9 +444,13 @@ void or_store_f32(const int L[4], cplx *M, int nmat)
  * Alg. 1 with single-precision storage of links and g (or_store_f32): the
  * arithmetic stays FP64, every g is stored before it is applied, every new
  * link is stored after its update (and projection), and Delta, F, theta of an
- * iteration are those of the new links before their storage. The starting
- * Delta is that of the input links, which are then stored. On return U holds
- * the stored links. Histories and return value as or_fix.
+ * iteration are those of the new links before their storage. A link of this
+ * representation is its two rows (section 2.2): the third row of a new link
+ * is rebuilt from its two computed rows before it is used, which matters
+ * here because stored matrices are special unitary only to the binary32
+ * rounding. The starting Delta is that of the input links, which are then
+ * stored. On return U holds the stored links. Histories and return value as
+ * or_fix.
  */
 int64_t or_fix_f32_storage(const int L[4], cplx *U, double alpha, double eps, int64_t max_iter, int reunit_every,
                            double *F_hist, double *theta_hist, int64_t hist_cap)
@@ -469,6 +476,7 @@ int64_t or_fix_f32_storage(const int L[4], cplx *U, double alpha, double eps, in
         or_apply_gauge(L, Ux, g);
         ++it;
         if (reunit_every > 0 && it % reunit_every == 0) or_reunit_links(L, Ux);
+        two_row_field(L, Ux, 4, 0);
         or_measure(L, Ux, &F, &theta);
         memcpy(U, Ux, sizeof(cplx) * 36 * V);
         or_store_f32(L, U, 4);
