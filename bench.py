@@ -137,6 +137,39 @@ def main():
                         time_to_theta_s=ttt, iterations=it, F_final=F, theta_final=th, fft_schedule=sched)
         log(f"[{tag}] {args.steps / dt:.1f} it/s, fixed in {it} its / {ttt * 1e3:.2f} ms, F={F:.15f}")
 
+    # single-precision link storage (the paper's single-precision mode, 12-real
+    # in binary32, FP64 arithmetic) with the FP32 transform; fix_until then
+    # refines in FP64 storage from theta <= 1e-10 down to 1e-15
+    U = U0.clone()
+    fx = GaugeFixer(U, fft_prec=1, link_prec=1)
+    fx.step(args.warmup)
+    torch.cuda.synchronize()
+    log(f"[sp_links] timed {args.steps} steps")
+    t0 = time.perf_counter()
+    fx.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fx.set_timing(True)
+    fx.reset_timing()
+    fx.step(args.steps)
+    kt_sp = fx.kernel_times()
+    fx.close()
+    del fx, U
+    U = U0.clone()
+    fx = GaugeFixer(U, fft_prec=1, link_prec=1, refine_theta=1e-10)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    it, F, th = fx.fix_until(1e-15, 100000)
+    torch.cuda.synchronize()
+    ttt = time.perf_counter() - t2
+    fx.close()
+    del fx, U
+    sp = {"iters_per_s": round(args.steps / dt, 2), "ms_per_step": round(1e3 * dt / args.steps, 4),
+          "kernels_us": {k: round(1e3 * ms / n, 2) for k, (ms, n) in kt_sp.items() if n},
+          "time_to_theta": {"seconds": round(ttt, 5), "iterations": it, "F_final": F, "theta_final": th,
+                            "F_minus_fp64": F - res["fp64"]["F_final"], "refine_theta": 1e-10}}
+    log(f"[sp_links] {args.steps / dt:.1f} it/s, fixed in {it} its / {ttt * 1e3:.2f} ms, F={F:.15f}")
+
     c = 16
     per_iter_bytes = 0.0
     kern = {}
@@ -200,9 +233,14 @@ def main():
         "time_to_theta": {"fp64": {"seconds": round(f64["time_to_theta_s"], 5), "iterations": f64["iterations"],
                                    "F_final": f64["F_final"], "theta_final": f64["theta_final"]},
                           "fp32_fft": {"seconds": round(f32["time_to_theta_s"], 5), "iterations": f32["iterations"],
-                                       "F_final": f32["F_final"], "theta_final": f32["theta_final"]}},
+                                       "F_final": f32["F_final"], "theta_final": f32["theta_final"]},
+                          "sp_links_fp32_fft_then_fp64": {"seconds": sp["time_to_theta"]["seconds"],
+                                                          "iterations": sp["time_to_theta"]["iterations"],
+                                                          "F_final": sp["time_to_theta"]["F_final"],
+                                                          "theta_final": sp["time_to_theta"]["theta_final"]}},
         "fp32_fft": {"iters_per_s": round(f32["iters_per_s"], 2), "ms_per_step": round(f32["ms_per_step"], 4),
                      "fft_schedule": f32["fft_schedule"]},
+        "sp_links_fp32_fft": sp,
         "fft_schedule": f64["fft_schedule"],
         "hbm": {"alg_bytes_per_iter": per_iter_bytes,
                 "effective_GBs": round(per_iter_bytes * f64["iters_per_s"] / 1e9, 1),

@@ -79,6 +79,18 @@ typedef struct {
                              (x,y) 2D pass of schedules 2 and 3 also forms g.
                              Schedules 2 and 3 need Lx*Ly <= 4096 (and
                              Lz*Lt <= 4096 for 3); GF_ERR_SHAPE otherwise.   */
+    int32_t link_prec;    /* 0: links and g stored in FP64. 1: stored in
+                             single precision in the 12-real form of section 2.2
+                             (two rows in binary32, the third rebuilt; the
+                             arithmetic stays FP64): gf_step iterates in this
+                             storage; gf_fix_until iterates in it until theta <=
+                             refine_theta, then in FP64 storage down to its
+                             theta_eps. Storage rounding is not a gauge
+                             transformation: the links leave their gauge orbit by
+                             ~1e-7 (a shifted plaquette).                        */
+    int32_t reserved;     /* must be 0                                             */
+    double refine_theta;  /* link_prec 1: theta at which gf_fix_until switches to
+                             FP64 storage; 0 = default 1e-10                       */
 } gf_params;
 
 /* Bytes of device workspace a context with these parameters needs. Returns 0

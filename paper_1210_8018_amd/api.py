@@ -30,13 +30,14 @@ class GaugeFixer:
     """Fourier-accelerated steepest-descent Landau gauge fixing of one configuration."""
 
     def __init__(self, links: torch.Tensor, alpha: float = 0.08, fft_prec: int = 0, reunit_every: int = 0,
-                 chunk: int = 0, fft_schedule: int = 0):
+                 chunk: int = 0, fft_schedule: int = 0, link_prec: int = 0, refine_theta: float = 0.0):
         _check_links(links)
         self.links = links
         self.dims = dims_of(links)
         self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
         self.fft_prec = int(fft_prec)
-        self.params = gf.make_params(self.dims, alpha, fft_prec, reunit_every, chunk, fft_schedule)
+        self.params = gf.make_params(self.dims, alpha, fft_prec, reunit_every, chunk, fft_schedule, link_prec,
+                                     refine_theta)
         nbytes = gf.gf_workspace_bytes(self.params)
         if nbytes == 0:
             raise ValueError(f"unsupported parameters for dims {self.dims}")
@@ -112,13 +113,13 @@ class BatchGaugeFixer:
     """Many independent configurations, possibly of different dims, in one context."""
 
     def __init__(self, links_list, alpha: float = 0.08, fft_prec: int = 1, reunit_every: int = 0, chunk: int = 0,
-                 fft_schedule: int = 0):
+                 fft_schedule: int = 0, link_prec: int = 0, refine_theta: float = 0.0):
         for t in links_list:
             _check_links(t)
         self.links = list(links_list)
         self.n = len(self.links)
-        self.params = [gf.make_params(dims_of(t), alpha, fft_prec, reunit_every, chunk, fft_schedule)
-                       for t in self.links]
+        self.params = [gf.make_params(dims_of(t), alpha, fft_prec, reunit_every, chunk, fft_schedule, link_prec,
+                                      refine_theta) for t in self.links]
         nbytes = gf.gf_workspace_bytes_batch(self.params)
         if nbytes == 0:
             raise ValueError("unsupported batch parameters")

@@ -74,6 +74,31 @@ __device__ __forceinline__ void m3_store12(double2 *__restrict__ base, int V, in
     for (int k = 0; k < 6; ++k) base[(size_t)k * V + s] = m.e[k];
 }
 
+// Two-row storage in either precision: S2 = double2 (FP64) or float2 (the
+// single-precision storage; entries widened on load, rounded to nearest on
+// store). Arithmetic is FP64 in both.
+__device__ __forceinline__ double2 widen(double2 v) { return v; }
+__device__ __forceinline__ double2 widen(float2 v) { return make_double2((double)v.x, (double)v.y); }
+__device__ __forceinline__ void narrow(double2 &d, double2 v) { d = v; }
+__device__ __forceinline__ void narrow(float2 &d, double2 v) { d = make_float2((float)v.x, (float)v.y); }
+
+template <typename S2>
+__device__ __forceinline__ M3 m3_load12s(const S2 *__restrict__ base, int V, int s)
+{
+    M3 m;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m.e[k] = widen(base[(size_t)k * V + s]);
+    m3_row2(m);
+    return m;
+}
+
+template <typename S2>
+__device__ __forceinline__ void m3_store12s(S2 *__restrict__ base, int V, int s, const M3 &m)
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) narrow(base[(size_t)k * V + s], m.e[k]);
+}
+
 // a b
 __device__ __forceinline__ M3 m3_mul(const M3 &a, const M3 &b)
 {

@@ -67,6 +67,8 @@ struct Cfg {
     double2 *U;           // links [4][3][3][V] (the caller's array)
     double2 *U12[2];      // two-row links [4][2][3][V], two buffers (workspace)
     double2 *g12;         // two-row gauge field [2][3][V] (workspace)
+    float2 *U12f[2];      // the same two link buffers in single-precision storage (link_prec 1)
+    float2 *g12f;         // two-row g in single-precision storage
     void *fields;         // packed transform fields [4][V], double2 or float2
     double2 *g;           // gauge field [3][3][V]
     double *partials;     // [nblk_march or nblk_site][4]: (F hi, F lo, theta hi, theta lo)
@@ -116,6 +118,7 @@ struct Launch {
     int fp32;             // transform precision
     int fused;            // iterations use the fused update + divergence kernel
     int xchg;             // ... in its LDS neighbour-exchange form
+    int link_f32;         // links and g held in single-precision two-row storage (this phase)
     int any_reunit;       // some configuration projects its links every R updates
     int ncfg;
     hipStream_t stream;

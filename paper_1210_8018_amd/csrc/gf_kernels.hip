@@ -995,11 +995,14 @@ __device__ __forceinline__ M3 gauge_from_fields(T2 a, T2 b, T2 d, T2 e)
 }
 
 // g goes to g_override (caller, full matrices) if given, else to the
-// workspace in two-row form (g12, fused path) or full (g).
+// workspace: two_row 1 in two-row form (g12, fused path), 2 in two-row
+// single-precision storage (g12f), 0 full (g).
 __device__ __forceinline__ void store_gauge(const Cfg &C, double2 *g_override, int two_row, int s, const M3 &m)
 {
     if (g_override)
         m3_store(g_override, C.V, s, m);
+    else if (two_row == 2)
+        m3_store12s(C.g12f, C.V, s, m);
     else if (two_row)
         m3_store12(C.g12, C.V, s, m);
     else
@@ -1246,6 +1249,20 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restri
     }
 }
 
+// Two-row link buffer b and two-row g of a configuration, in storage S2.
+template <typename S2>
+__device__ __forceinline__ S2 *links12(const Cfg &C, int b);
+template <>
+__device__ __forceinline__ double2 *links12<double2>(const Cfg &C, int b) { return C.U12[b]; }
+template <>
+__device__ __forceinline__ float2 *links12<float2>(const Cfg &C, int b) { return C.U12f[b]; }
+template <typename S2>
+__device__ __forceinline__ S2 *gauge12(const Cfg &C);
+template <>
+__device__ __forceinline__ double2 *gauge12<double2>(const Cfg &C) { return C.g12; }
+template <>
+__device__ __forceinline__ float2 *gauge12<float2>(const Cfg &C) { return C.g12f; }
+
 // The fused pass with neighbour exchange through LDS. Per t-slice each
 // work-item publishes its g(x) (two rows) and, after its forward links,
 // U'_mu(x) - U'_mu(x)^dag for mu = x, y; a neighbour inside the block reads
@@ -1261,7 +1278,8 @@ __device__ __forceinline__ int block_slot(int b3, int s3n)
     return (o >= 0 && o < kSiteBlock) ? o : -1;
 }
 
-template <typename T2, bool RU>
+// S2: storage of links and g, double2 or float2 (single-precision storage).
+template <typename T2, bool RU, typename S2>
 __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__restrict__ cfgs,
                                                                const Batch *__restrict__ B)
 {
@@ -1274,9 +1292,9 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
     const Ctrl *ct = C.ctrl;
     if (ct->done) return;  // the whole block leaves together
     const int V = C.V, V3 = C.V3;
-    const double2 *__restrict__ Uo = C.U12[ct->cur];
-    double2 *__restrict__ Un = C.U12[ct->cur ^ 1];
-    const double2 *__restrict__ G = C.g12;
+    const S2 *__restrict__ Uo = links12<S2>(C, ct->cur);
+    S2 *__restrict__ Un = links12<S2>(C, ct->cur ^ 1);
+    const S2 *__restrict__ G = gauge12<S2>(C);
     const bool reunit = C.reunit_every > 0 && ct->ru_now;
     if (reunit != RU) return;
     const int lb = blk - B->off_march[c];
@@ -1304,9 +1322,9 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
     M3 gx;
     AH utp;  // U'_t(x - t) - h.c.
     if (inside) {
-        gx = m3_load12(G, V, s3 + V3 * t0);
+        gx = m3_load12s(G, V, s3 + V3 * t0);
         const int sp = s3 + V3 * ((t0 == 0) ? Lt - 1 : t0 - 1);
-        M3 w = m3_mul_mul_dag_rows(m3_load12(G, V, sp), m3_load12(Uo + (size_t)18 * V, V, sp), gx);
+        M3 w = m3_mul_mul_dag_rows(m3_load12s(G, V, sp), m3_load12s(Uo + (size_t)18 * V, V, sp), gx);
         if (RU) m3_reunit(w);
         utp = ah_of(w);
     }
@@ -1332,11 +1350,11 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                     for (int k = 0; k < 6; ++k) gf.e[k] = sg[k][sf[mu]];
                     m3_row2(gf);
                 } else {
-                    gf = m3_load12(G, V, fwd3[mu] + V3 * t);
+                    gf = m3_load12s(G, V, fwd3[mu] + V3 * t);
                 }
-                M3 w = m3_mul_mul_dag_rows(gx, m3_load12(Uo + off, V, s), gf);
+                M3 w = m3_mul_mul_dag_rows(gx, m3_load12s(Uo + off, V, s), gf);
                 if (RU) m3_reunit(w);
-                m3_store12(Un + off, V, s, w);
+                m3_store12s(Un + off, V, s, w);
                 fsum += w.e[0].x + w.e[4].x + w.e[8].x;
                 const AH a = ah_of(w);
                 ah_acc(D, a, -1.0);
@@ -1355,11 +1373,11 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
             }
             {
                 const int tn = (t + 1 == Lt) ? 0 : t + 1;
-                gn = m3_load12(G, V, s3 + V3 * tn);
+                gn = m3_load12s(G, V, s3 + V3 * tn);
                 const size_t off = (size_t)18 * V;
-                M3 w = m3_mul_mul_dag_rows(gx, m3_load12(Uo + off, V, s), gn);
+                M3 w = m3_mul_mul_dag_rows(gx, m3_load12s(Uo + off, V, s), gn);
                 if (RU) m3_reunit(w);
-                m3_store12(Un + off, V, s, w);
+                m3_store12s(Un + off, V, s, w);
                 fsum += w.e[0].x + w.e[4].x + w.e[8].x;
                 utp = ah_of(w);
                 ah_acc(D, utp, -1.0);
@@ -1380,7 +1398,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                     a.d2 = sa[nu][8][o];
                 } else {
                     const int sbk = back3[nu] + V3 * t;
-                    M3 wb = m3_mul_mul_dag_rows(m3_load12(G, V, sbk), m3_load12(Uo + (size_t)nu * 6 * V, V, sbk), gx);
+                    M3 wb = m3_mul_mul_dag_rows(m3_load12s(G, V, sbk), m3_load12s(Uo + (size_t)nu * 6 * V, V, sbk), gx);
                     if (RU) m3_reunit(wb);
                     a = ah_of(wb);
                 }
@@ -1435,7 +1453,8 @@ __global__ __launch_bounds__(kSiteBlock) void k_momentum_table(const Cfg *__rest
     ((T *)C.kmom)[s] = (T)((p2 > 0.0) ? C.kfac / p2 : 0.0);
 }
 
-// Caller's links -> two-row buffer 0 (start of a call).
+// Caller's links -> two-row buffer 0 in storage S2 (start of a call).
+template <typename S2>
 __global__ __launch_bounds__(kSiteBlock) void k_pack_links(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B)
 {
     const int blk = blockIdx.x;
@@ -1443,13 +1462,16 @@ __global__ __launch_bounds__(kSiteBlock) void k_pack_links(const Cfg *__restrict
     const Cfg &C = cfgs[B->idx[c]];
     const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
     if (s >= C.V) return;
+    S2 *__restrict__ dst = links12<S2>(C, 0);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) C.U12[0][(size_t)(mu * 6 + k) * C.V + s] = C.U[(size_t)(mu * 9 + k) * C.V + s];
+        for (int k = 0; k < 6; ++k) narrow(dst[(size_t)(mu * 6 + k) * C.V + s], C.U[(size_t)(mu * 9 + k) * C.V + s]);
 }
 
-// Current two-row buffer -> caller's links, third rows rebuilt (end of a call).
+// Current two-row buffer in storage S2 -> caller's links, third rows rebuilt
+// (end of a call).
+template <typename S2>
 __global__ __launch_bounds__(kSiteBlock) void k_unpack_links(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B)
 {
     const int blk = blockIdx.x;
@@ -1457,10 +1479,10 @@ __global__ __launch_bounds__(kSiteBlock) void k_unpack_links(const Cfg *__restri
     const Cfg &C = cfgs[B->idx[c]];
     const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
     if (s >= C.V) return;
-    const double2 *__restrict__ src = C.U12[C.ctrl->cur];
+    const S2 *__restrict__ src = links12<S2>(C, C.ctrl->cur);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-        const M3 m = m3_load12(src + (size_t)mu * 6 * C.V, C.V, s);
+        const M3 m = m3_load12s(src + (size_t)mu * 6 * C.V, C.V, s);
         m3_store(C.U + (size_t)mu * 9 * C.V, C.V, s, m);
     }
 }
@@ -1753,6 +1775,10 @@ hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *
     return hipGetLastError();
 }
 
+// Where the gauge passes put g: 0 full (g), 1 two-row FP64 (g12), 2 two-row
+// single-precision storage (g12f).
+static int gauge_store_mode(const Launch &L) { return L.fused ? (L.link_f32 ? 2 : 1) : 0; }
+
 // (tile capacity, work-group size) instances of the 2D passes: 4 or 8
 // elements per work-item.
 #define GF_2D_SIZES(X, P2) \
@@ -1810,7 +1836,7 @@ static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
 #define X(C_, T_, P2_)                                                                                            \
     if (L.xy_cap == C_ && L.xy_th == T_ && (P2_ ? L.xy_p2 : L.xy_gen)) {                                          \
         hipLaunchKernelGGL((k_fft_xy_inv_gauge<T2, C_, T_, P2_>), dim3(L.total_xy_tiles), dim3(T_), sh, L.stream,    \
-                           L.cfgs, L.batch, rd, go, L.xy_tw2, L.fused);                                           \
+                           L.cfgs, L.batch, rd, go, L.xy_tw2, gauge_store_mode(L));                                           \
         ++launched;                                                                                               \
     }
     GF_2D_VARIANTS(X)
@@ -1873,10 +1899,10 @@ hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override)
 {
     if (L.fp32)
         hipLaunchKernelGGL(k_gauge<float2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
-                           L.batch, respect_done, g_override, L.fused);
+                           L.batch, respect_done, g_override, gauge_store_mode(L));
     else
         hipLaunchKernelGGL(k_gauge<double2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
-                           L.batch, respect_done, g_override, L.fused);
+                           L.batch, respect_done, g_override, gauge_store_mode(L));
     return hipGetLastError();
 }
 
@@ -1884,16 +1910,25 @@ hipError_t launch_update_delta(const Launch &L)
 {
     const dim3 grid(L.total_march_blocks), blk(kSiteBlock);
     if (L.any_reunit) hipLaunchKernelGGL(k_mark_reunit, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.batch);
-    if (L.xchg) {
+    if (L.xchg || L.link_f32) {
+#define GF_UPD(T2_, S2_)                                                                                      \
+    do {                                                                                                       \
+        hipLaunchKernelGGL((k_update_delta_x<T2_, false, S2_>), grid, blk, 0, L.stream, L.cfgs, L.batch);     \
+        if (L.any_reunit)                                                                                      \
+            hipLaunchKernelGGL((k_update_delta_x<T2_, true, S2_>), grid, blk, 0, L.stream, L.cfgs, L.batch);  \
+    } while (0)
         if (L.fp32) {
-            hipLaunchKernelGGL((k_update_delta_x<float2, false>), grid, blk, 0, L.stream, L.cfgs, L.batch);
-            if (L.any_reunit)
-                hipLaunchKernelGGL((k_update_delta_x<float2, true>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+            if (L.link_f32)
+                GF_UPD(float2, float2);
+            else
+                GF_UPD(float2, double2);
         } else {
-            hipLaunchKernelGGL((k_update_delta_x<double2, false>), grid, blk, 0, L.stream, L.cfgs, L.batch);
-            if (L.any_reunit)
-                hipLaunchKernelGGL((k_update_delta_x<double2, true>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+            if (L.link_f32)
+                GF_UPD(double2, float2);
+            else
+                GF_UPD(double2, double2);
         }
+#undef GF_UPD
         return hipGetLastError();
     }
     if (L.fp32) {
@@ -1910,7 +1945,12 @@ hipError_t launch_update_delta(const Launch &L)
 hipError_t launch_pack_links(const Launch &L)
 {
     hipLaunchKernelGGL(k_set_cur, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.ncfg, 0);
-    hipLaunchKernelGGL(k_pack_links, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs, L.batch);
+    if (L.link_f32)
+        hipLaunchKernelGGL(k_pack_links<float2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
+                           L.batch);
+    else
+        hipLaunchKernelGGL(k_pack_links<double2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
+                           L.batch);
     return hipGetLastError();
 }
 
@@ -1927,7 +1967,12 @@ hipError_t launch_momentum_table(const Launch &L)
 
 hipError_t launch_unpack_links(const Launch &L)
 {
-    hipLaunchKernelGGL(k_unpack_links, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs, L.batch);
+    if (L.link_f32)
+        hipLaunchKernelGGL(k_unpack_links<float2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
+                           L.batch);
+    else
+        hipLaunchKernelGGL(k_unpack_links<double2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
+                           L.batch);
     return hipGetLastError();
 }
 

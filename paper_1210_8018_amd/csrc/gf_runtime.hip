@@ -50,6 +50,8 @@ bool valid_params(const gf_params *p)
     if (V > 2147483647.0 / 9.0) return false;  // 32-bit element offsets inside a plane
     if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return false;
     if (p->fft_prec != 0 && p->fft_prec != 1) return false;
+    if (p->link_prec != 0 && p->link_prec != 1) return false;
+    if (p->reserved != 0 || !(p->refine_theta >= 0.0)) return false;
     if (p->reunit_every < 0 || p->chunk < 0 || p->chunk > kHist) return false;
     if (p->fft_schedule < 0 || p->fft_schedule >= kSchedCount) return false;
     if (p->fft_schedule == kSchedXY1D && !xy_feasible(p->dims)) return false;
@@ -170,7 +172,7 @@ FftAxis plan_axis(const int dims[4], int mu)
 }
 
 struct Layout {
-    size_t fields, g, partials, sin2, tw, links12a, links12b, g12, kmom, total;
+    size_t fields, g, partials, sin2, tw, links12a, links12b, g12, kmom, links12fa, links12fb, g12f, total;
 };
 
 Layout layout_for(const gf_params &p, size_t start)
@@ -204,6 +206,16 @@ Layout layout_for(const gf_params &p, size_t start)
     // K(p) table in the transform's precision
     l.kmom = o;
     o = align_up(o + V * (csz / 2));
+    // single-precision storage of the two link buffers and of g (link_prec 1)
+    l.links12fa = l.links12fb = l.g12f = 0;
+    if (p.link_prec == 1) {
+        l.links12fa = o;
+        o = align_up(o + 24 * V * 8);
+        l.links12fb = o;
+        o = align_up(o + 24 * V * 8);
+        l.g12f = o;
+        o = align_up(o + 6 * V * 8);
+    }
     l.total = o;
     return l;
 }
@@ -237,6 +249,8 @@ struct gf_ctx_s {
     int ncfg = 0;
     bool batch = false;
     std::vector<gf_params> params;
+    int link_prec = 0;          // 1: iterate in single-precision link storage (first phase)
+    double refine_theta = 1e-10;  // theta at which gf_fix_until leaves it
     std::vector<Cfg> cfg;
     Batch bmap{};
     Launch L{};
@@ -439,10 +453,21 @@ gf_status read_ctrl(gf_ctx c)
 gf_status run_chunks(gf_ctx c);
 gf_status reset_active(gf_ctx c);
 gf_status compact_active(gf_ctx c);
+void drop_graph(gf_ctx c);
 
 // Run graph chunks until every configuration is done. On the fused path the
 // iterations work on two-row copies of the links in the workspace: packed from
 // the caller's array first, written back (third rows rebuilt) at the end.
+// Storage of links and g for the coming iterations (a launch property; the
+// captured graph holds the instances of one storage).
+void set_link_storage(gf_ctx c, int f32)
+{
+    if (c->L.link_f32 == f32) return;
+    c->L.link_f32 = f32;
+    c->Lact.link_f32 = f32;
+    drop_graph(c);
+}
+
 gf_status run_until_done(gf_ctx c)
 {
     gf_status st = reset_active(c);
@@ -455,6 +480,36 @@ gf_status run_until_done(gf_ctx c)
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return GF_OK;
+}
+
+// gf_fix_until and its batch form: with link_prec 1, iterations in
+// single-precision storage until theta <= refine_theta, then (if theta_eps
+// is below it and every configuration got there) a measurement of the stored
+// links and iterations in FP64 storage down to theta_eps. max_iter bounds
+// the updates of both phases together.
+gf_status fix_phases(gf_ctx c, double theta_eps, int64_t max_iter)
+{
+    std::vector<long long> before(c->ncfg);
+    for (int k = 0; k < c->ncfg; ++k) before[k] = c->h_ctrl[k].iter;
+    const bool two = c->link_prec == 1 && theta_eps < c->refine_theta;
+    set_link_storage(c, c->link_prec == 1 ? 1 : 0);
+    HIPCHK(c, launch_arm(c->L, c->ncfg, two ? c->refine_theta : theta_eps, max_iter, 0));
+    gf_status st = run_until_done(c);
+    if (st != GF_OK || !two) return st;
+    bool all = true;
+    long long used = 0;
+    for (int k = 0; k < c->ncfg; ++k) {
+        all = all && c->h_ctrl[k].done == kConverged;
+        used = std::max(used, c->h_ctrl[k].iter - before[k]);
+    }
+    if (!all) return GF_OK;
+    set_link_storage(c, 0);
+    // the caller's links now hold the stored links: measure them (not an update)
+    HIPCHK(c, enqueue_measure(c));
+    HIPCHK(c, launch_arm(c->L, c->ncfg, theta_eps, max_iter - used, 0));
+    st = read_ctrl(c);
+    if (st != GF_OK) return st;
+    return run_until_done(c);
 }
 
 gf_status run_chunks(gf_ctx c)
@@ -847,6 +902,9 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         C.U12[0] = (double2 *)(c->ws + l.links12a);
         C.U12[1] = (double2 *)(c->ws + l.links12b);
         C.g12 = (double2 *)(c->ws + l.g12);
+        C.U12f[0] = l.links12fa ? (float2 *)(c->ws + l.links12fa) : nullptr;
+        C.U12f[1] = l.links12fb ? (float2 *)(c->ws + l.links12fb) : nullptr;
+        C.g12f = l.g12f ? (float2 *)(c->ws + l.g12f) : nullptr;
         C.fields = c->ws + l.fields;
         C.g = (double2 *)(c->ws + l.g);
         C.partials = (double *)(c->ws + l.partials);
@@ -891,7 +949,11 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         }
     }
     c->L.fp32 = params[0].fft_prec;
-    c->L.fused = getenv("GF_NOFUSE") ? 0 : 1;
+    // single-precision storage exists only in the fused exchange pass
+    c->L.fused = (getenv("GF_NOFUSE") && params[0].link_prec == 0) ? 0 : 1;
+    c->L.link_f32 = 0;
+    c->link_prec = params[0].link_prec;
+    c->refine_theta = params[0].refine_theta > 0.0 ? params[0].refine_theta : 1e-10;
     c->L.xchg = getenv("GF_NOXCHG") ? 0 : 1;
     c->L.any_reunit = 0;
     for (int k = 0; k < ncfg; ++k) c->L.any_reunit |= params[k].reunit_every > 0;
@@ -952,7 +1014,8 @@ size_t gf_workspace_bytes_batch(int32_t n_cfg, const gf_params *params)
     if (n_cfg < 1 || n_cfg > kMaxCfg || !params) return 0;
     for (int k = 0; k < n_cfg; ++k)
         if (params[k].fft_prec != params[0].fft_prec || params[k].chunk != params[0].chunk ||
-            params[k].fft_schedule != params[0].fft_schedule)
+            params[k].fft_schedule != params[0].fft_schedule || params[k].link_prec != params[0].link_prec ||
+            params[k].refine_theta != params[0].refine_theta)
             return 0;
     return workspace_total(n_cfg, params);
 }
@@ -1028,6 +1091,7 @@ gf_status gf_step(gf_ctx c, int32_t n, double *F, double *theta)
     if (!c || n < 0) return GF_ERR_ARG;
     if (c->batch) return GF_ERR_STATE;
     if (n > 0) {
+        set_link_storage(c, c->link_prec == 1 ? 1 : 0);
         HIPCHK(c, launch_arm(c->L, c->ncfg, -1.0, n, 0));
         gf_status st = run_until_done(c);
         if (st != GF_OK) return st;
@@ -1042,8 +1106,7 @@ gf_status gf_fix_until(gf_ctx c, double theta_eps, int64_t max_iter, int64_t *it
     if (!c || max_iter < 0) return GF_ERR_ARG;
     if (c->batch) return GF_ERR_STATE;
     const long long before = c->h_ctrl[0].iter;
-    HIPCHK(c, launch_arm(c->L, c->ncfg, theta_eps, max_iter, 0));
-    gf_status st = run_until_done(c);
+    gf_status st = fix_phases(c, theta_eps, max_iter);
     if (st != GF_OK) return st;
     if (iters) *iters = c->h_ctrl[0].iter - before;
     if (F) *F = c->h_ctrl[0].F;
@@ -1056,8 +1119,7 @@ gf_status gf_fix_until_batch(gf_ctx c, double theta_eps, int64_t max_iter, int64
     if (!c || max_iter < 0) return GF_ERR_ARG;
     std::vector<long long> before(c->ncfg);
     for (int k = 0; k < c->ncfg; ++k) before[k] = c->h_ctrl[k].iter;
-    HIPCHK(c, launch_arm(c->L, c->ncfg, theta_eps, max_iter, 0));
-    gf_status st = run_until_done(c);
+    gf_status st = fix_phases(c, theta_eps, max_iter);
     if (st != GF_OK) return st;
     for (int k = 0; k < c->ncfg; ++k) {
         if (iters) iters[k] = c->h_ctrl[k].iter - before[k];

@@ -26,6 +26,9 @@ class gf_params(ctypes.Structure):
         ("reunit_every", ctypes.c_int32),
         ("chunk", ctypes.c_int32),
         ("fft_schedule", ctypes.c_int32),
+        ("link_prec", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("refine_theta", ctypes.c_double),
     ]
 
 
@@ -100,7 +103,8 @@ def _check(status: int, where: str, ctx=None, ok=(GF_OK,)):
     return status
 
 
-def make_params(dims, alpha=0.08, fft_prec=0, reunit_every=0, chunk=0, fft_schedule=0) -> gf_params:
+def make_params(dims, alpha=0.08, fft_prec=0, reunit_every=0, chunk=0, fft_schedule=0, link_prec=0,
+                refine_theta=0.0) -> gf_params:
     p = gf_params()
     for k in range(4):
         p.dims[k] = int(dims[k])
@@ -109,6 +113,9 @@ def make_params(dims, alpha=0.08, fft_prec=0, reunit_every=0, chunk=0, fft_sched
     p.reunit_every = int(reunit_every)
     p.chunk = int(chunk)
     p.fft_schedule = int(fft_schedule)
+    p.link_prec = int(link_prec)
+    p.reserved = 0
+    p.refine_theta = float(refine_theta)
     return p
 
 

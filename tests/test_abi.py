@@ -44,3 +44,25 @@ def test_host_only_calls_without_gpu():
     pl[1] = gf.make_params((8, 8, 8, 16), fft_prec=0)  # one precision per batch
     assert gf.gf_workspace_bytes_batch(pl) == 0
     assert gf.lib().gf_init(None, None, None, None, 0, None) == gf.GF_ERR_ARG
+
+
+def test_params_layout_and_link_storage_options():
+    """gf_params matches the C layout (56 bytes); single-precision link storage
+    adds its buffers to the workspace; bad values are rejected."""
+    import ctypes
+
+    from paper_1210_8018_amd import gf
+
+    assert ctypes.sizeof(gf.gf_params) == 56
+    assert gf.gf_params.refine_theta.offset == 48 and gf.gf_params.link_prec.offset == 40
+    V = 16**4
+    b0 = gf.gf_workspace_bytes(gf.make_params((16, 16, 16, 16)))
+    b1 = gf.gf_workspace_bytes(gf.make_params((16, 16, 16, 16), link_prec=1))
+    assert b1 - b0 >= V * (2 * 192 + 48)
+    assert gf.gf_workspace_bytes(gf.make_params((8, 8, 8, 8), link_prec=2)) == 0
+    assert gf.gf_workspace_bytes(gf.make_params((8, 8, 8, 8), link_prec=1, refine_theta=-1.0)) == 0
+    p = gf.make_params((8, 8, 8, 8))
+    p.reserved = 1
+    assert gf.gf_workspace_bytes(p) == 0
+    pl = [gf.make_params((8, 8, 8, 8), link_prec=1), gf.make_params((8, 8, 8, 16), link_prec=0)]
+    assert gf.gf_workspace_bytes_batch(pl) == 0  # one link storage per batch

@@ -347,3 +347,73 @@ def test_batch_equals_single_runs(monkeypatch, prec, sched):
         (it, F, th), Uf = single[k]
         assert its[k] == it and Fs[k] == F and ths[k] == th
         assert np.array_equal(host(Ubs[k]), Uf)
+
+
+# ---------------------------------------------------------------- single-precision link storage
+
+def test_single_precision_storage_matches_oracle():
+    """link_prec 1, FP64 transform: per-iteration F and theta against the oracle
+    run with the same storage (binary32 two-row links and g, FP64 arithmetic).
+    Both round the same FP64 values, so they agree far below the storage
+    rounding unless an FP64 difference straddles a binary32 rounding boundary
+    (then one entry differs by one binary32 ulp)."""
+    dims = (8, 8, 8, 8)
+    U = random_links(dims, 0.3, 1)
+    n = 25
+    _, Uo, Fr, Tr = oracle.fix(dims, U, alpha=ALPHA, eps=-1.0, max_iter=n, f32_storage=True)
+    Ud = dev(U)
+    fx = GaugeFixer(Ud, link_prec=1)
+    fx.step(n)
+    Fh, Th = fx.history()
+    assert len(Fh) == n + 1
+    Fh, Th = np.asarray(Fh), np.asarray(Th)
+    assert np.max(np.abs(Fh - Fr)) < 1e-10
+    assert np.max(np.abs(Th - Tr) / Tr) < 1e-6
+    # the caller's links hold the stored links (binary32 rows)
+    got = host(Ud)
+    assert np.max(np.abs(got - Uo)) < 1e-6
+    rows = got[:, :2]
+    assert np.array_equal(rows.real.astype(np.float32).astype(np.float64), rows.real)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_single_precision_storage_then_fp64_refinement(prec):
+    """gf_fix_until with link_prec 1: single-precision storage down to
+    refine_theta, FP64 storage down to 1e-15; compared with the oracle doing
+    the same two phases (FP64 transform) and with the plain FP64 run."""
+    dims = (8, 8, 8, 8)
+    U = random_links(dims, 0.3, 1)
+    n1, U1, F1, T1 = oracle.fix(dims, U, alpha=ALPHA, eps=1e-10, max_iter=5000, f32_storage=True)
+    n2, U2, F2, T2 = oracle.fix(dims, U1, alpha=ALPHA, eps=EPS, max_iter=5000)
+    n64, _, F64, _ = oracle.fix(dims, U, alpha=ALPHA, eps=EPS, max_iter=5000)
+    Ud = dev(U)
+    fx = GaugeFixer(Ud, link_prec=1, refine_theta=1e-10, fft_prec=prec)
+    it, F, th = fx.fix_until(EPS, 5000)
+    assert th <= EPS
+    if prec == 0:
+        assert abs(it - (n1 + n2)) <= 1, (it, n1, n2)
+        assert abs(F - F2[-1]) < 1e-11
+    assert abs(F - F64[-1]) < 1e-6
+    Uf = host(Ud)
+    assert abs(oracle.plaquette(dims, Uf) - oracle.plaquette(dims, U)) < 1e-6
+    M = np.moveaxis(Uf.reshape(4, 3, 3, -1), 3, 1).reshape(-1, 3, 3)
+    assert np.max(np.abs(M @ np.conj(np.swapaxes(M, -1, -2)) - np.eye(3))) < 1e-5
+
+
+def test_single_precision_storage_batch_equals_single(monkeypatch):
+    monkeypatch.setenv("GF_TCHUNK", "2")
+    monkeypatch.setenv("GF_TCHUNK_BATCH", "2")
+    cases = [((8, 8, 8, 8), 0.3, 1), ((12, 8, 6, 4), 0.35, 3)]
+    Us = [random_links(d, e, s) for d, e, s in cases]
+    single = []
+    for U in Us:
+        Ud = dev(U)
+        fx = GaugeFixer(Ud, link_prec=1, fft_prec=1, fft_schedule=3)
+        single.append((fx.fix_until(EPS, 5000), host(Ud)))
+    Ubs = [dev(U) for U in Us]
+    bx = BatchGaugeFixer(Ubs, link_prec=1, fft_prec=1, fft_schedule=3)
+    its, Fs, ths = bx.fix_until(EPS, 5000)
+    for k in range(len(cases)):
+        (it, F, th), Uf = single[k]
+        assert its[k] == it and Fs[k] == F and ths[k] == th
+        assert np.array_equal(host(Ubs[k]), Uf)
