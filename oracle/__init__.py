@@ -62,6 +62,10 @@ def lib():
             "or_local_functional_g": (D, [P, P, P, I64, P]),
             "or_grad_omega_sites": (None, [P, P, P, I64, P, P]),
             "or_grad_links": (None, [P, P, P]),
+            "or_philox4x32_10": (None, [P, P, P]),
+            "or_heatbath": (None, [P, P, D, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, I64]),
+            "or_kp_samples": (I64, [D, I64, ctypes.c_uint64, P]),
+            "or_overrelax": (None, [P, P, ctypes.c_int]),
             "or_num_threads": (ctypes.c_int, []),
             "or_set_num_threads": (None, [ctypes.c_int]),
         }
@@ -190,6 +194,38 @@ def store_f32(dims, M):
     n = M.size // (9 * int(np.prod(dims)))
     lib().or_store_f32(_p(d), _p(M), n)
     return M
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block: four uint32 outputs for a 4-word counter and 2-word key."""
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def heatbath(dims, U, beta, n_sweeps, n_or=0, seed=0, sweep0=0):
+    """Wilson-action heatbath + overrelaxation sweeps on a copy of U (every extent even)."""
+    U = np.array(U, dtype=np.complex128, copy=True)
+    d = _dims(dims)
+    lib().or_heatbath(_p(d), _p(U), float(beta), int(n_sweeps), int(n_or), int(seed), int(sweep0))
+    return U
+
+
+def overrelax(dims, U, n):
+    """n overrelaxation sweeps on a copy of U."""
+    U = np.array(U, dtype=np.complex128, copy=True)
+    d = _dims(dims)
+    lib().or_overrelax(_p(d), _p(U), int(n))
+    return U
+
+
+def kp_samples(a, n, seed=0):
+    """x0 of n Kennedy-Pendleton draws at parameter a (accepted ones)."""
+    out = np.zeros(int(n), dtype=np.float64)
+    m = lib().or_kp_samples(float(a), int(n), int(seed), _p(out))
+    return out[:m]
 
 
 def plaquette(dims, U):

@@ -885,3 +885,242 @@ void or_set_num_threads(int n)
     (void)n;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* input generator: Wilson-action heatbath and overrelaxation                 */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Thermalised SU(3) configurations for the Wilson action
+ * S = beta sum_P (1 - Re Tr U_P / 3), the workload of the paper's tests
+ * (section 3: beta = 5.8, 6.0, 6.2). Not part of the method; it produces its
+ * inputs. Pseudo-heatbath of Cabibbo and Marinari (Phys. Lett. B 119, 1982)
+ * over the three SU(2) subgroups, each drawn with the algorithm of Kennedy
+ * and Pendleton (Phys. Lett. B 156, 1985); microcanonical overrelaxation
+ * (Creutz, Phys. Rev. D 36, 1987); random numbers from Philox4x32-10
+ * (Salmon, Moraes, Dror and Shaw, SC 2011), one counter per draw.
+ */
+
+static const uint32_t PHILOX_M0 = 0xD2511F53u, PHILOX_M1 = 0xCD9E8D57u;
+static const uint32_t PHILOX_W0 = 0x9E3779B9u, PHILOX_W1 = 0xBB67AE85u;
+
+/* Philox4x32 with 10 rounds: out = f(ctr, key). */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        const uint64_t p0 = (uint64_t)PHILOX_M0 * c0, p1 = (uint64_t)PHILOX_M1 * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* A 32-bit draw as a uniform number in (0, 1]. */
+static double unit_open0(uint32_t u) { return ((double)u + 1.0) * (1.0 / 4294967296.0); }
+
+/* Counter of draw `slot` (attempt, or 255 for the direction) of subgroup k of
+ * the update of U_mu(site) in heatbath sweep n. */
+static void hb_counter(int64_t site, int mu, int k, int slot, int64_t n, uint32_t ctr[4])
+{
+    ctr[0] = (uint32_t)site;
+    ctr[1] = (uint32_t)(mu + 4 * k + 16 * slot);
+    ctr[2] = (uint32_t)((uint64_t)n & 0xffffffffu);
+    ctr[3] = (uint32_t)((uint64_t)n >> 32);
+}
+
+enum { HB_MAX_ATTEMPTS = 64, HB_DIRECTION_SLOT = 255 };
+
+/*
+ * x in SU(2) (quaternion x0 + i x.sigma) with density proportional to
+ * exp(a x0) on SU(2) (Kennedy-Pendleton): x0 from sqrt(1 - x0^2) e^(a x0) by
+ * rejection, the vector part uniform on its sphere. Returns 0 and leaves x
+ * untouched if no attempt is accepted (probability below 1e-30 for a > 0.5).
+ */
+static int kp_draw(double a, int64_t site, int mu, int k, int64_t n, const uint32_t key[2], double x[4])
+{
+    uint32_t ctr[4], r[4];
+    for (int j = 0; j < HB_MAX_ATTEMPTS; ++j) {
+        hb_counter(site, mu, k, j, n, ctr);
+        or_philox4x32_10(ctr, key, r);
+        const double r1 = unit_open0(r[0]), r2 = unit_open0(r[1]), r3 = unit_open0(r[2]), r4 = unit_open0(r[3]);
+        const double c = cos(2.0 * M_PI * r2);
+        const double lam2 = -(log(r1) + c * c * log(r3)) / (2.0 * a);
+        if (r4 * r4 <= 1.0 - lam2) {
+            x[0] = 1.0 - 2.0 * lam2;
+            hb_counter(site, mu, k, HB_DIRECTION_SLOT, n, ctr);
+            or_philox4x32_10(ctr, key, r);
+            const double ct = 2.0 * unit_open0(r[0]) - 1.0, phi = 2.0 * M_PI * unit_open0(r[1]);
+            const double rad = sqrt(fmax(0.0, 1.0 - x[0] * x[0]));
+            const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+            x[1] = rad * st * cos(phi);
+            x[2] = rad * st * sin(phi);
+            x[3] = rad * ct;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+/* Staple sum A of U_mu(s): U_mu(s) A is the sum of the six plaquettes through it. */
+static void staple_sum(const int L[4], const cplx *U, int64_t s, int mu, mat3 A)
+{
+    const int64_t V = vol(L);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) A[i][j] = 0.0;
+    const int64_t sp = hop(L, s, mu, +1);
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        mat3 a, b, c, t, u;
+        /* upper: U_nu(s + mu) U_mu^dag(s + nu) U_nu^dag(s) */
+        get_link(U, V, nu, sp, a);
+        get_link(U, V, mu, hop(L, s, nu, +1), b);
+        get_link(U, V, nu, s, c);
+        mat_dag(b, b);
+        mat_dag(c, c);
+        mat_mul(a, b, t);
+        mat_mul(t, c, u);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) A[i][j] += u[i][j];
+        /* lower: U_nu^dag(s + mu - nu) U_mu^dag(s - nu) U_nu(s - nu) */
+        const int64_t sm = hop(L, s, nu, -1);
+        get_link(U, V, nu, hop(L, sp, nu, -1), a);
+        get_link(U, V, mu, sm, b);
+        get_link(U, V, nu, sm, c);
+        mat_dag(a, a);
+        mat_dag(b, b);
+        mat_mul(a, b, t);
+        mat_mul(t, c, u);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) A[i][j] += u[i][j];
+    }
+}
+
+/*
+ * One Cabibbo-Marinari update of U (left multiplication by an SU(2) matrix
+ * in each subgroup (0,1), (0,2), (1,2) in turn) against staple sum A.
+ * mode 0: heatbath; mode 1: overrelaxation. Then Gram-Schmidt.
+ */
+static void cm_update(mat3 U, mat3 A, double beta, int mode, int64_t site, int mu, int64_t n,
+                      const uint32_t key[2])
+{
+    static const int sub[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int k = 0; k < 3; ++k) {
+        const int p = sub[k][0], q = sub[k][1];
+        mat3 W;
+        mat_mul(U, A, W);
+        /* the part of the 2x2 block proportional to SU(2): [[al, be], [-conj(be), conj(al)]] */
+        const cplx al = 0.5 * (W[p][p] + conj(W[q][q]));
+        const cplx be = 0.5 * (W[p][q] - conj(W[q][p]));
+        const double det = creal(al) * creal(al) + cimag(al) * cimag(al) + creal(be) * creal(be) +
+                           cimag(be) * cimag(be);
+        if (!(det > 1e-300)) continue;
+        const double nk = sqrt(det);
+        /* V = block / |block| in SU(2); Re Tr(r W_block) = nk Re Tr(r V) */
+        const cplx v00 = al / nk, v01 = be / nk;
+        /* r = X V^dag (heatbath) or r = V^dag V^dag (overrelaxation) */
+        cplx vd00 = conj(v00), vd01 = -v01, vd10 = conj(v01), vd11 = v00; /* V^dag */
+        cplx r00, r01, r10, r11;
+        if (mode == 0) {
+            double x[4];
+            if (!kp_draw(2.0 * beta / 3.0 * nk, site, mu, k, n, key, x)) continue;
+            const cplx x00 = x[0] + I * x[3], x01 = x[2] + I * x[1];
+            const cplx x10 = -x[2] + I * x[1], x11 = x[0] - I * x[3];
+            r00 = x00 * vd00 + x01 * vd10;
+            r01 = x00 * vd01 + x01 * vd11;
+            r10 = x10 * vd00 + x11 * vd10;
+            r11 = x10 * vd01 + x11 * vd11;
+        } else {
+            r00 = vd00 * vd00 + vd01 * vd10;
+            r01 = vd00 * vd01 + vd01 * vd11;
+            r10 = vd10 * vd00 + vd11 * vd10;
+            r11 = vd10 * vd01 + vd11 * vd11;
+        }
+        for (int j = 0; j < 3; ++j) {
+            const cplx up = U[p][j], uq = U[q][j];
+            U[p][j] = r00 * up + r01 * uq;
+            U[q][j] = r10 * up + r11 * uq;
+        }
+    }
+    or_reunit(&U[0][0]);
+}
+
+/*
+ * n_sweeps sweeps, each a heatbath sweep (sweep index sweep0 + i for the
+ * random numbers) followed by n_or overrelaxation sweeps. A sweep visits
+ * mu = 0..3, and for each the even then the odd sites (x+y+z+t even/odd);
+ * the links of one (mu, parity) class are independent and updated together.
+ * Every extent must be even.
+ */
+void or_heatbath(const int L[4], cplx *U, double beta, int n_sweeps, int n_or, uint64_t seed, int64_t sweep0)
+{
+    const int64_t V = vol(L);
+    const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    for (int i = 0; i < n_sweeps; ++i) {
+        for (int rep = 0; rep <= n_or; ++rep) {
+            const int mode = rep == 0 ? 0 : 1;
+            for (int mu = 0; mu < 4; ++mu)
+                for (int par = 0; par < 2; ++par) {
+#pragma omp parallel for schedule(static)
+                    for (int64_t s = 0; s < V; ++s) {
+                        int c[4];
+                        coords(L, s, c);
+                        if (((c[0] + c[1] + c[2] + c[3]) & 1) != par) continue;
+                        mat3 u, A;
+                        staple_sum(L, U, s, mu, A);
+                        get_link(U, V, mu, s, u);
+                        cm_update(u, A, beta, mode, s, mu, sweep0 + i, key);
+                        put_link(U, V, mu, s, u);
+                    }
+                }
+        }
+    }
+}
+
+/* n overrelaxation sweeps alone (no random numbers; the action is unchanged). */
+void or_overrelax(const int L[4], cplx *U, int n)
+{
+    const int64_t V = vol(L);
+    const uint32_t key[2] = {0u, 0u};
+    for (int i = 0; i < n; ++i)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int par = 0; par < 2; ++par) {
+#pragma omp parallel for schedule(static)
+                for (int64_t s = 0; s < V; ++s) {
+                    int c[4];
+                    coords(L, s, c);
+                    if (((c[0] + c[1] + c[2] + c[3]) & 1) != par) continue;
+                    mat3 u, A;
+                    staple_sum(L, U, s, mu, A);
+                    get_link(U, V, mu, s, u);
+                    cm_update(u, A, 1.0, 1, s, mu, 0, key);
+                    put_link(U, V, mu, s, u);
+                }
+            }
+}
+
+/* Kennedy-Pendleton draws for tests: x0 of n draws at parameter a (subgroup 0,
+ * mu 0, sweep n0 + j for draw j at site 0). Returns the number accepted. */
+int64_t or_kp_samples(double a, int64_t n, uint64_t seed, double *x0)
+{
+    const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    int64_t acc = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        double x[4];
+        if (kp_draw(a, 0, 0, 0, j, key, x)) x0[acc++] = x[0];
+    }
+    return acc;
+}
