@@ -9,7 +9,7 @@ durations measured with HIP events on the library's stream, the roofline of
 the dominant kernel, and the CPU oracle on a bounded sample.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-iters N] [--no-cpu]
-python bench.py --workload batch|large48|large64|diff   (other measured workloads)
+python bench.py --workload batch|large48|large64|diff|thermal   (other measured workloads)
 """
 import argparse
 import json
@@ -67,7 +67,10 @@ def main():
     ap.add_argument("--dims", default="32,32,32,32")
     ap.add_argument("--eps", type=float, default=0.3)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--workload", default="headline", choices=["headline", "batch", "large48", "large64", "diff"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "batch", "large48", "large64", "diff", "thermal"])
+    ap.add_argument("--beta", type=float, default=6.0)
+    ap.add_argument("--sweeps", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -81,7 +84,8 @@ def main():
     from paper_1210_8018_amd.inputs import random_links
 
     if args.workload != "headline":
-        {"batch": bench_batch, "large48": bench_large, "large64": bench_large, "diff": bench_diff}[args.workload](args)
+        {"batch": bench_batch, "large48": bench_large, "large64": bench_large, "diff": bench_diff,
+         "thermal": bench_thermal}[args.workload](args)
         return
 
     dims = tuple(int(v) for v in args.dims.split(","))
@@ -422,6 +426,61 @@ def bench_diff(args):
            "unit": "ms (forward)", "backward_ms": round((t2 - t1) / n * 1e3, 4), "n_gpus": 1, "higher_is_better": False,
            "data": "synthetic", "dtype": "f64", "F": F,
            "config": {"workload": "24^4 links eps 0.3 seed 5, omega ~ N(0, 0.1^2) seed 6"}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_thermal(args):
+    """32^4 Wilson-action configuration thermalised on the GPU (cold start, heatbath + 4
+    overrelaxation sweeps), then gauge-fixed to theta <= 1e-15 in each precision mode."""
+    import numpy as np
+    import torch
+
+    from paper_1210_8018_amd.api import GaugeFixer
+
+    dims = (32, 32, 32, 32)
+    V = int(np.prod(dims))
+    one = torch.zeros((4, 3, 3, V), dtype=torch.complex128, device="cuda")
+    for i in range(3):
+        one[:, i, i, :] = 1
+    U0 = one.reshape(4, 3, 3, 32, 32, 32, 32).contiguous()
+    fx = GaugeFixer(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plaq = []
+    done = 0
+    while done < args.sweeps:
+        n = min(50, args.sweeps - done)
+        fx.heatbath(args.beta, n, 4, seed=20121030, sweep0=done)
+        done += n
+        plaq.append((done, fx.plaquette()))
+        log(f"  {time.perf_counter() - t0:.1f}s: {done} sweeps, plaquette {plaq[-1][1]:.6f}")
+    gen_s = time.perf_counter() - t0
+    fx.close()
+    res = {}
+    for tag, kw in (("fp64", {}), ("fp32_fft", {"fft_prec": 1}), ("sp_links_fp32_fft", {"fft_prec": 1, "link_prec": 1})):
+        U = U0.clone()
+        fx = GaugeFixer(U, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        it = 0
+        while True:  # slices of 1000 iterations, progress between them
+            di, F, th = fx.fix_until(1e-15, 1000, allow_maxiter=True)
+            it += di
+            log(f"  [{tag}] {time.perf_counter() - t1:.2f}s: {it} iterations, theta {th:.3e}")
+            if th <= 1e-15 or it >= 100000:
+                break
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        res[tag] = {"seconds": round(dt, 4), "iterations": it, "F_final": F, "theta_final": th,
+                    "iters_per_s": round(it / dt, 1)}
+        fx.close()
+        del fx, U
+    out = {"metric": f"time to theta<=1e-15 at 32^4 SU(3), Wilson action beta={args.beta} thermalised on the GPU",
+           "value": res["fp64"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "dtype": "f64",
+           "config": {"workload": f"32^4 cold start, {args.sweeps} x (heatbath + 4 overrelaxation) sweeps at "
+                                  f"beta={args.beta}, Philox seed 20121030"},
+           "generation": {"seconds": round(gen_s, 3), "plaquette": plaq}, "fix": res}
     print(json.dumps(out), flush=True)
 
 

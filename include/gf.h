@@ -159,6 +159,27 @@ gf_status gf_apply_gauge(gf_ctx ctx, const void *d_g);
 gf_status gf_fft(gf_ctx ctx, void *d_fields, int32_t nfields, int32_t sign);
 
 /*
+ * Input generator: thermalised configurations of the Wilson action
+ * S = beta sum_P (1 - Re Tr U_P / 3), the workload the paper gauge-fixes
+ * (section 3: beta = 5.8, 6.0, 6.2). Updates the context's links in place
+ * with n_sweeps sweeps, each one heatbath sweep (Cabibbo-Marinari over the
+ * SU(2) subgroups (0,1), (0,2), (1,2), Kennedy-Pendleton draws) followed by
+ * n_or overrelaxation sweeps; a sweep visits mu = 0..3 and for each the even
+ * then the odd sites. Random numbers: Philox4x32-10 with key (seed low
+ * 32 bits, seed high 32 bits) and, for draw j of subgroup k of U_mu(site) in
+ * heatbath sweep n = sweep0 + i, counter (site, mu + 4k + 16j, n low, n high)
+ * (j = 255 for the direction of the SU(2) element, at most 64 attempts).
+ * Every link is projected to SU(3) after its update. Afterwards Delta, F and
+ * theta are measured as by gf_init. Every extent must be even (GF_ERR_SHAPE);
+ * not for batch contexts (GF_ERR_STATE). Synchronises.
+ */
+gf_status gf_heatbath(gf_ctx ctx, double beta, int32_t n_sweeps, int32_t n_or, uint64_t seed, int64_t sweep0);
+
+/* Average plaquette (1/(18 V)) sum_x sum_{mu<nu} Re Tr U_mu(x) U_nu(x+mu)
+ * U_mu^dag(x+nu) U_nu^dag(x) of the context's links; synchronises. */
+gf_status gf_plaquette(gf_ctx ctx, double *P);
+
+/*
  * Batches: n_cfg independent configurations of possibly different dims in
  * one context. Every kernel launch covers the tiles of every configuration
  * still iterating; each configuration has its own device-side stopping test.

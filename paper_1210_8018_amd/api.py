@@ -88,6 +88,13 @@ class GaugeFixer:
     def fft_schedule(self) -> int:
         return gf.gf_fft_schedule(self.ctx)
 
+    def heatbath(self, beta: float, n_sweeps: int, n_or: int = 0, seed: int = 0, sweep0: int = 0):
+        """Wilson-action heatbath + overrelaxation sweeps on the links (the input generator)."""
+        gf.gf_heatbath(self.ctx, beta, n_sweeps, n_or, seed, sweep0)
+
+    def plaquette(self) -> float:
+        return gf.gf_plaquette(self.ctx)
+
     def set_timing(self, on: bool):
         gf.gf_set_timing(self.ctx, on)
 

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgfix.so")
-SOURCES = ["gf_kernels.hip", "gf_runtime.hip"]
+SOURCES = ["gf_kernels.hip", "gf_heatbath.hip", "gf_runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -147,6 +147,16 @@ __device__ __forceinline__ M3 m3_dag_mul(const M3 &a, const M3 &b)
     return c;
 }
 
+__device__ __forceinline__ M3 m3_dag(const M3 &a)
+{
+    M3 c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) c.e[i * 3 + j] = cconj(a.e[j * 3 + i]);
+    return c;
+}
+
 __device__ __forceinline__ M3 m3_add(const M3 &a, const M3 &b)
 {
     M3 c;

@@ -139,6 +139,8 @@ hipError_t launch_update(const Launch &L, int respect_done, const double2 *g_ove
 hipError_t launch_update_delta(const Launch &L);
 hipError_t launch_pack_links(const Launch &L);
 hipError_t launch_momentum_table(const Launch &L);
+hipError_t launch_heatbath_sweep(const Launch &L, int V, int mode, double beta, uint64_t seed, long long n);
+hipError_t launch_plaquette(const Launch &L, int nblk, double *out);
 hipError_t launch_unpack_links(const Launch &L);
 hipError_t launch_functional_g_impl(const Launch &L, int nblk, const double *omega, double scale, double *out);
 hipError_t launch_functional_g_backward_impl(const Launch &L, int nblk, const double *omega, double scale,

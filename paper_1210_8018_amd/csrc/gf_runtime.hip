@@ -1175,6 +1175,35 @@ gf_status gf_apply_gauge(gf_ctx c, const void *d_g)
     return GF_OK;
 }
 
+gf_status gf_heatbath(gf_ctx c, double beta, int32_t n_sweeps, int32_t n_or, uint64_t seed, int64_t sweep0)
+{
+    if (!c || n_sweeps < 0 || n_or < 0 || !(beta >= 0.0) || sweep0 < 0) return GF_ERR_ARG;
+    if (c->batch) return GF_ERR_STATE;
+    const Cfg &C = c->cfg[0];
+    for (int mu = 0; mu < 4; ++mu)
+        if (C.dims[mu] % 2) return GF_ERR_SHAPE;
+    for (int i = 0; i < n_sweeps; ++i) {
+        HIPCHK(c, launch_heatbath_sweep(c->L, C.V, 0, beta, seed, (long long)(sweep0 + i)));
+        for (int r = 0; r < n_or; ++r) HIPCHK(c, launch_heatbath_sweep(c->L, C.V, 1, beta, seed, 0));
+    }
+    // the links changed: measure them again, as after any other change
+    HIPCHK(c, enqueue_measure(c));
+    return read_ctrl(c);
+}
+
+gf_status gf_plaquette(gf_ctx c, double *P)
+{
+    if (!c || !P) return GF_ERR_ARG;
+    if (c->batch) return GF_ERR_STATE;
+    const Cfg &C = c->cfg[0];
+    HIPCHK(c, launch_plaquette(c->L, C.nblk_site, c->d_scalar));
+    double h = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&h, c->d_scalar, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *P = h;
+    return std::isfinite(h) ? GF_OK : GF_ERR_NONFINITE;
+}
+
 gf_status gf_fft(gf_ctx c, void *d_fields, int32_t nfields, int32_t sign)
 {
     if (!c || !d_fields || nfields < 1 || nfields > 65535 || (sign != 1 && sign != -1)) return GF_ERR_ARG;

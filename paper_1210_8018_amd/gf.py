@@ -72,6 +72,8 @@ def lib():
             "gf_gauge": (st, [P, P]),
             "gf_apply_gauge": (st, [P, P]),
             "gf_fft": (st, [P, P, I32, I32]),
+            "gf_heatbath": (st, [P, D, I32, I32, ctypes.c_uint64, I64]),
+            "gf_plaquette": (st, [P, PD]),
             "gf_functional_g": (st, [P, P, PD]),
             "gf_functional_g_backward": (st, [P, P, D, P, P]),
             "gf_destroy": (st, [P]),
@@ -218,6 +220,16 @@ def gf_apply_gauge(ctx, g: torch.Tensor):
 
 def gf_fft(ctx, fields: torch.Tensor, nfields: int, sign: int):
     _check(lib().gf_fft(ctx, _ptr(fields), int(nfields), int(sign)), "gf_fft", ctx)
+
+
+def gf_heatbath(ctx, beta: float, n_sweeps: int, n_or: int = 0, seed: int = 0, sweep0: int = 0):
+    _check(lib().gf_heatbath(ctx, float(beta), int(n_sweeps), int(n_or), int(seed), int(sweep0)), "gf_heatbath", ctx)
+
+
+def gf_plaquette(ctx) -> float:
+    P = ctypes.c_double()
+    _check(lib().gf_plaquette(ctx, ctypes.byref(P)), "gf_plaquette", ctx)
+    return P.value
 
 
 def gf_functional_g(ctx, omega: torch.Tensor) -> float:
