@@ -30,6 +30,42 @@ __device__ __forceinline__ double2 ccmul(double2 a, double2 b)
 }
 __device__ __forceinline__ double cnorm2(double2 a) { return a.x * a.x + a.y * a.y; }
 
+// Complex multiply-accumulate as four fused multiply-adds: acc + a b,
+// acc + a conj(b), acc + conj(a) b.
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc - a b
+__device__ __forceinline__ double2 cfms(double2 a, double2 b, double2 acc)
+{
+    acc.x = fma(-a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+__device__ __forceinline__ double2 cfmac(double2 a, double2 b, double2 acc)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.y, b.x, acc.y);
+    acc.y = fma(-a.x, b.y, acc.y);
+    return acc;
+}
+__device__ __forceinline__ double2 ccfma(double2 a, double2 b, double2 acc)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+
 // ---------------------------------------------------------------- 3x3
 struct M3 {
     double2 e[9];
@@ -54,9 +90,9 @@ __device__ __forceinline__ void m3_store(double2 *__restrict__ base, int V, int 
 // every special unitary matrix.
 __device__ __forceinline__ void m3_row2(M3 &m)
 {
-    m.e[6] = cconj(csub(cmul(m.e[1], m.e[5]), cmul(m.e[2], m.e[4])));
-    m.e[7] = cconj(csub(cmul(m.e[2], m.e[3]), cmul(m.e[0], m.e[5])));
-    m.e[8] = cconj(csub(cmul(m.e[0], m.e[4]), cmul(m.e[1], m.e[3])));
+    m.e[6] = cconj(cfms(m.e[2], m.e[4], cmul(m.e[1], m.e[5])));
+    m.e[7] = cconj(cfms(m.e[0], m.e[5], cmul(m.e[2], m.e[3])));
+    m.e[8] = cconj(cfms(m.e[1], m.e[3], cmul(m.e[0], m.e[4])));
 }
 
 __device__ __forceinline__ M3 m3_load12(const double2 *__restrict__ base, int V, int s)
@@ -108,9 +144,8 @@ __device__ __forceinline__ M3 m3_mul(const M3 &a, const M3 &b)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             double2 acc = cmul(a.e[i * 3], b.e[j]);
-            acc = cadd(acc, cmul(a.e[i * 3 + 1], b.e[3 + j]));
-            acc = cadd(acc, cmul(a.e[i * 3 + 2], b.e[6 + j]));
-            c.e[i * 3 + j] = acc;
+            acc = cfma(a.e[i * 3 + 1], b.e[3 + j], acc);
+            c.e[i * 3 + j] = cfma(a.e[i * 3 + 2], b.e[6 + j], acc);
         }
     return c;
 }
@@ -124,9 +159,8 @@ __device__ __forceinline__ M3 m3_mul_dag(const M3 &a, const M3 &b)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             double2 acc = cmulc(a.e[i * 3], b.e[j * 3]);
-            acc = cadd(acc, cmulc(a.e[i * 3 + 1], b.e[j * 3 + 1]));
-            acc = cadd(acc, cmulc(a.e[i * 3 + 2], b.e[j * 3 + 2]));
-            c.e[i * 3 + j] = acc;
+            acc = cfmac(a.e[i * 3 + 1], b.e[j * 3 + 1], acc);
+            c.e[i * 3 + j] = cfmac(a.e[i * 3 + 2], b.e[j * 3 + 2], acc);
         }
     return c;
 }
@@ -140,9 +174,8 @@ __device__ __forceinline__ M3 m3_dag_mul(const M3 &a, const M3 &b)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             double2 acc = ccmul(a.e[i], b.e[j]);
-            acc = cadd(acc, ccmul(a.e[3 + i], b.e[3 + j]));
-            acc = cadd(acc, ccmul(a.e[6 + i], b.e[6 + j]));
-            c.e[i * 3 + j] = acc;
+            acc = ccfma(a.e[3 + i], b.e[3 + j], acc);
+            c.e[i * 3 + j] = ccfma(a.e[6 + i], b.e[6 + j], acc);
         }
     return c;
 }
@@ -200,14 +233,14 @@ __device__ __forceinline__ M3 m3_mul_mul_dag_rows(const M3 &a, const M3 &b, cons
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             double2 acc = cmul(a.e[i * 3], b.e[l]);
-            acc = cadd(acc, cmul(a.e[i * 3 + 1], b.e[3 + l]));
-            ab[l] = cadd(acc, cmul(a.e[i * 3 + 2], b.e[6 + l]));
+            acc = cfma(a.e[i * 3 + 1], b.e[3 + l], acc);
+            ab[l] = cfma(a.e[i * 3 + 2], b.e[6 + l], acc);
         }
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             double2 acc = cmulc(ab[0], c.e[j * 3]);
-            acc = cadd(acc, cmulc(ab[1], c.e[j * 3 + 1]));
-            w.e[i * 3 + j] = cadd(acc, cmulc(ab[2], c.e[j * 3 + 2]));
+            acc = cfmac(ab[1], c.e[j * 3 + 1], acc);
+            w.e[i * 3 + j] = cfmac(ab[2], c.e[j * 3 + 2], acc);
         }
     }
     m3_row2(w);
@@ -262,9 +295,7 @@ __device__ __forceinline__ void m3_reunit(M3 &m)
     m.e[3] = cscale(m.e[3], i1);
     m.e[4] = cscale(m.e[4], i1);
     m.e[5] = cscale(m.e[5], i1);
-    m.e[6] = cconj(csub(cmul(m.e[1], m.e[5]), cmul(m.e[2], m.e[4])));
-    m.e[7] = cconj(csub(cmul(m.e[2], m.e[3]), cmul(m.e[0], m.e[5])));
-    m.e[8] = cconj(csub(cmul(m.e[0], m.e[4]), cmul(m.e[1], m.e[3])));
+    m3_row2(m);
 }
 
 // ---------------------------------------------------------------- sums
