@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the method's data-parallel kernel runs on one GPU's share); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
