@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#define GF_KERNEL_SOURCE
 #include "gf_internal.h"
 
 namespace gfk {

@@ -7,6 +7,17 @@
 
 namespace gfk {
 
+// Device pointers of the configuration table carry the global address space
+// in the device code of the kernel sources (those that include gf_device.h),
+// so that accesses through them are global (not flat) memory instructions:
+// flat accesses also count as LDS operations, and every wait for LDS would
+// then wait for them as well. The layout is the same (64-bit pointers).
+#if defined(__HIP_DEVICE_COMPILE__) && defined(GF_KERNEL_SOURCE)
+#define GF_GLOBAL __attribute__((address_space(1)))
+#else
+#define GF_GLOBAL
+#endif
+
 constexpr int kMaxCfg = 64;        // configurations per batch context
 constexpr int kHist = 256;         // device ring of (F, theta) per configuration
 constexpr int kSiteBlock = 256;    // work-items per site-parallel block
@@ -64,21 +75,21 @@ struct Cfg {
     int ntile[3];         // tiles along x, y, z (tile mode)
     int tch;              // t-slices marched by one block
     int nblk_march;       // nb3 * (Lt / tch): blocks of the marching kernels
-    double2 *U;           // links [4][3][3][V] (the caller's array)
-    double2 *U12[2];      // two-row links [4][2][3][V], two buffers (workspace)
-    double2 *g12;         // two-row gauge field [2][3][V] (workspace)
-    float2 *U12f[2];      // the same two link buffers in single-precision storage (link_prec 1)
-    float2 *g12f;         // two-row g in single-precision storage
-    void *fields;         // packed transform fields [4][V], double2 or float2
-    double2 *g;           // gauge field [3][3][V]
-    double *partials;     // [nblk_march or nblk_site][4]: (F hi, F lo, theta hi, theta lo)
-    Ctrl *ctrl;
-    const double *sin2;   // 4 sin^2(pi n / L_mu), axis mu at sin2 + sin2_off[mu]
+    GF_GLOBAL double2 *U;        // links [4][3][3][V] (the caller's array)
+    GF_GLOBAL double2 *U12[2];   // two-row links [4][2][3][V], two buffers (workspace)
+    GF_GLOBAL double2 *g12;      // two-row gauge field [2][3][V] (workspace)
+    GF_GLOBAL float2 *U12f[2];   // the same two link buffers in single-precision storage (link_prec 1)
+    GF_GLOBAL float2 *g12f;      // two-row g in single-precision storage
+    GF_GLOBAL void *fields;      // packed transform fields [4][V], double2 or float2
+    GF_GLOBAL double2 *g;        // gauge field [3][3][V]
+    GF_GLOBAL double *partials;  // [nblk_march or nblk_site][4]: (F hi, F lo, theta hi, theta lo)
+    GF_GLOBAL Ctrl *ctrl;
+    GF_GLOBAL const double *sin2;  // 4 sin^2(pi n / L_mu), axis mu at sin2 + sin2_off[mu]
     int sin2_off[4];
-    const void *tw;       // twiddles exp(-2 pi i e / L_mu), axis mu at tw + tw_off[mu]
+    GF_GLOBAL const void *tw;    // twiddles exp(-2 pi i e / L_mu), axis mu at tw + tw_off[mu]
     int tw_off[4];
     double kfac;          // (alpha / 2) * p2max / V
-    void *kmom;           // K(p) per momentum site [V], double (FP64 transform) or float (FP32)
+    GF_GLOBAL void *kmom;        // K(p) per momentum site [V], double (FP64 transform) or float (FP32)
     int reunit_every;
     FftAxis ax[4];
     int xyQ, nxy;         // xy pass: Q consecutive xy-planes per tile, nxy tiles per field
@@ -109,6 +120,7 @@ struct Launch {
     int total_zt_tiles;
     int xy_cap, zt_cap;            // 2D tile capacity variant (1024, 2048 or 4096 elements)
     int xy_th, zt_th;              // work-group size of the 2D passes (capacity / elements per work-item)
+    int xy_fpb, zt_fpb;            // fields per work-group of the 2D passes (the next one prefetched)
     int xy_p2, zt_p2;              // some configuration has power-of-two extents in that pass
     int xy_gen, zt_gen;            // some configuration has not
     int ax_p2[4], ax_gen[4];       // same for the 1D passes of each axis

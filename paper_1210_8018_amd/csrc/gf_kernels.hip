@@ -5,6 +5,8 @@
 // control block says "done" return at once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gf_device.h"
 #include "gf_internal.h"
 
@@ -479,46 +481,71 @@ __device__ __forceinline__ void tile_load_contig(T2 *buf, const T2 *__restrict__
     }
 }
 
-// Rows of `rowlen` elements with `pad` LDS elements after each row.
-template <typename T2, int CAP, int TH>
-__device__ __forceinline__ void tile_load_padded(T2 *buf, const T2 *__restrict__ g, int n, int rowlen, int pad)
+// Register-staged tiles of the 2D passes. tile_fetch issues the global loads
+// of a work-item's elements (element i = threadIdx.x + k TH of the tile) into
+// registers; tile_put / tile_get move them to and from LDS. A barrier waits
+// only for LDS operations, so the fetch of the next field of a tile stays in
+// flight while the current one is transformed. Nothing before the global
+// stores branches on the tile size: fetches clamp the element index (n >= 1),
+// and LDS accesses of elements past n go to the spare last slot of the
+// CAP + CAP/8 data area, which no element of a tile smaller than CAP uses
+// (the row padding stays below CAP/8). Registers are copied component-wise:
+// whole-vector assignment keeps the array out of registers across the loop.
+template <int CAP, int TH>
+__host__ __device__ constexpr int tile_regs() { return (CAP + TH - 1) / TH; }
+
+template <int CAP>
+__host__ __device__ constexpr int spare_slot() { return CAP + CAP / 8 - 1; }
+
+template <typename T2>
+__device__ __forceinline__ void cp2(T2 &d, const T2 &v)
 {
-    constexpr int NL = (CAP + TH - 1) / TH;
-    if (is_p2(rowlen)) {
-        const int lr = ilog2(rowlen);
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int i = threadIdx.x + k * TH;
-            if (i < n) buf[i + pad * (i >> lr)] = g[i];
-        }
-        return;
-    }
-    const FastDiv fr = fast_div(rowlen);
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int i = threadIdx.x + k * TH;
-        if (i < n) buf[i + pad * fdiv(i, fr)] = g[i];
-    }
+    d.x = v.x;
+    d.y = v.y;
 }
 
-template <typename T2, int CAP, int TH>
-__device__ __forceinline__ void tile_store_padded(T2 *__restrict__ g, const T2 *buf, int n, int rowlen, int pad)
+template <typename T2, int CAP, int TH, int NL>
+__device__ __forceinline__ void tile_fetch(T2 (&r)[NL], const T2 *__restrict__ g, int n)
 {
-    constexpr int NL = (CAP + TH - 1) / TH;
-    if (is_p2(rowlen)) {
-        const int lr = ilog2(rowlen);
+    static_assert(NL == tile_regs<CAP, TH>(), "one register per tile element of a work-item");
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int i = threadIdx.x + k * TH;
-            if (i < n) g[i] = buf[i + pad * (i >> lr)];
-        }
-        return;
-    }
+    for (int k = 0; k < NL; ++k) cp2(r[k], g[min(threadIdx.x + k * TH, (unsigned)n - 1)]);
+}
+
+// LDS slot of element i of a tile of rows of `rowlen` with `pad` after each.
+template <int CAP>
+__device__ __forceinline__ int padded_slot(int i, int n, int lr, FastDiv fr, int pad)
+{
+    return i < n ? i + pad * (lr >= 0 ? (i >> lr) : fdiv(i, fr)) : spare_slot<CAP>();
+}
+
+template <typename T2, int CAP, int TH, int NL>
+__device__ __forceinline__ void tile_put_padded(T2 *buf, const T2 (&r)[NL], int n, int rowlen, int pad)
+{
+    static_assert(NL == tile_regs<CAP, TH>(), "one register per tile element of a work-item");
+    const int lr = is_p2(rowlen) ? ilog2(rowlen) : -1;
     const FastDiv fr = fast_div(rowlen);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) cp2(buf[padded_slot<CAP>(threadIdx.x + k * TH, n, lr, fr, pad)], r[k]);
+}
+
+template <typename T2, int CAP, int TH, int NL>
+__device__ __forceinline__ void tile_get_padded(T2 (&r)[NL], const T2 *buf, int n, int rowlen, int pad)
+{
+    static_assert(NL == tile_regs<CAP, TH>(), "one register per tile element of a work-item");
+    const int lr = is_p2(rowlen) ? ilog2(rowlen) : -1;
+    const FastDiv fr = fast_div(rowlen);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) cp2(r[k], buf[padded_slot<CAP>(threadIdx.x + k * TH, n, lr, fr, pad)]);
+}
+
+template <typename T2, int CAP, int TH, int NL>
+__device__ __forceinline__ void tile_store_regs(T2 *__restrict__ g, const T2 (&r)[NL], int n)
+{
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int i = threadIdx.x + k * TH;
-        if (i < n) g[i] = buf[i + pad * fdiv(i, fr)];
+        if (i < n) cp2(g[i], r[k]);
     }
 }
 
@@ -557,33 +584,56 @@ __device__ __forceinline__ int rows_lds(int r, int p, int lp, FastDiv frpp, int 
     return (r << lp) + p + pad * (lrpp >= 0 ? (r >> lrpp) : fdiv(r, frpp));
 }
 
-template <typename T2, int CAP, int TH>
-__device__ __forceinline__ void tile_load_rows_padded(T2 *buf, const T2 *__restrict__ g, int P, int rows, size_t rs,
-                                                      int rpp, int pad)
+// Row tiles (the zt pass): element (r, p), r < rows, of rows of P; the
+// same register and LDS conventions as the padded tiles above.
+template <typename T2, int CAP, int TH, int NL>
+__device__ __forceinline__ void tile_fetch_rows(T2 (&v)[NL], const T2 *__restrict__ g, int P, int rows, size_t rs)
 {
-    constexpr int NL = (CAP + TH - 1) / TH;
-    const int lp = ilog2(P), lrpp = is_p2(rpp) ? ilog2(rpp) : -1;
-    const FastDiv frpp = fast_div(rpp);
+    static_assert(NL == tile_regs<CAP, TH>(), "one register per tile element of a work-item");
+    const int lp = ilog2(P);
     const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int r = r0 + k * dr;
-        if (r < rows) buf[rows_lds(r, p, lp, frpp, lrpp, pad)] = g[(size_t)r * rs + p];
-    }
+    for (int k = 0; k < NL; ++k) cp2(v[k], g[(size_t)min(r0 + k * dr, rows - 1) * rs + p]);
 }
 
-template <typename T2, int CAP, int TH>
-__device__ __forceinline__ void tile_store_rows_padded(T2 *__restrict__ g, const T2 *buf, int P, int rows, size_t rs,
-                                                       int rpp, int pad)
+template <int CAP>
+__device__ __forceinline__ int rows_slot(int r, int p, int rows, int lp, FastDiv frpp, int lrpp, int pad)
 {
-    constexpr int NL = (CAP + TH - 1) / TH;
+    return r < rows ? rows_lds(r, p, lp, frpp, lrpp, pad) : spare_slot<CAP>();
+}
+
+template <typename T2, int CAP, int TH, int NL>
+__device__ __forceinline__ void tile_put_rows(T2 *buf, const T2 (&v)[NL], int P, int rows, int rpp, int pad)
+{
+    static_assert(NL == tile_regs<CAP, TH>(), "one register per tile element of a work-item");
     const int lp = ilog2(P), lrpp = is_p2(rpp) ? ilog2(rpp) : -1;
     const FastDiv frpp = fast_div(rpp);
     const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
 #pragma unroll
+    for (int k = 0; k < NL; ++k) cp2(buf[rows_slot<CAP>(r0 + k * dr, p, rows, lp, frpp, lrpp, pad)], v[k]);
+}
+
+template <typename T2, int CAP, int TH, int NL>
+__device__ __forceinline__ void tile_get_rows(T2 (&v)[NL], const T2 *buf, int P, int rows, int rpp, int pad)
+{
+    static_assert(NL == tile_regs<CAP, TH>(), "one register per tile element of a work-item");
+    const int lp = ilog2(P), lrpp = is_p2(rpp) ? ilog2(rpp) : -1;
+    const FastDiv frpp = fast_div(rpp);
+    const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) cp2(v[k], buf[rows_slot<CAP>(r0 + k * dr, p, rows, lp, frpp, lrpp, pad)]);
+}
+
+template <typename T2, int CAP, int TH, int NL>
+__device__ __forceinline__ void tile_store_rows_regs(T2 *__restrict__ g, const T2 (&v)[NL], int P, int rows,
+                                                    size_t rs)
+{
+    const int lp = ilog2(P);
+    const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
+#pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int r = r0 + k * dr;
-        if (r < rows) g[(size_t)r * rs + p] = buf[rows_lds(r, p, lp, frpp, lrpp, pad)];
+        if (r < rows) cp2(g[(size_t)r * rs + p], v[k]);
     }
 }
 
@@ -733,7 +783,7 @@ __device__ __forceinline__ void stage_ip(T2 *buf, const T2 *__restrict__ tw, int
 
 // All stages of one axis over pencils laid out as in stage_ip.
 template <typename T2, int MAXE, int TH>
-__device__ void fft_axis_ip(T2 *buf, const T2 *tw, const FftAxis &A, int npen, int m1, int a1, int a2, int ls,
+__device__ __forceinline__ void fft_axis_ip(T2 *buf, const T2 *tw, const FftAxis &A, int npen, int m1, int a1, int a2, int ls,
                             int sign, bool k_fast)
 {
     int Ns = 1;
@@ -806,7 +856,7 @@ __device__ __forceinline__ void stage_ip_p2(T2 *buf, const T2 *__restrict__ tw, 
 
 // fft_axis_ip for a power-of-two axis and power-of-two pencil counts.
 template <typename T2, int MAXE, int TH>
-__device__ void fft_axis_ip_p2(T2 *buf, const T2 *tw, const FftAxis &A, int lnpen, int lm1, int a1, int a2, int ls,
+__device__ __forceinline__ void fft_axis_ip_p2(T2 *buf, const T2 *tw, const FftAxis &A, int lnpen, int lm1, int a1, int a2, int ls,
                                int sign)
 {
     const int lL = ilog2(A.L);
@@ -853,23 +903,14 @@ __device__ __forceinline__ void xy_transform(T2 *buf, const T2 *twx, const T2 *t
 __device__ __forceinline__ bool xy_is_p2(const Cfg &C) { return is_p2(C.dims[0]) && is_p2(C.dims[1]) && is_p2(C.xyQ); }
 __device__ __forceinline__ bool zt_is_p2(const Cfg &C) { return is_p2(C.dims[2]) && is_p2(C.dims[3]); }
 
-// LDS index of element i of an xy tile in global (unpadded) order.
-__device__ __forceinline__ int xy_lds(const Cfg &C, int i)
-{
-    const int Lx = C.dims[0];
-    return i + C.xyPad * (is_p2(Lx) ? (i >> ilog2(Lx)) : fdiv(i, fast_div(Lx)));
-}
-
-// Pass over (x, y): tile = Q consecutive xy-planes of one field. LDS: CAP
-// data elements, then the twiddles of x (tw2 entries reserved) and y.
 template <typename T2, int CAP, int TH, bool P2>
-__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_xy(
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(CAP / TH >= 8 ? 2 : 4))) void k_fft_xy(
     const Cfg *__restrict__ cfgs, const Batch *__restrict__ B, int sign, void *fields_override, int respect_done,
-    int tw2)
+    int tw2, int nf, int fpb)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int field = blockIdx.y;
+    const int f0 = blockIdx.y * fpb, f1 = min(nf, f0 + fpb);
     const int c = find_cfg(B->off_xy, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
@@ -879,28 +920,42 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     T2 *buf = (T2 *)smem;
     T2 *twx = buf + CAP + CAP / 8;
     T2 *twy = twx + tw2;
+    T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)f0 * C.V + (size_t)t * n;
+    constexpr int NL = tile_regs<CAP, TH>();
+    T2 pre[NL], out[NL];
+    tile_fetch<T2, CAP, TH>(pre, g, n);
     load_twiddles(twx, C, 0);
     load_twiddles(twy, C, 1);
-    T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)field * C.V + (size_t)t * n;
-    tile_load_padded<T2, CAP, TH>(buf, g, n, C.dims[0], C.xyPad);
+    tile_put_padded<T2, CAP, TH>(buf, pre, n, C.dims[0], C.xyPad);
     __syncthreads();
-    xy_transform<T2, CAP, TH, P2>(buf, twx, twy, C, C.xyQ, sign);
-    tile_store_padded<T2, CAP, TH>(g, buf, n, C.dims[0], C.xyPad);
+    for (int f = f0; f < f1; ++f, g += C.V) {
+        const bool more = f + 1 < f1;
+        if (more) tile_fetch<T2, CAP, TH>(pre, g + C.V, n);
+        xy_transform<T2, CAP, TH, P2>(buf, twx, twy, C, C.xyQ, sign);
+        // a work-item reads its own LDS slots, refills them with the next
+        // field, then stores: the wait for the fetch precedes the stores
+        tile_get_padded<T2, CAP, TH>(out, buf, n, C.dims[0], C.xyPad);
+        if (more) tile_put_padded<T2, CAP, TH>(buf, pre, n, C.dims[0], C.xyPad);
+        tile_store_regs<T2, CAP, TH>(g, out, n);
+        __syncthreads();
+    }
 }
 
-// Pass over (z, t): tile = P consecutive xy-sites times the whole (z, t) plane
-// of one field, LDS layout [t][z][p]. mode 0: plain transform with `sign`;
-// mode 1: forward, multiplication by K(p) = (alpha/2)(p2max/p2)/V with
-// K(0) = 0 (Eq. 2; 1/V normalises the backward transform), backward.
+// Pass over (z, t): tile = P consecutive xy-sites times the whole (z, t)
+// plane, LDS layout [t][z][p]; fields [fpb y, fpb (y + 1)) of nf one after the
+// other, the next fetched during the current transform. mode 0: plain
+// transform with `sign`; mode 1: forward, multiplication by K(p) =
+// (alpha/2)(p2max/p2)/V with K(0) = 0 (Eq. 2; 1/V normalises the backward
+// transform), backward.
 template <typename T2, int CAP, int TH, bool P2>
-__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_zt(
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(CAP / TH >= 8 ? 2 : 4))) void k_fft_zt(
     const Cfg *__restrict__ cfgs, const Batch *__restrict__ B, int mode, int sign, void *fields_override,
-    int respect_done, int tw2)
+    int respect_done, int tw2, int nf, int fpb)
 {
     using T = typename Cx<T2>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int field = blockIdx.y;
+    const int f0 = blockIdx.y * fpb, f1 = min(nf, f0 + fpb);
     const int c = find_cfg(B->off_zt, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
@@ -912,60 +967,66 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4))) void k_
     T2 *buf = (T2 *)smem;
     T2 *twz = buf + CAP + CAP / 8;
     T2 *twt = twz + tw2;
-    load_twiddles(twz, C, 2);
-    load_twiddles(twt, C, 3);
-    T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)field * C.V + i0;
+    T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)f0 * C.V + i0;
     // LDS layout [t][z][p] with t-planes Tp = P Lz + ztPad elements apart
     const int Tp = P * Lz + C.ztPad;
     const int rows = Lz * Lt;
-    tile_load_rows_padded<T2, CAP, TH>(buf, g, P, rows, V2, Lz, C.ztPad);
-    // K(p) of this tile's elements, same (row, p) assignment as the tile load
-    constexpr int NL = (CAP + TH - 1) / TH;
+    constexpr int NL = tile_regs<CAP, TH>();
+    T2 pre[NL], out[NL];
+    tile_fetch_rows<T2, CAP, TH>(pre, g, P, rows, V2);
+    // K(p) of this tile's elements, same (row, p) assignment as the tile
+    // fetch; shared by all fields of the tile
     const int lp = ilog2(P), lz = is_p2(Lz) ? ilog2(Lz) : -1;
     const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
     T kreg[NL];
     if (mode == 1) {
         const T *__restrict__ Km = (const T *)C.kmom + i0;
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int r = r0 + k * dr;
-            kreg[k] = (r < rows) ? Km[(size_t)r * V2 + p] : (T)0;
-        }
+        for (int k = 0; k < NL; ++k) kreg[k] = Km[(size_t)min(r0 + k * dr, rows - 1) * V2 + p];
     }
+    load_twiddles(twz, C, 2);
+    load_twiddles(twt, C, 3);
+    tile_put_rows<T2, CAP, TH>(buf, pre, P, rows, Lz, C.ztPad);
     __syncthreads();
     const int s0 = (mode == 1) ? -1 : sign;
     const int lt = P2 ? ilog2(Lt) : 0;
-    // z: pencils k = (p, t), start p + Tp t, stride P
-    // t: pencils k = (p, z), start k, stride Tp
-    if constexpr (P2) {
-        fft_axis_ip_p2<T2, CAP, TH>(buf, twz, C.ax[2], lp + lt, lp, 1, Tp, P, s0);
-        fft_axis_ip_p2<T2, CAP, TH>(buf, twt, C.ax[3], lp + lz, lp + lz, 1, 0, Tp, s0);
-    } else {
-        fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, s0, true);
-        fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, s0, true);
-    }
-    if (mode == 1) {
+    const FastDiv flz = fast_div(Lz);
+    for (int f = f0; f < f1; ++f, g += C.V) {
+        const bool more = f + 1 < f1;
+        if (more) tile_fetch_rows<T2, CAP, TH>(pre, g + C.V, P, rows, V2);
+        // z: pencils k = (p, t), start p + Tp t, stride P
+        // t: pencils k = (p, z), start k, stride Tp
+        if constexpr (P2) {
+            fft_axis_ip_p2<T2, CAP, TH>(buf, twz, C.ax[2], lp + lt, lp, 1, Tp, P, s0);
+            fft_axis_ip_p2<T2, CAP, TH>(buf, twt, C.ax[3], lp + lz, lp + lz, 1, 0, Tp, s0);
+        } else {
+            fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, s0, true);
+            fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, s0, true);
+        }
+        if (mode == 1) {
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int r = r0 + k * dr;
-            if (r < rows) {
-                const int li = rows_lds(r, p, lp, fast_div(Lz), lz, C.ztPad);
+            for (int k = 0; k < NL; ++k) {
+                const int li = rows_slot<CAP>(r0 + k * dr, p, rows, lp, flz, lz, C.ztPad);
                 T2 v = buf[li];
                 v.x *= kreg[k];
                 v.y *= kreg[k];
                 buf[li] = v;
             }
+            __syncthreads();
+            if constexpr (P2) {
+                fft_axis_ip_p2<T2, CAP, TH>(buf, twt, C.ax[3], lp + lz, lp + lz, 1, 0, Tp, +1);
+                fft_axis_ip_p2<T2, CAP, TH>(buf, twz, C.ax[2], lp + lt, lp, 1, Tp, P, +1);
+            } else {
+                fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, +1, true);
+                fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, +1, true);
+            }
         }
+        // own slots out, next field in, then the stores (see k_fft_xy)
+        tile_get_rows<T2, CAP, TH>(out, buf, P, rows, Lz, C.ztPad);
+        if (more) tile_put_rows<T2, CAP, TH>(buf, pre, P, rows, Lz, C.ztPad);
+        tile_store_rows_regs<T2, CAP, TH>(g, out, P, rows, V2);
         __syncthreads();
-        if constexpr (P2) {
-            fft_axis_ip_p2<T2, CAP, TH>(buf, twt, C.ax[3], lp + lz, lp + lz, 1, 0, Tp, +1);
-            fft_axis_ip_p2<T2, CAP, TH>(buf, twz, C.ax[2], lp + lt, lp, 1, Tp, P, +1);
-        } else {
-            fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, +1, true);
-            fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, +1, true);
-        }
     }
-    tile_store_rows_padded<T2, CAP, TH>(g, buf, P, rows, V2, Lz, C.ztPad);
 }
 
 // ============================================================ S4: g = 1 + Delta~, projected
@@ -1046,21 +1107,24 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
     T2 *buf = (T2 *)smem;
     T2 *twx = buf + CAP + CAP / 8;
     T2 *twy = twx + tw2;
+    const T2 *__restrict__ src = (const T2 *)C.fields + site0;
+    T2 val[kFields][MS];
+    T2 pre[MS];
+    tile_fetch<T2, CAP, TH>(pre, src, n);
     load_twiddles(twx, C, 0);
     load_twiddles(twy, C, 1);
-    T2 val[kFields][MS];
+    tile_put_padded<T2, CAP, TH>(buf, pre, n, C.dims[0], C.xyPad);
+    __syncthreads();
 #pragma unroll
     for (int f = 0; f < kFields; ++f) {
-        const T2 *__restrict__ src = (const T2 *)C.fields + (size_t)f * C.V + site0;
-        tile_load_padded<T2, CAP, TH>(buf, src, n, C.dims[0], C.xyPad);
-        __syncthreads();
+        if (f + 1 < kFields) tile_fetch<T2, CAP, TH>(pre, src + (size_t)(f + 1) * C.V, n);
         xy_transform<T2, CAP, TH, P2>(buf, twx, twy, C, C.xyQ, +1);
-#pragma unroll
-        for (int k = 0; k < MS; ++k) {
-            const int i = threadIdx.x + k * TH;
-            if (i < n) val[f][k] = buf[xy_lds(C, i)];
+        // own slots out, next field in (the fetch had the transform to land)
+        tile_get_padded<T2, CAP, TH>(val[f], buf, n, C.dims[0], C.xyPad);
+        if (f + 1 < kFields) {
+            tile_put_padded<T2, CAP, TH>(buf, pre, n, C.dims[0], C.xyPad);
+            __syncthreads();
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < MS; ++k) {
@@ -1797,14 +1861,16 @@ static size_t lds2d(int cap, int tw2, int tw_total)
 // power-of-two extents in that pass, and the general one if some has not;
 // each instance leaves the other's configurations at once.
 template <typename T2>
-static hipError_t run_xy(const Launch &L, dim3 grid, int sign, void *fo, int rd)
+static hipError_t run_xy(const Launch &L, int nf, int sign, void *fo, int rd)
 {
+    const int fpb = std::max(1, std::min(L.xy_fpb, nf));
+    const dim3 grid(L.total_xy_tiles, (nf + fpb - 1) / fpb);
     const size_t sh = lds2d<T2>(L.xy_cap, L.xy_tw2, L.xy_tw_total);
     int launched = 0;
 #define X(C_, T_, P2_)                                                                                            \
     if (L.xy_cap == C_ && L.xy_th == T_ && (P2_ ? L.xy_p2 : L.xy_gen)) {                                          \
         hipLaunchKernelGGL((k_fft_xy<T2, C_, T_, P2_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, sign, fo, rd, \
-                           L.xy_tw2);                                                                             \
+                           L.xy_tw2, nf, fpb);                                                                    \
         ++launched;                                                                                               \
     }
     GF_2D_VARIANTS(X)
@@ -1813,14 +1879,16 @@ static hipError_t run_xy(const Launch &L, dim3 grid, int sign, void *fo, int rd)
 }
 
 template <typename T2>
-static hipError_t run_zt(const Launch &L, dim3 grid, int mode, int sign, void *fo, int rd)
+static hipError_t run_zt(const Launch &L, int nf, int mode, int sign, void *fo, int rd)
 {
+    const int fpb = std::max(1, std::min(L.zt_fpb, nf));
+    const dim3 grid(L.total_zt_tiles, (nf + fpb - 1) / fpb);
     const size_t sh = lds2d<T2>(L.zt_cap, L.zt_tw2, L.zt_tw_total);
     int launched = 0;
 #define X(C_, T_, P2_)                                                                                            \
     if (L.zt_cap == C_ && L.zt_th == T_ && (P2_ ? L.zt_p2 : L.zt_gen)) {                                          \
         hipLaunchKernelGGL((k_fft_zt<T2, C_, T_, P2_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, mode, sign,   \
-                           fo, rd, L.zt_tw2);                                                                     \
+                           fo, rd, L.zt_tw2, nf, fpb);                                                            \
         ++launched;                                                                                               \
     }
     GF_2D_VARIANTS(X)
@@ -1846,16 +1914,14 @@ static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
 
 hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done)
 {
-    const dim3 grid(L.total_xy_tiles, nfields);
-    return L.fp32 ? run_xy<float2>(L, grid, sign, fields_override, respect_done)
-                  : run_xy<double2>(L, grid, sign, fields_override, respect_done);
+    return L.fp32 ? run_xy<float2>(L, nfields, sign, fields_override, respect_done)
+                  : run_xy<double2>(L, nfields, sign, fields_override, respect_done);
 }
 
 hipError_t launch_fft_zt(const Launch &L, int mode, int sign, void *fields_override, int nfields, int respect_done)
 {
-    const dim3 grid(L.total_zt_tiles, nfields);
-    return L.fp32 ? run_zt<float2>(L, grid, mode, sign, fields_override, respect_done)
-                  : run_zt<double2>(L, grid, mode, sign, fields_override, respect_done);
+    return L.fp32 ? run_zt<float2>(L, nfields, mode, sign, fields_override, respect_done)
+                  : run_zt<double2>(L, nfields, mode, sign, fields_override, respect_done);
 }
 
 hipError_t launch_fft_zt_scale(const Launch &L, int respect_done)

@@ -652,6 +652,14 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
     c->L.zt_cap = cap_for(zt_max);
     c->L.xy_th = c->L.xy_cap / tl.xy_ept;
     c->L.zt_th = c->L.zt_cap / tl.zt_ept;
+    // fields per work-group of the 2D passes (GF_XY_FPB, GF_ZT_FPB: 1 to 4)
+    auto fpb = [](const char *name) {
+        const char *e = getenv(name);
+        const int v = e ? atoi(e) : kFields;
+        return (v >= 1 && v <= kFields) ? v : kFields;
+    };
+    c->L.xy_fpb = fpb("GF_XY_FPB");
+    c->L.zt_fpb = fpb("GF_ZT_FPB");
     c->L.xy_p2 = xy_p2;
     c->L.zt_p2 = zt_p2;
     c->L.xy_gen = xy_gen;
