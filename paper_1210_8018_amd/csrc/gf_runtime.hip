@@ -625,9 +625,16 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
         const char *np = getenv("GF_NO_LDS_PAD");
         const int xycap = C.xyQ * C.V2 <= 1024 ? 1024 : (C.xyQ * C.V2 <= 2048 ? 2048 : 4096);
         C.xyPad = (!np && C.dims[1] * C.xyQ <= xycap / 8) ? 1 : 0;
+        // zt tile: t-planes Tp = P Lz + ztPad elements apart with Tp = P (mod
+        // 32), so that the lanes of one z-pencil access (p fastest, then t)
+        // fall on distinct LDS banks: 16 consecutive lanes for 16-byte
+        // elements (mod 16), 32 for 8-byte elements (mod 32)
         const int ztn = C.ztP * C.dims[2] * C.dims[3];
         const int ztcap = ztn <= 1024 ? 1024 : (ztn <= 2048 ? 2048 : 4096);
-        C.ztPad = (!np && 4 * C.dims[3] <= ztcap / 8) ? 4 : 0;
+        const int r = C.ztP - C.ztP * C.dims[2];
+        int zp = ((r % 32) + 32) % 32;
+        if (zp * C.dims[3] > ztcap / 8) zp = ((r % 16) + 16) % 16;
+        C.ztPad = (!np && zp * C.dims[3] <= ztcap / 8) ? zp : 0;
     }
     std::vector<int> all(c->ncfg);
     for (int k = 0; k < c->ncfg; ++k) all[k] = k;
