@@ -823,27 +823,50 @@ gf_status choose_schedule(gf_ctx c, int requested)
                     cands.push_back({kSchedXYZT, t});
                 }
         }
-    double best = 1e300;
-    Cand pick = cands[0];
     hipEvent_t e0 = take_event(c), e1 = take_event(c);
     if (!e0 || !e1) return GF_ERR_HIP;
     const bool timing = c->timing;
     c->timing = false;
-    for (const Cand &cd : cands) {
+    // time of `reps` transform passes (after one warm-up pass) of a candidate
+    auto time_cand = [&](const Cand &cd, int reps, double &ms_out) -> gf_status {
         gf_status st = apply_schedule(c, cd.sched, cd.tiles);
         if (st != GF_OK) return st;
-        HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, nullptr));  // warm-up
+        HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, nullptr));
         HIPCHK(c, hipEventRecord(e0, c->stream));
-        for (int r = 0; r < 3; ++r) HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, nullptr));
+        for (int r = 0; r < reps; ++r) HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, nullptr));
         HIPCHK(c, hipEventRecord(e1, c->stream));
         HIPCHK(c, hipEventSynchronize(e1));
         float ms = 0.f;
         HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            pick = cd;
-        }
+        ms_out = ms / reps;
+        return GF_OK;
+    };
+    // round 1: every candidate briefly; round 2: the four fastest, twice
+    // more at more repetitions, the best of the three times kept (the
+    // candidates are often within a few per cent of each other)
+    std::vector<std::pair<double, int>> t1;
+    for (int k = 0; k < (int)cands.size(); ++k) {
+        double ms;
+        gf_status st = time_cand(cands[k], 3, ms);
+        if (st != GF_OK) return st;
+        t1.push_back({ms, k});
     }
+    std::sort(t1.begin(), t1.end());
+    t1.resize(std::min<size_t>(t1.size(), 4));
+    double best = 1e300;
+    Cand pick = cands[t1[0].second];
+    for (int round = 0; round < 2; ++round)
+        for (auto &e : t1) {
+            double ms;
+            gf_status st = time_cand(cands[e.second], 8, ms);
+            if (st != GF_OK) return st;
+            e.first = std::min(e.first, ms);
+        }
+    for (const auto &e : t1)
+        if (e.first < best) {
+            best = e.first;
+            pick = cands[e.second];
+        }
     c->timing = timing;
     c->ev_used = 0;
     // the fields were transformed in place: measure again so they hold Delta
