@@ -355,11 +355,13 @@ __device__ __forceinline__ void stage(const T2 *__restrict__ src, T2 *__restrict
         T2 a[R];
 #pragma unroll
         for (int m = 0; m < R; ++m) a[m] = src[k * ks + (j + m * nb) * ls];
+        if (Ns > 1) {  // the first stage's twiddles are all 1
 #pragma unroll
-        for (int m = 1; m < R; ++m) {
-            T2 w = tw[m * kk * tstep];
-            if (sign > 0) w.y = -w.y;
-            a[m] = t_mul(a[m], w);
+            for (int m = 1; m < R; ++m) {
+                T2 w = tw[m * kk * tstep];
+                if (sign > 0) w.y = -w.y;
+                a[m] = t_mul(a[m], w);
+            }
         }
         if constexpr (R == 2)
             dft2(a);
@@ -427,11 +429,13 @@ __device__ __forceinline__ void stage_p2(const T2 *__restrict__ src, T2 *__restr
             a[m] = src[k_fast ? k + (l << lP) : (k << lL) + l];
         }
         const int tb = kk << ltstep;
+        if (lNs > 0) {  // the first stage's twiddles are all 1
 #pragma unroll
-        for (int m = 1; m < R; ++m) {
-            T2 w = tw[m * tb];
-            if (sign > 0) w.y = -w.y;
-            a[m] = t_mul(a[m], w);
+            for (int m = 1; m < R; ++m) {
+                T2 w = tw[m * tb];
+                if (sign > 0) w.y = -w.y;
+                a[m] = t_mul(a[m], w);
+            }
         }
         if constexpr (R == 2)
             dft2(a);
@@ -752,11 +756,13 @@ __device__ __forceinline__ void stage_ip(T2 *buf, const T2 *__restrict__ tw, int
             const int kk = j - fdiv(j, fNs) * Ns;
 #pragma unroll
             for (int m = 0; m < R; ++m) v[i][m] = buf[base + (j + m * nb) * ls];
+            if (Ns > 1) {  // the first stage's twiddles are all 1
 #pragma unroll
-            for (int m = 1; m < R; ++m) {
-                T2 w = tw[m * kk * tstep];
-                if (sign > 0) w.y = -w.y;
-                v[i][m] = t_mul(v[i][m], w);
+                for (int m = 1; m < R; ++m) {
+                    T2 w = tw[m * kk * tstep];
+                    if (sign > 0) w.y = -w.y;
+                    v[i][m] = t_mul(v[i][m], w);
+                }
             }
             if constexpr (R == 2)
                 dft2(v[i]);
@@ -827,11 +833,13 @@ __device__ __forceinline__ void stage_ip_p2(T2 *buf, const T2 *__restrict__ tw, 
 #pragma unroll
             for (int m = 0; m < R; ++m) v[i][m] = buf[e0 + m * mstride];
             const int tb = kk << ltstep;
+            if (lNs > 0) {  // the first stage's twiddles are all 1
 #pragma unroll
-            for (int m = 1; m < R; ++m) {
-                T2 w = tw[m * tb];
-                if (sign > 0) w.y = -w.y;
-                v[i][m] = t_mul(v[i][m], w);
+                for (int m = 1; m < R; ++m) {
+                    T2 w = tw[m * tb];
+                    if (sign > 0) w.y = -w.y;
+                    v[i][m] = t_mul(v[i][m], w);
+                }
             }
             if constexpr (R == 2)
                 dft2(v[i]);
