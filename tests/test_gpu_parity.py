@@ -105,13 +105,8 @@ TILE_VARIANTS = [  # (xy target, xy elements per work-item, zt target, zt elemen
     (1024, 8, 2048, 4), (4096, 4, 2048, 8), (4096, 8, 4096, 4), (2048, 4, 1024, 8), (1024, 4, 4096, 8)]
 
 
-@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (12, 8, 6, 4), (24, 4, 2, 6), (4, 12, 4, 8), (16, 8, 4, 32)])
-@pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("tiles", TILE_VARIANTS)
-def test_2d_tile_variants_match_oracle(monkeypatch, dims, prec, tiles):
-    """Every (tile size, work-group size) instance of the 2D passes: transform and gauge vector."""
-    for name, v in zip(("GF_XY_TARGET", "GF_XY_EPT", "GF_ZT_TARGET", "GF_ZT_EPT"), tiles):
-        monkeypatch.setenv(name, str(v))
+def check_2d_passes(dims, prec):
+    """Gauge vector and forward/backward transform of the xy + zt schedule against the oracle."""
     V = int(np.prod(dims))
     U = random_links(dims, 0.4, 43)
     fx = GaugeFixer(dev(U), fft_prec=prec, fft_schedule=3)
@@ -127,6 +122,27 @@ def test_2d_tile_variants_match_oracle(monkeypatch, dims, prec, tiles):
         for k in range(2):
             ref = oracle.fft4d(dims, f[k], sign)
             assert np.max(np.abs(got[k] - ref)) < tol * np.max(np.abs(ref)), (sign, k)
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (12, 8, 6, 4), (24, 4, 2, 6), (4, 12, 4, 8), (16, 8, 4, 32)])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("tiles", TILE_VARIANTS)
+def test_2d_tile_variants_match_oracle(monkeypatch, dims, prec, tiles):
+    """Every (tile size, work-group size) instance of the 2D passes: transform and gauge vector."""
+    for name, v in zip(("GF_XY_TARGET", "GF_XY_EPT", "GF_ZT_TARGET", "GF_ZT_EPT"), tiles):
+        monkeypatch.setenv(name, str(v))
+    check_2d_passes(dims, prec)
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (12, 8, 6, 4), (27, 2, 4, 6), (16, 8, 4, 32)])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("fpb", [(1, 1), (3, 2), (2, 3)])
+def test_fields_per_workgroup_match_oracle(monkeypatch, dims, prec, fpb):
+    """The 2D passes with 1 to 3 of the 4 fields per work-group (a shorter last group, the
+    next field prefetched while the current one is transformed): transform and gauge vector."""
+    monkeypatch.setenv("GF_XY_FPB", str(fpb[0]))
+    monkeypatch.setenv("GF_ZT_FPB", str(fpb[1]))
+    check_2d_passes(dims, prec)
 
 
 @pytest.mark.parametrize("dims", SHAPES)
