@@ -841,8 +841,8 @@ gf_status choose_schedule(gf_ctx c, int requested)
         ms_out = ms / reps;
         return GF_OK;
     };
-    // round 1: every candidate briefly; round 2: the four fastest, twice
-    // more at more repetitions, the best of the three times kept (the
+    // first pass: every candidate briefly; then the four fastest twice more
+    // at more repetitions, the best of their three times kept (the
     // candidates are often within a few per cent of each other)
     std::vector<std::pair<double, int>> t1;
     for (int k = 0; k < (int)cands.size(); ++k) {
@@ -855,7 +855,7 @@ gf_status choose_schedule(gf_ctx c, int requested)
     t1.resize(std::min<size_t>(t1.size(), 4));
     double best = 1e300;
     Cand pick = cands[t1[0].second];
-    for (int round = 0; round < 2; ++round)
+    for (int pass = 0; pass < 2; ++pass)
         for (auto &e : t1) {
             double ms;
             gf_status st = time_cand(cands[e.second], 8, ms);
