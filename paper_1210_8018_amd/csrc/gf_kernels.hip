@@ -879,6 +879,112 @@ __device__ __forceinline__ void fft_axis_ip_p2(T2 *buf, const T2 *tw, const FftA
     }
 }
 
+// Stages s0, s0 + step, ... (up to, not including, s1) of a power-of-two
+// axis, the first of them with Ns = 2^lNs (step -1: the radix list
+// backwards).
+template <typename T2, int MAXE, int TH>
+__device__ __forceinline__ void fft_axis_stages_p2(T2 *buf, const T2 *tw, const FftAxis &A, int lnpen, int lm1, int a1,
+                                                   int a2, int ls, int sign, int s0, int s1, int lNs)
+{
+    const int lL = ilog2(A.L);
+    const int step = s1 >= s0 ? 1 : -1;
+    for (int st = s0; st != s1; st += step) {
+        switch (A.radix[st]) {
+        case 2: stage_ip_p2<2, T2, MAXE, TH>(buf, tw, lL, lnpen, lm1, a1, a2, ls, lNs, sign); lNs += 1; break;
+        case 4: stage_ip_p2<4, T2, MAXE, TH>(buf, tw, lL, lnpen, lm1, a1, a2, ls, lNs, sign); lNs += 2; break;
+        default: stage_ip_p2<8, T2, MAXE, TH>(buf, tw, lL, lnpen, lm1, a1, a2, ls, lNs, sign); lNs += 3; break;
+        }
+    }
+}
+
+template <int R, int MAXE, int TH>
+__host__ __device__ constexpr int centre_butterflies() { return (MAXE + R * TH - 1) / (R * TH); }
+
+// The centre of the scaled transform along the last axis: its last forward
+// radix-R stage (Ns = L/R), the multiplication by K(p) and the first stage of
+// the backward transform run with the same radix first (Ns = 1) act on the
+// same R elements of a pencil, j + q L/R, so they are done in registers in
+// one LDS round trip. The forward stage leaves element q of the butterfly at
+// its natural index; the backward stage reads exactly those R elements and
+// needs no twiddles. kc[i R + q]: K(p) of element q of butterfly i. Radix 2
+// or 4: a work-item then holds as many centre elements (NK) as tile elements.
+template <int R, typename T2, int MAXE, int TH, int NK>
+__device__ __forceinline__ void stage_centre_p2(T2 *buf, const T2 *__restrict__ tw, int lL, int lnpen, int lm1, int a1,
+                                                int a2, int ls, const typename Cx<T2>::T (&kc)[NK])
+{
+    static_assert(R == 2 || R == 4, "centre stage radix");
+    constexpr int lR = (R == 2) ? 1 : 2;
+    constexpr int MAXB = centre_butterflies<R, MAXE, TH>();
+    static_assert(MAXB * R <= NK, "K registers of the centre stage");
+    const int lnb = lL - lR;  // nb = L / R = Ns of the forward stage
+    const int total = 1 << (lnpen + lnb);
+    const int mstride = __mul24(1 << lnb, ls);
+    T2 v[MAXB][R];
+    int ob[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = threadIdx.x + i * TH;
+        if (b < total) {
+            const int k = b & ((1 << lnpen) - 1), j = b >> lnpen;
+            const int base = __mul24(k & ((1 << lm1) - 1), a1) + __mul24(k >> lm1, a2);
+            const int e0 = base + __mul24(j, ls);
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[i][m] = buf[e0 + m * mstride];
+            if (lnb > 0) {  // forward twiddles exp(-2 pi i m j / L)
+#pragma unroll
+                for (int m = 1; m < R; ++m) v[i][m] = t_mul(v[i][m], tw[m * j]);
+            }
+            if constexpr (R == 2)
+                dft2(v[i]);
+            else
+                dft4(v[i], -1);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                v[i][q].x *= kc[i * R + q];
+                v[i][q].y *= kc[i * R + q];
+            }
+            if constexpr (R == 2)
+                dft2(v[i]);
+            else
+                dft4(v[i], +1);
+            ob[i] = base + __mul24(j << lR, ls);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = threadIdx.x + i * TH;
+        if (b < total) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[ob[i] + q * ls] = v[i][q];
+        }
+    }
+    __syncthreads();
+}
+
+// K(p) of the centre stage's elements for this work-item (zt tile: t-axis
+// pencil k = p + P z, element t = j + q L/R); Km points at the tile's first
+// xy-site of the K(p) table.
+template <int R, typename T, int MAXE, int TH, int NK>
+__device__ __forceinline__ void centre_k_p2(T (&kc)[NK], const T *__restrict__ Km, int lL, int lnpen, int lp, int Lz,
+                                            size_t V2)
+{
+    static_assert(R == 2 || R == 4, "centre stage radix");
+    constexpr int lR = (R == 2) ? 1 : 2;
+    constexpr int MAXB = centre_butterflies<R, MAXE, TH>();
+    static_assert(MAXB * R <= NK, "K registers of the centre stage");
+    const int lnb = lL - lR;
+    const int total = 1 << (lnpen + lnb);
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = min((int)threadIdx.x + i * TH, total - 1);  // lanes past the last butterfly: any valid one
+        const int k = b & ((1 << lnpen) - 1), j = b >> lnpen;
+        const int p = k & ((1 << lp) - 1), z = k >> lp;
+#pragma unroll
+        for (int q = 0; q < R; ++q) kc[i * R + q] = Km[(size_t)(z + Lz * (j + (q << lnb))) * V2 + p];
+    }
+}
+
 template <typename T2>
 __device__ __forceinline__ void load_twiddles(T2 *dst, const Cfg &C, int axis)
 {
@@ -982,22 +1088,33 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(CAP / TH >= 
     constexpr int NL = tile_regs<CAP, TH>();
     T2 pre[NL], out[NL];
     tile_fetch_rows<T2, CAP, TH>(pre, g, P, rows, V2);
-    // K(p) of this tile's elements, same (row, p) assignment as the tile
-    // fetch; shared by all fields of the tile
+    // K(p) of this tile's elements, shared by all fields of the tile: in the
+    // assignment of the t-axis centre stage (power-of-two extents, last t
+    // radix 2 or 4), else in the (row, p) assignment of the tile fetch
     const int lp = ilog2(P), lz = is_p2(Lz) ? ilog2(Lz) : -1;
     const int p = threadIdx.x & (P - 1), r0 = threadIdx.x >> lp, dr = TH >> lp;
+    const int lt = P2 ? ilog2(Lt) : 0;
+    const FftAxis &At = C.ax[3];
+    const int rlast = At.radix[At.nstage - 1];
+    const bool centre = P2 && mode == 1 && rlast <= 4;
     T kreg[NL];
     if (mode == 1) {
         const T *__restrict__ Km = (const T *)C.kmom + i0;
+        if (centre) {
+            if (rlast == 2)
+                centre_k_p2<2, T, CAP, TH>(kreg, Km, lt, lp + lz, lp, Lz, V2);
+            else
+                centre_k_p2<4, T, CAP, TH>(kreg, Km, lt, lp + lz, lp, Lz, V2);
+        } else {
 #pragma unroll
-        for (int k = 0; k < NL; ++k) kreg[k] = Km[(size_t)min(r0 + k * dr, rows - 1) * V2 + p];
+            for (int k = 0; k < NL; ++k) kreg[k] = Km[(size_t)min(r0 + k * dr, rows - 1) * V2 + p];
+        }
     }
     load_twiddles(twz, C, 2);
     load_twiddles(twt, C, 3);
     tile_put_rows<T2, CAP, TH>(buf, pre, P, rows, Lz, C.ztPad);
     __syncthreads();
     const int s0 = (mode == 1) ? -1 : sign;
-    const int lt = P2 ? ilog2(Lt) : 0;
     const FastDiv flz = fast_div(Lz);
     for (int f = f0; f < f1; ++f, g += C.V) {
         const bool more = f + 1 < f1;
@@ -1006,12 +1123,26 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(CAP / TH >= 
         // t: pencils k = (p, z), start k, stride Tp
         if constexpr (P2) {
             fft_axis_ip_p2<T2, CAP, TH>(buf, twz, C.ax[2], lp + lt, lp, 1, Tp, P, s0);
-            fft_axis_ip_p2<T2, CAP, TH>(buf, twt, C.ax[3], lp + lz, lp + lz, 1, 0, Tp, s0);
+            if (centre) {
+                // t: forward stages but the last, the centre stage with K(p),
+                // the remaining backward stages with the radix list reversed;
+                // then z backward
+                const int ns = At.nstage;
+                fft_axis_stages_p2<T2, CAP, TH>(buf, twt, At, lp + lz, lp + lz, 1, 0, Tp, -1, 0, ns - 1, 0);
+                if (rlast == 2)
+                    stage_centre_p2<2, T2, CAP, TH>(buf, twt, lt, lp + lz, lp + lz, 1, 0, Tp, kreg);
+                else
+                    stage_centre_p2<4, T2, CAP, TH>(buf, twt, lt, lp + lz, lp + lz, 1, 0, Tp, kreg);
+                fft_axis_stages_p2<T2, CAP, TH>(buf, twt, At, lp + lz, lp + lz, 1, 0, Tp, +1, ns - 2, -1, ilog2(rlast));
+                fft_axis_ip_p2<T2, CAP, TH>(buf, twz, C.ax[2], lp + lt, lp, 1, Tp, P, +1);
+            } else {
+                fft_axis_ip_p2<T2, CAP, TH>(buf, twt, C.ax[3], lp + lz, lp + lz, 1, 0, Tp, s0);
+            }
         } else {
             fft_axis_ip<T2, CAP, TH>(buf, twz, C.ax[2], P * Lt, P, 1, Tp, P, s0, true);
             fft_axis_ip<T2, CAP, TH>(buf, twt, C.ax[3], P * Lz, P * Lz, 1, 0, Tp, s0, true);
         }
-        if (mode == 1) {
+        if (mode == 1 && !centre) {
 #pragma unroll
             for (int k = 0; k < NL; ++k) {
                 const int li = rows_slot<CAP>(r0 + k * dr, p, rows, lp, flz, lz, C.ztPad);
