@@ -26,9 +26,11 @@ ALPHA = 0.08
 EPS = 1e-15
 
 # several tiles, ragged site blocks (V not a multiple of 256), radix-3 lengths
-# (27 = three radix-3 stages, odd extents 3 and 9), L = 2, the longest axis (256)
+# (27 = three radix-3 stages, odd extents 3 and 9), L = 2, the longest axis
+# (256); t extents 2, 4, 16, 256 (last radix 2 or 4: the t-axis centre stage
+# with 1, 2 or 3 stages) and 8 (last radix 8: separate scaling step)
 SHAPES = [(8, 8, 8, 8), (12, 8, 6, 4), (6, 6, 6, 2), (2, 2, 2, 2), (24, 4, 2, 6), (4, 12, 4, 8),
-          (27, 2, 4, 6), (3, 9, 2, 4), (256, 4, 2, 2), (2, 2, 2, 256)]
+          (27, 2, 4, 6), (3, 9, 2, 4), (256, 4, 2, 2), (2, 2, 2, 256), (4, 4, 4, 4), (4, 2, 4, 16)]
 
 
 def dev(a):
