@@ -136,6 +136,56 @@ __device__ __forceinline__ void m3_store12s(S2 *__restrict__ base, int V, int s,
     for (int k = 0; k < 6; ++k) narrow(base[(size_t)k * V + s], m.e[k]);
 }
 
+// Streaming (non-temporal) access to elements that a pass reads or writes
+// once, so that they do not displace data other work-groups re-read from L2.
+typedef double gf_dv2 __attribute__((ext_vector_type(2)));
+typedef float gf_fv2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream(const double2 *p)
+{
+    const gf_dv2 v = __builtin_nontemporal_load((const gf_dv2 *)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_stream(const float2 *p)
+{
+    const gf_fv2 v = __builtin_nontemporal_load((const gf_fv2 *)p);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st_stream(double2 *p, double2 a)
+{
+    gf_dv2 v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, (gf_dv2 *)p);
+}
+__device__ __forceinline__ void st_stream(float2 *p, float2 a)
+{
+    gf_fv2 v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, (gf_fv2 *)p);
+}
+
+template <typename S2>
+__device__ __forceinline__ M3 m3_load12s_stream(const S2 *__restrict__ base, int V, int s)
+{
+    M3 m;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m.e[k] = widen(ld_stream(base + (size_t)k * V + s));
+    m3_row2(m);
+    return m;
+}
+
+template <typename S2>
+__device__ __forceinline__ void m3_store12s_stream(S2 *__restrict__ base, int V, int s, const M3 &m)
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        S2 v;
+        narrow(v, m.e[k]);
+        st_stream(base + (size_t)k * V + s, v);
+    }
+}
+
 // a b
 __device__ __forceinline__ M3 m3_mul(const M3 &a, const M3 &b)
 {

@@ -1555,9 +1555,12 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                 } else {
                     gf = m3_load12s(G, V, fwd3[mu] + V3 * t);
                 }
-                M3 w = m3_mul_mul_dag_rows(gx, m3_load12s(Uo + off, V, s), gf);
+                // U_x(x) is read by this work-item only; U_y and U_z are
+                // read again as the backward neighbour of other work-groups
+                const M3 u = (mu == 0) ? m3_load12s_stream(Uo + off, V, s) : m3_load12s(Uo + off, V, s);
+                M3 w = m3_mul_mul_dag_rows(gx, u, gf);
                 if (RU) m3_reunit(w);
-                m3_store12s(Un + off, V, s, w);
+                m3_store12s_stream(Un + off, V, s, w);
                 fsum += w.e[0].x + w.e[4].x + w.e[8].x;
                 const AH a = ah_of(w);
                 ah_acc(D, a, -1.0);
@@ -1578,9 +1581,9 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                 const int tn = (t + 1 == Lt) ? 0 : t + 1;
                 gn = m3_load12s(G, V, s3 + V3 * tn);
                 const size_t off = (size_t)18 * V;
-                M3 w = m3_mul_mul_dag_rows(gx, m3_load12s(Uo + off, V, s), gn);
+                M3 w = m3_mul_mul_dag_rows(gx, m3_load12s_stream(Uo + off, V, s), gn);
                 if (RU) m3_reunit(w);
-                m3_store12s(Un + off, V, s, w);
+                m3_store12s_stream(Un + off, V, s, w);
                 fsum += w.e[0].x + w.e[4].x + w.e[8].x;
                 utp = ah_of(w);
                 ah_acc(D, utp, -1.0);
@@ -1612,14 +1615,19 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
             const double tr3 = (D.d0 + D.d1 + D.d2) * (1.0 / 3.0);
             const double e0 = D.d0 - tr3, e1 = D.d1 - tr3, e2 = D.d2 - tr3;
             const double tsum = 2.0 * (cnorm2(D.o01) + cnorm2(D.o02) + cnorm2(D.o12)) + e0 * e0 + e1 * e1 + e2 * e2;
-            f[s].x = D.o01.x;
-            f[s].y = D.o01.y;
-            f[(size_t)V + s].x = D.o02.x;
-            f[(size_t)V + s].y = D.o02.y;
-            f[(size_t)2 * V + s].x = D.o12.x;
-            f[(size_t)2 * V + s].y = D.o12.y;
-            f[(size_t)3 * V + s].x = e0;
-            f[(size_t)3 * V + s].y = e1;
+            T2 fv;
+            fv.x = D.o01.x;
+            fv.y = D.o01.y;
+            st_stream(f + s, fv);
+            fv.x = D.o02.x;
+            fv.y = D.o02.y;
+            st_stream(f + (size_t)V + s, fv);
+            fv.x = D.o12.x;
+            fv.y = D.o12.y;
+            st_stream(f + (size_t)2 * V + s, fv);
+            fv.x = e0;
+            fv.y = e1;
+            st_stream(f + (size_t)3 * V + s, fv);
             fs = dd_add(fs, dd{fsum, 0.0});
             ts = dd_add(ts, dd{tsum, 0.0});
             gx = gn;
