@@ -508,12 +508,18 @@ __device__ __forceinline__ void cp2(T2 &d, const T2 &v)
     d.y = v.y;
 }
 
-template <typename T2, int CAP, int TH, int NL>
+template <typename T2, int CAP, int TH, int NL, bool STREAM = false>
 __device__ __forceinline__ void tile_fetch(T2 (&r)[NL], const T2 *__restrict__ g, int n)
 {
     static_assert(NL == tile_regs<CAP, TH>(), "one register per tile element of a work-item");
 #pragma unroll
-    for (int k = 0; k < NL; ++k) cp2(r[k], g[min(threadIdx.x + k * TH, (unsigned)n - 1)]);
+    for (int k = 0; k < NL; ++k) {
+        const T2 *e = g + min(threadIdx.x + k * TH, (unsigned)n - 1);
+        if constexpr (STREAM)
+            cp2(r[k], ld_stream(e));
+        else
+            cp2(r[k], *e);
+    }
 }
 
 // LDS slot of element i of a tile of rows of `rowlen` with `pad` after each.
@@ -1227,7 +1233,8 @@ __global__ __launch_bounds__(kSiteBlock) void k_gauge(const Cfg *__restrict__ cf
 
 // Inverse transform over (x, y) of the four fields of Q xy-planes, then g and
 // its projection at every site of the tile (the last steps of the transform
-// and the gauge step in one pass; the fields are not written back).
+// and the gauge step in one pass; the fields are not written back). A tile
+// is whole contiguous planes, read once: the field loads are streaming.
 template <typename T2, int CAP, int TH, bool P2>
 __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
                                                          int respect_done, double2 *__restrict__ g_override, int tw2,
@@ -1249,14 +1256,14 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
     const T2 *__restrict__ src = (const T2 *)C.fields + site0;
     T2 val[kFields][MS];
     T2 pre[MS];
-    tile_fetch<T2, CAP, TH>(pre, src, n);
+    tile_fetch<T2, CAP, TH, MS, true>(pre, src, n);
     load_twiddles(twx, C, 0);
     load_twiddles(twy, C, 1);
     tile_put_padded<T2, CAP, TH>(buf, pre, n, C.dims[0], C.xyPad);
     __syncthreads();
 #pragma unroll
     for (int f = 0; f < kFields; ++f) {
-        if (f + 1 < kFields) tile_fetch<T2, CAP, TH>(pre, src + (size_t)(f + 1) * C.V, n);
+        if (f + 1 < kFields) tile_fetch<T2, CAP, TH, MS, true>(pre, src + (size_t)(f + 1) * C.V, n);
         xy_transform<T2, CAP, TH, P2>(buf, twx, twy, C, C.xyQ, +1);
         // own slots out, next field in (the fetch had the transform to land)
         tile_get_padded<T2, CAP, TH>(val[f], buf, n, C.dims[0], C.xyPad);
@@ -1555,9 +1562,10 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                 } else {
                     gf = m3_load12s(G, V, fwd3[mu] + V3 * t);
                 }
-                // U_x(x) is read by this work-item only; U_y and U_z are
-                // read again as the backward neighbour of other work-groups
-                const M3 u = (mu == 0) ? m3_load12s_stream(Uo + off, V, s) : m3_load12s(Uo + off, V, s);
+                // U_x(x) and U_y(x) are read again only at the block's edge
+                // rows; U_z(x) is the backward neighbour of the next
+                // work-group in z, which reads it in the same slice
+                const M3 u = (mu < 2) ? m3_load12s_stream(Uo + off, V, s) : m3_load12s(Uo + off, V, s);
                 M3 w = m3_mul_mul_dag_rows(gx, u, gf);
                 if (RU) m3_reunit(w);
                 m3_store12s_stream(Un + off, V, s, w);
