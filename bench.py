@@ -210,7 +210,8 @@ def main():
         dcpu = time.perf_counter() - t3
         cpu = {"value": args.cpu_iters / dcpu, "unit": "iters/s", "cores": nthr, "kind": "oracle",
                "sample": f"{args.cpu_iters} iterations of Alg. 1 on the same {'x'.join(map(str, dims))} "
-                         f"configuration (FP64 C oracle, OpenMP), {dcpu:.1f} s"}
+                         f"configuration (FP64 C oracle, OpenMP), {dcpu:.1f} s",
+               "cpu_model": _cpu_model()}
 
     f64 = res["fp64"]
     f32 = res["fp32_fft"]
@@ -482,6 +483,17 @@ def bench_thermal(args):
                                   f"beta={args.beta}, Philox seed 20121030"},
            "generation": {"seconds": round(gen_s, 3), "plaquette": plaq}, "fix": res}
     print(json.dumps(out), flush=True)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _source_hash():
