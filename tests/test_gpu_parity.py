@@ -28,9 +28,12 @@ EPS = 1e-15
 # several tiles, ragged site blocks (V not a multiple of 256), radix-3 lengths
 # (27 = three radix-3 stages, odd extents 3 and 9), L = 2, the longest axis
 # (256); t extents 2, 4, 16, 256 (last radix 2 or 4: the t-axis centre stage
-# with 1, 2 or 3 stages) and 8 (last radix 8: separate scaling step)
+# with 1, 2 or 3 stages) and 8 (last radix 8: separate scaling step); 48 x 48
+# planes (a general-extent tile filling 56 % of its 4096-element capacity) in
+# the xy and in the zt pass
 SHAPES = [(8, 8, 8, 8), (12, 8, 6, 4), (6, 6, 6, 2), (2, 2, 2, 2), (24, 4, 2, 6), (4, 12, 4, 8),
-          (27, 2, 4, 6), (3, 9, 2, 4), (256, 4, 2, 2), (2, 2, 2, 256), (4, 4, 4, 4), (4, 2, 4, 16)]
+          (27, 2, 4, 6), (3, 9, 2, 4), (256, 4, 2, 2), (2, 2, 2, 256), (4, 4, 4, 4), (4, 2, 4, 16),
+          (48, 48, 2, 2), (2, 2, 48, 48)]
 
 
 def dev(a):
@@ -373,6 +376,29 @@ def test_batch_equals_single_runs(monkeypatch, prec, sched):
         single.append((fx.fix_until(EPS, 20000), host(Ud)))
     Ubs = [dev(U) for U in Us]
     bx = BatchGaugeFixer(Ubs, fft_prec=prec, fft_schedule=sched)
+    its, Fs, ths = bx.fix_until(EPS, 20000)
+    for k in range(len(cases)):
+        (it, F, th), Uf = single[k]
+        assert its[k] == it and Fs[k] == F and ths[k] == th
+        assert np.array_equal(host(Ubs[k]), Uf)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_mixed_general_and_power_of_two(monkeypatch, prec):
+    """48 x 48 planes (general-extent instances of the 2D passes) batched with a
+    power-of-two lattice (the other instances, same launches): each evolves
+    bitwise as in its own context."""
+    monkeypatch.setenv("GF_TCHUNK", "2")
+    monkeypatch.setenv("GF_TCHUNK_BATCH", "2")
+    cases = [((48, 48, 2, 2), 0.3, 7), ((2, 2, 48, 48), 0.3, 8), ((8, 8, 8, 8), 0.3, 9)]
+    Us = [random_links(d, e, s) for d, e, s in cases]
+    single = []
+    for U in Us:
+        Ud = dev(U)
+        fx = GaugeFixer(Ud, fft_prec=prec, fft_schedule=3)
+        single.append((fx.fix_until(EPS, 20000), host(Ud)))
+    Ubs = [dev(U) for U in Us]
+    bx = BatchGaugeFixer(Ubs, fft_prec=prec, fft_schedule=3)
     its, Fs, ths = bx.fix_until(EPS, 20000)
     for k in range(len(cases)):
         (it, F, th), Uf = single[k]
