@@ -266,6 +266,32 @@ def test_step_equals_fix_prefix():
     assert Fb == Fa[:11] and Tb == Ta[:11]  # deterministic: bitwise equal
 
 
+def test_resume_from_saved_links():
+    """The links a call leaves behind are the whole state: a run stopped after 4
+    updates and resumed in a new context from a copy of its links follows the
+    uninterrupted run. Not bitwise: the first measurement of a call computes the
+    divergence with the separate kernel, whose summation order differs from the
+    fused pass's, so the two paths differ by rounding from there on."""
+    dims = (8, 8, 8, 8)
+    U = random_links(dims, 0.3, 1)
+    Ua = dev(U)
+    a = GaugeFixer(Ua)
+    a.step(10)
+    Fa, Ta = a.history()
+    Ub = dev(U)
+    b = GaugeFixer(Ub)
+    b.step(4)
+    saved = Ub.clone()  # the checkpoint
+    del b
+    c = GaugeFixer(saved)
+    c.step(6)
+    Fc, Tc = c.history()
+    assert len(Fc) == 7
+    assert np.max(np.abs(np.array(Fc) - np.array(Fa[4:11]))) < 1e-14
+    assert np.max(np.abs(np.array(Tc) / np.array(Ta[4:11]) - 1)) < 1e-9
+    assert np.max(np.abs(host(saved) - host(Ua))) < 1e-13
+
+
 def test_trajectory_32x4_matches_stored_oracle():
     """Plain FP64 at 32^4 (eps 0.3, seed 2) against the stored oracle run."""
     ref = json.load(open(os.path.join(HERE, "golden", "oracle_32x32x32x32_eps0.3_seed2.json")))
