@@ -1583,7 +1583,6 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                     sa[mu][7][tid] = a.d1;
                     sa[mu][8][tid] = a.d2;
                 }
-                __builtin_amdgcn_sched_barrier(0);
             }
             {
                 const int tn = (t + 1 == Lt) ? 0 : t + 1;
@@ -1617,7 +1616,6 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                     a = ah_of(wb);
                 }
                 ah_acc(D, a, 1.0);
-                __builtin_amdgcn_sched_barrier(0);
             }
             // Delta = A - Tr(A)/3 with A = D - D^dag
             const double tr3 = (D.d0 + D.d1 + D.d2) * (1.0 / 3.0);
