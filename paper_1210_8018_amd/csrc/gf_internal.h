@@ -141,7 +141,11 @@ hipError_t launch_delta(const Launch &L, int respect_done, double2 *full_delta);
 hipError_t launch_reduce(const Launch &L, int ncfg, int count_iter, int respect_done);
 hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *fields_override,
                            int nfields, int respect_done);
-hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done);
+// fold_reduce: the pass also does the final reduction of the previous update
+// (in place of launch_reduce after it); only where can_fold_reduce(L).
+hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done,
+                         int fold_reduce = 0);
+bool can_fold_reduce(const Launch &L);
 hipError_t launch_fft_xy_inv_gauge(const Launch &L, int respect_done, double2 *g_override);
 hipError_t launch_fft_zt(const Launch &L, int mode, int sign, void *fields_override, int nfields, int respect_done);
 hipError_t launch_fft_zt_scale(const Launch &L, int respect_done);

@@ -154,11 +154,17 @@ __global__ __launch_bounds__(kSiteBlock) void k_delta(const Cfg *__restrict__ cf
 // block takes part), F = sum/(12 V) (Eq. 1), theta = sum/(3 V) (Eq. 4); with
 // count_iter, count the update, record the history, flip the link buffer if
 // asked and evaluate the stopping rule theta <= eps.
+// The partial sums are taken kReduceLanes at a time in a fixed order; a
+// larger work-group leaves its other work-items at zero, which adds nothing
+// (dd_add of an exact zero returns its other operand), so every caller forms
+// the same sums bit for bit.
+constexpr int kReduceLanes = 256;
+
 __device__ void finalize_config(const Cfg &C, int nparts, int count_iter, int flip, dd *red)
 {
     Ctrl *ct = C.ctrl;
     dd f = {0.0, 0.0}, t = {0.0, 0.0};
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nparts && (int)threadIdx.x < kReduceLanes; i += kReduceLanes) {
         const double *p = C.partials + (size_t)i * 4;
         f = dd_add(f, dd{p[0], p[1]});
         t = dd_add(t, dd{p[2], p[3]});
@@ -192,10 +198,10 @@ __device__ void finalize_config(const Cfg &C, int nparts, int count_iter, int fl
 
 // One block per configuration entry: finalize_config over the partials of
 // the divergence kernel.
-__global__ __launch_bounds__(256) void k_reduce(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
-                                                int count_iter, int respect_done, int flip)
+__global__ __launch_bounds__(kReduceLanes) void k_reduce(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                         int count_iter, int respect_done, int flip)
 {
-    __shared__ dd red[2 * (256 / 64)];
+    __shared__ dd red[2 * (kReduceLanes / 64)];
     const Cfg &C = cfgs[B->idx[blockIdx.x]];
     if (respect_done && C.ctrl->done) return;
     finalize_config(C, C.nblk_march, count_iter, flip, red);
@@ -1023,13 +1029,31 @@ __device__ __forceinline__ void xy_transform(T2 *buf, const T2 *twx, const T2 *t
 __device__ __forceinline__ bool xy_is_p2(const Cfg &C) { return is_p2(C.dims[0]) && is_p2(C.dims[1]) && is_p2(C.xyQ); }
 __device__ __forceinline__ bool zt_is_p2(const Cfg &C) { return is_p2(C.dims[2]) && is_p2(C.dims[3]); }
 
+// Pass over (x, y): tile = Q consecutive xy-planes; a work-group transforms
+// that tile in fields [fpb y, fpb (y + 1)) of the nf fields, one after the
+// other, fetching the next field while it transforms the current one. LDS:
+// CAP data elements, then the twiddles of x (tw2 entries reserved) and y.
+// fold != 0: one more work-group per configuration (after the tiles) does the
+// final reduction of the previous update as k_reduce would (count, stopping
+// rule, buffer flip if fold == 2) while the tiles are transformed; the tiles
+// of a configuration that has just stopped transform once more, unused.
 template <typename T2, int CAP, int TH, bool P2>
 __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(CAP / TH >= 8 ? 2 : 4))) void k_fft_xy(
     const Cfg *__restrict__ cfgs, const Batch *__restrict__ B, int sign, void *fields_override, int respect_done,
-    int tw2, int nf, int fpb)
+    int tw2, int nf, int fpb, int fold)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int ntiles = B->off_xy[B->n];
+    if ((int)blockIdx.x >= ntiles) {
+        if constexpr (TH >= kReduceLanes) {
+            if (blockIdx.y != 0) return;
+            const Cfg &R = cfgs[B->idx[blockIdx.x - ntiles]];
+            if (R.ctrl->done) return;
+            finalize_config(R, R.nblk_march, 1, fold == 2, (dd *)smem);
+        }
+        return;
+    }
+    const int tile = xcd_remap(blockIdx.x, ntiles);
     const int f0 = blockIdx.y * fpb, f1 = min(nf, f0 + fpb);
     const int c = find_cfg(B->off_xy, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
@@ -1962,7 +1986,7 @@ hipError_t launch_delta(const Launch &L, int respect_done, double2 *full_delta)
 
 hipError_t launch_reduce(const Launch &L, int ncfg, int count_iter, int respect_done)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(ncfg), dim3(256), 0, L.stream, L.cfgs, L.batch, count_iter, respect_done,
+    hipLaunchKernelGGL(k_reduce, dim3(ncfg), dim3(kReduceLanes), 0, L.stream, L.cfgs, L.batch, count_iter, respect_done,
                        count_iter ? L.fused : 0);
     return hipGetLastError();
 }
@@ -2014,16 +2038,19 @@ static size_t lds2d(int cap, int tw2, int tw_total)
 // power-of-two extents in that pass, and the general one if some has not;
 // each instance leaves the other's configurations at once.
 template <typename T2>
-static hipError_t run_xy(const Launch &L, int nf, int sign, void *fo, int rd)
+static hipError_t run_xy(const Launch &L, int nf, int sign, void *fo, int rd, int fold)
 {
     const int fpb = std::max(1, std::min(L.xy_fpb, nf));
-    const dim3 grid(L.total_xy_tiles, (nf + fpb - 1) / fpb);
     const size_t sh = lds2d<T2>(L.xy_cap, L.xy_tw2, L.xy_tw_total);
     int launched = 0;
+    // a batch mixing power-of-two and general extents launches both
+    // instances; only the first carries the folded reduction
 #define X(C_, T_, P2_)                                                                                            \
     if (L.xy_cap == C_ && L.xy_th == T_ && (P2_ ? L.xy_p2 : L.xy_gen)) {                                          \
+        const int f = launched ? 0 : fold;                                                                        \
+        const dim3 grid(L.total_xy_tiles + (f ? L.ncfg : 0), (nf + fpb - 1) / fpb);                               \
         hipLaunchKernelGGL((k_fft_xy<T2, C_, T_, P2_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, sign, fo, rd, \
-                           L.xy_tw2, nf, fpb);                                                                    \
+                           L.xy_tw2, nf, fpb, f);                                                                 \
         ++launched;                                                                                               \
     }
     GF_2D_VARIANTS(X)
@@ -2065,10 +2092,16 @@ static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
     return launched ? hipGetLastError() : hipErrorInvalidValue;
 }
 
-hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done)
+bool can_fold_reduce(const Launch &L) { return L.xy_th >= kReduceLanes; }
+
+hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done,
+                         int fold_reduce)
 {
-    return L.fp32 ? run_xy<float2>(L, nfields, sign, fields_override, respect_done)
-                  : run_xy<double2>(L, nfields, sign, fields_override, respect_done);
+    // the folded reduction needs a work-group of at least kReduceLanes
+    if (fold_reduce && !can_fold_reduce(L)) return hipErrorInvalidValue;
+    const int fold = fold_reduce ? (L.fused ? 2 : 1) : 0;
+    return L.fp32 ? run_xy<float2>(L, nfields, sign, fields_override, respect_done, fold)
+                  : run_xy<double2>(L, nfields, sign, fields_override, respect_done, fold);
 }
 
 hipError_t launch_fft_zt(const Launch &L, int mode, int sign, void *fields_override, int nfields, int respect_done)

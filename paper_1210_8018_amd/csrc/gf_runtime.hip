@@ -347,7 +347,9 @@ gf_status collect_timing(gf_ctx c)
 // Transform of the four fields, scaling, inverse transform and g, as the
 // schedule in use arranges them (respect_done: skip finished configurations;
 // g_override: write g there instead of the workspace).
-hipError_t enqueue_gauge_steps(gf_ctx c, hipStream_t s, int respect_done, double2 *g_override)
+// fold_reduce: the first pass (the xy pass) also does the final reduction of
+// the previous update (schedules that start with it; see fold_ok).
+hipError_t enqueue_gauge_steps(gf_ctx c, hipStream_t s, int respect_done, double2 *g_override, int fold_reduce = 0)
 {
     Launch L = respect_done ? c->Lact : c->L;
     L.stream = s;
@@ -357,18 +359,19 @@ hipError_t enqueue_gauge_steps(gf_ctx c, hipStream_t s, int respect_done, double
     if ((e = timed(c, kid, s, [&] { return call; })) != hipSuccess) return e;
     switch (c->sched) {
     case kSchedXYZT:
-        GF_TRY(K_FFTXY, launch_fft_xy(L, -1, nullptr, nf, rd));
+        GF_TRY(K_FFTXY, launch_fft_xy(L, -1, nullptr, nf, rd, fold_reduce));
         GF_TRY(K_FFTZT_S, launch_fft_zt_scale(L, rd));
         GF_TRY(K_IFFTXY_GAUGE, launch_fft_xy_inv_gauge(L, rd, g_override));
         break;
     case kSchedXY1D:
-        GF_TRY(K_FFTXY, launch_fft_xy(L, -1, nullptr, nf, rd));
+        GF_TRY(K_FFTXY, launch_fft_xy(L, -1, nullptr, nf, rd, fold_reduce));
         GF_TRY(K_FFT2, launch_fft_axis(L, 2, -1, 0, nullptr, nf, rd));
         GF_TRY(K_FFT3S, launch_fft_axis(L, 3, -1, 1, nullptr, nf, rd));
         GF_TRY(K_IFFT2, launch_fft_axis(L, 2, +1, 0, nullptr, nf, rd));
         GF_TRY(K_IFFTXY_GAUGE, launch_fft_xy_inv_gauge(L, rd, g_override));
         break;
     default:
+        if (fold_reduce) return hipErrorInvalidValue;  // no xy pass to carry it
         GF_TRY(K_FFT0, launch_fft_axis(L, 0, -1, 0, nullptr, nf, rd));
         GF_TRY(K_FFT1, launch_fft_axis(L, 1, -1, 0, nullptr, nf, rd));
         GF_TRY(K_FFT2, launch_fft_axis(L, 2, -1, 0, nullptr, nf, rd));
@@ -382,13 +385,23 @@ hipError_t enqueue_gauge_steps(gf_ctx c, hipStream_t s, int respect_done, double
     return hipSuccess;
 }
 
+// Whether the final reduction of an update can ride on the next iteration's
+// first pass (an xy pass with work-groups of at least 256 work-items).
+bool fold_ok(gf_ctx c)
+{
+    return (c->sched == kSchedXYZT || c->sched == kSchedXY1D) && can_fold_reduce(c->Lact);
+}
+
 // Alg. 1 inner loop body: transform, scale, transform back, g, link update,
-// re-measurement. Every kernel returns at once for configurations that are done.
-hipError_t enqueue_iteration(gf_ctx c, hipStream_t s)
+// re-measurement. Every kernel returns at once for configurations that are
+// done. fold_prev: the previous iteration's final reduction is done by this
+// iteration's first pass; reduce_after: this iteration's own is launched
+// (else the next iteration folds it).
+hipError_t enqueue_iteration(gf_ctx c, hipStream_t s, int fold_prev = 0, int reduce_after = 1)
 {
     Launch L = c->Lact;
     L.stream = s;
-    hipError_t e = enqueue_gauge_steps(c, s, 1, nullptr);
+    hipError_t e = enqueue_gauge_steps(c, s, 1, nullptr, fold_prev);
     if (e != hipSuccess) return e;
     if (L.fused) {
         GF_TRY(K_UPDATE_DELTA, launch_update_delta(L));
@@ -396,7 +409,7 @@ hipError_t enqueue_iteration(gf_ctx c, hipStream_t s)
         GF_TRY(K_UPDATE, launch_update(L, 1, nullptr));
         GF_TRY(K_DELTA, launch_delta(L, 1, nullptr));
     }
-    GF_TRY(K_REDUCE, launch_reduce(L, L.ncfg, 1, 1));
+    if (reduce_after) GF_TRY(K_REDUCE, launch_reduce(L, L.ncfg, 1, 1));
 #undef GF_TRY
     return hipSuccess;
 }
@@ -413,7 +426,12 @@ gf_status build_graph(gf_ctx c)
     if (c->gexec) return GF_OK;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int i = 0; i < c->chunk && e == hipSuccess; ++i) e = enqueue_iteration(c, c->cap_stream);
+    // inside a chunk each iteration's final reduction rides on the next
+    // iteration's first pass; the chunk's last one is launched on its own,
+    // so the host reads a complete control block after every chunk
+    const bool fold = fold_ok(c);
+    for (int i = 0; i < c->chunk && e == hipSuccess; ++i)
+        e = enqueue_iteration(c, c->cap_stream, fold && i > 0, !(fold && i + 1 < c->chunk));
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e != hipSuccess) {
