@@ -500,8 +500,8 @@ def _source_hash():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("gf_kernels.hip", "gf_device.h", "gf_internal.h"):
-        with open(os.path.join(ROOT, "paper_1210_8018_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/gf_kernels.hip", "csrc/gf_device.h", "csrc/gf_internal.h", "build.py"):
+        with open(os.path.join(ROOT, "paper_1210_8018_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

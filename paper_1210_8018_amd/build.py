@@ -19,6 +19,10 @@ FLAGS = [
     "-shared",
     # no packed-FP32 instructions anywhere (they are not used deliberately)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a multiply-add is fused only where one source expression holds it, so
+    # every inlined copy of a helper rounds alike (a link recomputed by a
+    # neighbouring work-group equals the one its owner stores)
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 

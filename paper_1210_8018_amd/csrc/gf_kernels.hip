@@ -1501,15 +1501,30 @@ __device__ __forceinline__ float2 *gauge12<float2>(const Cfg &C) { return C.g12f
 // work-item publishes its g(x) (two rows) and, after its forward links,
 // U'_mu(x) - U'_mu(x)^dag for mu = x, y; a neighbour inside the block reads
 // them instead of loading g(x + mu) and recomputing U'_nu(x - nu) from the old
-// links. Neighbours in other blocks (all of z, the block's edge rows in y) are
-// loaded and recomputed as in k_update_delta. The new links are formed by
-// their first two rows (m3_mul_mul_dag_rows), exactly what is stored, so a
-// recomputed backward link equals the one its owner writes. Divergence and
-// sums as in k_update_delta; D is accumulated as its anti-hermitian part.
-__device__ __forceinline__ int block_slot(int b3, int s3n)
+// links. The z-neighbours, and x and y neighbours in other blocks (the edge
+// rows of a linear site set, the faces of a box), are loaded and recomputed as
+// in k_update_delta. (Exchanging z too, for boxes and for sets longer than an
+// xy-plane, needs a third LDS array: 80 KB per block, and the single-precision
+// storage pass 3 % slower at 32^4 where no block holds a z-neighbour.) The new
+// links are formed by their first two rows (m3_mul_mul_dag_rows), exactly what
+// is stored, so a recomputed backward link equals the one its owner writes
+// (with contraction of multiply-adds fixed by the source, every inlined copy
+// rounds alike). Divergence and sums as in k_update_delta; D is accumulated
+// as its anti-hermitian part.
+//
+// Slot of the site (xn, yn, zn), flat index s3n, among the work-items of
+// marching block b3 (march_xyz's numbering), or -1 if another block owns it.
+__device__ __forceinline__ int block_slot(const Cfg &C, int b3, int s3n, int xn, int yn, int zn)
 {
-    const int o = s3n - b3 * kSiteBlock;
-    return (o >= 0 && o < kSiteBlock) ? o : -1;
+    if (C.tile[0] == 0) {
+        const int o = s3n - b3 * kSiteBlock;
+        return (o >= 0 && o < kSiteBlock) ? o : -1;
+    }
+    const int tx = C.tile[0], ty = C.tile[1], tz = C.tile[2];
+    const int bx = b3 % C.ntile[0], rb = b3 / C.ntile[0];
+    const int by = rb % C.ntile[1], bz = rb / C.ntile[1];
+    const int lx = xn - bx * tx, ly = yn - by * ty, lz = zn - bz * tz;
+    return (lx >= 0 && lx < tx && ly >= 0 && ly < ty && lz >= 0 && lz < tz) ? lx + tx * (ly + ty * lz) : -1;
 }
 
 // S2: storage of links and g, double2 or float2 (single-precision storage).
@@ -1539,18 +1554,19 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
     const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
     const int s3 = x + Lx * (y + Ly * z);
     int fwd3[3], back3[3], sf[2], sb[2];
-    fwd3[0] = (x == Lx - 1) ? s3 - (Lx - 1) : s3 + 1;
-    fwd3[1] = (y == Ly - 1) ? s3 - (Ly - 1) * Lx : s3 + Lx;
-    fwd3[2] = (z == Lz - 1) ? s3 - (Lz - 1) * C.V2 : s3 + C.V2;
-    back3[0] = (x == 0) ? s3 + (Lx - 1) : s3 - 1;
-    back3[1] = (y == 0) ? s3 + (Ly - 1) * Lx : s3 - Lx;
-    back3[2] = (z == 0) ? s3 + (Lz - 1) * C.V2 : s3 - C.V2;
-    const bool lin = C.tile[0] == 0;  // exchange needs the linear site sets
-#pragma unroll
-    for (int mu = 0; mu < 2; ++mu) {
-        sf[mu] = (inside && lin) ? block_slot(b3, fwd3[mu]) : -1;
-        sb[mu] = (inside && lin) ? block_slot(b3, back3[mu]) : -1;
-    }
+    const int xf = (x == Lx - 1) ? 0 : x + 1, xb = (x == 0) ? Lx - 1 : x - 1;
+    const int yf = (y == Ly - 1) ? 0 : y + 1, yb = (y == 0) ? Ly - 1 : y - 1;
+    const int zf = (z == Lz - 1) ? 0 : z + 1, zb = (z == 0) ? Lz - 1 : z - 1;
+    fwd3[0] = s3 + (xf - x);
+    fwd3[1] = s3 + (yf - y) * Lx;
+    fwd3[2] = s3 + (zf - z) * C.V2;
+    back3[0] = s3 + (xb - x);
+    back3[1] = s3 + (yb - y) * Lx;
+    back3[2] = s3 + (zb - z) * C.V2;
+    sf[0] = inside ? block_slot(C, b3, fwd3[0], xf, y, z) : -1;
+    sf[1] = inside ? block_slot(C, b3, fwd3[1], x, yf, z) : -1;
+    sb[0] = inside ? block_slot(C, b3, back3[0], xb, y, z) : -1;
+    sb[1] = inside ? block_slot(C, b3, back3[1], x, yb, z) : -1;
     const int t0 = tc * C.tch;
     dd fs = {0.0, 0.0}, ts = {0.0, 0.0};
     M3 gx;
