@@ -27,27 +27,28 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # FP32 transform fields (c = bytes per complex transform element):
 #   divergence: read 4 links (576) + write 4 packed fields (4c)
 #   transform pass: read + write 4 fields (8c)
-#   gauge: read 4 fields (4c) + write g (144); the inverse (x, y) pass fused
-#     with it writes g in two-row form (96)
+#   gauge: read 4 fields (4c) + write g (144); the inverse (x, y) pass, which
+#     ends the transform, writes the 4 filtered fields (4c) for the fused pass
 #   link update: read 4 links (576) + g(x) (144) + write 4 links (576);
 #     neighbour g(x + mu) is counted once (its own site's read)
-#   fused link update + divergence of the new links, links and g in two-row
-#     (12-real) form: read links (384) + g (96) + write links (384) + 4 fields
-#     (neighbour links and g recomputed from cache)
+#   fused link update + divergence of the new links, links in two-row
+#     (12-real) form, g formed from the 4 filtered fields: read links (384) +
+#     filtered fields (4c) + write links (384) + 4 fields (4c) (neighbour
+#     links and g recomputed from cache)
 #   reduction: negligible (one double-double pair per 256 sites)
 
 
 def kernel_bytes_per_site(name: str, c: int) -> float:
-    if name == "fft_xy_inv_gauge":  # inverse (x, y) pass fused with g: read 4 fields, write two-row g
-        return 4 * c + 96
+    if name == "fft_xy_inv_gauge":  # inverse (x, y) pass: read and write 4 fields
+        return 8 * c
     if name.startswith("delta"):
         return 576 + 4 * c
     if name.startswith("fft"):
         return 8 * c
     if name.startswith("gauge"):
         return 4 * c + 144
-    if name == "link_update_delta":  # fused update + divergence, two-row links and g
-        return 384 + 96 + 384 + 4 * c
+    if name == "link_update_delta":  # fused update + divergence, two-row links, g from the filtered fields
+        return 384 + 4 * c + 384 + 4 * c
     if name.startswith("link_update"):
         return 576 + 144 + 576
     return 0.0

@@ -81,6 +81,7 @@ struct Cfg {
     GF_GLOBAL float2 *U12f[2];   // the same two link buffers in single-precision storage (link_prec 1)
     GF_GLOBAL float2 *g12f;      // two-row g in single-precision storage
     GF_GLOBAL void *fields;      // packed transform fields [4][V], double2 or float2
+    GF_GLOBAL void *fields2;     // the filtered fields Delta~ [4][V] read by the fused pass
     GF_GLOBAL double2 *g;        // gauge field [3][3][V]
     GF_GLOBAL double *partials;  // [nblk_march or nblk_site][4]: (F hi, F lo, theta hi, theta lo)
     GF_GLOBAL Ctrl *ctrl;

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "gf_device.h"
 #include "gf_internal.h"
@@ -1225,8 +1226,10 @@ __device__ __forceinline__ M3 gauge_from_fields(T2 a, T2 b, T2 d, T2 e)
 }
 
 // g goes to g_override (caller, full matrices) if given, else to the
-// workspace: two_row 1 in two-row form (g12, fused path), 2 in two-row
-// single-precision storage (g12f), 0 full (g).
+// workspace: two_row 1 in two-row form (g12, fused path without exchange),
+// 2 in two-row single-precision storage (g12f), 0 full (g). two_row 3: the
+// gauge steps write the filtered fields Delta~ to fields2 instead, and the
+// fused exchange pass (FP64 link storage) forms each g it needs from them.
 __device__ __forceinline__ void store_gauge(const Cfg &C, double2 *g_override, int two_row, int s, const M3 &m)
 {
     if (g_override)
@@ -1251,14 +1254,22 @@ __global__ __launch_bounds__(kSiteBlock) void k_gauge(const Cfg *__restrict__ cf
     const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
     if (s >= V) return;
     const T2 *__restrict__ f = (const T2 *)C.fields;
+    if (two_row == 3 && !g_override) {  // the fused pass forms g itself
+        T2 *__restrict__ o = (T2 *)C.fields2;
+#pragma unroll
+        for (int k = 0; k < kFields; ++k) o[(size_t)k * V + s] = f[(size_t)k * V + s];
+        return;
+    }
     const M3 m = gauge_from_fields(f[s], f[(size_t)V + s], f[(size_t)2 * V + s], f[(size_t)3 * V + s]);
     store_gauge(C, g_override, two_row, s, m);
 }
 
 // Inverse transform over (x, y) of the four fields of Q xy-planes, then g and
 // its projection at every site of the tile (the last steps of the transform
-// and the gauge step in one pass; the fields are not written back). A tile
-// is whole contiguous planes, read once: the field loads are streaming.
+// and the gauge step in one pass; the fields are not written back), or, for
+// the fused exchange pass (two_row 3), the four transformed fields written
+// to fields2. A tile is whole contiguous planes, read once: the field loads
+// are streaming.
 template <typename T2, int CAP, int TH, bool P2>
 __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
                                                          int respect_done, double2 *__restrict__ g_override, int tw2,
@@ -1295,6 +1306,12 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
             tile_put_padded<T2, CAP, TH>(buf, pre, n, C.dims[0], C.xyPad);
             __syncthreads();
         }
+    }
+    if (two_row == 3 && !g_override) {
+        T2 *__restrict__ dst = (T2 *)C.fields2 + site0;
+#pragma unroll
+        for (int f = 0; f < kFields; ++f) tile_store_regs<T2, CAP, TH>(dst + (size_t)f * C.V, val[f], n);
+        return;
     }
 #pragma unroll
     for (int k = 0; k < MS; ++k) {
@@ -1490,15 +1507,12 @@ template <>
 __device__ __forceinline__ double2 *links12<double2>(const Cfg &C, int b) { return C.U12[b]; }
 template <>
 __device__ __forceinline__ float2 *links12<float2>(const Cfg &C, int b) { return C.U12f[b]; }
-template <typename S2>
-__device__ __forceinline__ S2 *gauge12(const Cfg &C);
-template <>
-__device__ __forceinline__ double2 *gauge12<double2>(const Cfg &C) { return C.g12; }
-template <>
-__device__ __forceinline__ float2 *gauge12<float2>(const Cfg &C) { return C.g12f; }
 
-// The fused pass with neighbour exchange through LDS. Per t-slice each
-// work-item publishes its g(x) (two rows) and, after its forward links,
+// The fused pass with neighbour exchange through LDS. With FP64 link storage
+// every g(x) it needs is formed from the filtered fields Delta~ (4 complex
+// numbers per site instead of the 6 of a two-row g) by the same projection
+// the gauge step uses (fused_gauge). Per t-slice each work-item publishes its
+// g(x) (two rows) and, after its forward links,
 // U'_mu(x) - U'_mu(x)^dag for mu = x, y; a neighbour inside the block reads
 // them instead of loading g(x + mu) and recomputing U'_nu(x - nu) from the old
 // links. The z-neighbours, and x and y neighbours in other blocks (the edge
@@ -1527,6 +1541,36 @@ __device__ __forceinline__ int block_slot(const Cfg &C, int b3, int s3n, int xn,
     return (lx >= 0 && lx < tx && ly >= 0 && ly < ty && lz >= 0 && lz < tz) ? lx + tx * (ly + ty * lz) : -1;
 }
 
+// g(x) from the filtered fields Delta~ (transform precision T2), exactly as a
+// g stored in two-row form S2 reads back: rows 0 and 1 rounded to S2 (no-op
+// for double2), row 2 rebuilt from them.
+template <typename T2, typename S2>
+__device__ __forceinline__ M3 gauge_at(const T2 *__restrict__ f, int V, int s)
+{
+    M3 m = gauge_from_fields(f[s], f[(size_t)V + s], f[(size_t)2 * V + s], f[(size_t)3 * V + s]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        S2 v;
+        narrow(v, m.e[k]);
+        m.e[k] = widen(v);
+    }
+    m3_row2(m);
+    return m;
+}
+
+// g(x) in the fused pass. FP64 link storage: formed from the filtered fields
+// (64 or 32 bytes instead of a 96-byte two-row g). Single-precision storage:
+// the stored binary32 two-row g (48 bytes; forming it from 32 bytes of fields
+// costs more in projections than it saves, 4 % at 32^4).
+template <typename T2, typename S2>
+__device__ __forceinline__ M3 fused_gauge(const Cfg &C, int s)
+{
+    if constexpr (std::is_same<S2, float2>::value)
+        return m3_load12s((const float2 *)C.g12f, C.V, s);
+    else
+        return gauge_at<T2, S2>((const T2 *)C.fields2, C.V, s);
+}
+
 // S2: storage of links and g, double2 or float2 (single-precision storage).
 template <typename T2, bool RU, typename S2>
 __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__restrict__ cfgs,
@@ -1543,7 +1587,6 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
     const int V = C.V, V3 = C.V3;
     const S2 *__restrict__ Uo = links12<S2>(C, ct->cur);
     S2 *__restrict__ Un = links12<S2>(C, ct->cur ^ 1);
-    const S2 *__restrict__ G = gauge12<S2>(C);
     const bool reunit = C.reunit_every > 0 && ct->ru_now;
     if (reunit != RU) return;
     const int lb = blk - B->off_march[c];
@@ -1572,9 +1615,9 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
     M3 gx;
     AH utp;  // U'_t(x - t) - h.c.
     if (inside) {
-        gx = m3_load12s(G, V, s3 + V3 * t0);
+        gx = fused_gauge<T2, S2>(C, s3 + V3 * t0);
         const int sp = s3 + V3 * ((t0 == 0) ? Lt - 1 : t0 - 1);
-        M3 w = m3_mul_mul_dag_rows(m3_load12s(G, V, sp), m3_load12s(Uo + (size_t)18 * V, V, sp), gx);
+        M3 w = m3_mul_mul_dag_rows(fused_gauge<T2, S2>(C, sp), m3_load12s(Uo + (size_t)18 * V, V, sp), gx);
         if (RU) m3_reunit(w);
         utp = ah_of(w);
     }
@@ -1600,7 +1643,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                     for (int k = 0; k < 6; ++k) gf.e[k] = sg[k][sf[mu]];
                     m3_row2(gf);
                 } else {
-                    gf = m3_load12s(G, V, fwd3[mu] + V3 * t);
+                    gf = fused_gauge<T2, S2>(C, fwd3[mu] + V3 * t);
                 }
                 // U_x(x) and U_y(x) are read again only at the block's edge
                 // rows; U_z(x) is the backward neighbour of the next
@@ -1626,7 +1669,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
             }
             {
                 const int tn = (t + 1 == Lt) ? 0 : t + 1;
-                gn = m3_load12s(G, V, s3 + V3 * tn);
+                gn = fused_gauge<T2, S2>(C, s3 + V3 * tn);
                 const size_t off = (size_t)18 * V;
                 M3 w = m3_mul_mul_dag_rows(gx, m3_load12s_stream(Uo + off, V, s), gn);
                 if (RU) m3_reunit(w);
@@ -1651,7 +1694,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                     a.d2 = sa[nu][8][o];
                 } else {
                     const int sbk = back3[nu] + V3 * t;
-                    M3 wb = m3_mul_mul_dag_rows(m3_load12s(G, V, sbk), m3_load12s(Uo + (size_t)nu * 6 * V, V, sbk), gx);
+                    M3 wb = m3_mul_mul_dag_rows(fused_gauge<T2, S2>(C, sbk), m3_load12s(Uo + (size_t)nu * 6 * V, V, sbk), gx);
                     if (RU) m3_reunit(wb);
                     a = ah_of(wb);
                 }
@@ -2034,7 +2077,7 @@ hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *
 
 // Where the gauge passes put g: 0 full (g), 1 two-row FP64 (g12), 2 two-row
 // single-precision storage (g12f).
-static int gauge_store_mode(const Launch &L) { return L.fused ? (L.link_f32 ? 2 : 1) : 0; }
+static int gauge_store_mode(const Launch &L) { return L.fused ? (L.link_f32 ? 2 : (L.xchg ? 3 : 1)) : 0; }
 
 // (tile capacity, work-group size) instances of the 2D passes: 4 or 8
 // elements per work-item.

@@ -172,7 +172,7 @@ FftAxis plan_axis(const int dims[4], int mu)
 }
 
 struct Layout {
-    size_t fields, g, partials, sin2, tw, links12a, links12b, g12, kmom, links12fa, links12fb, g12f, total;
+    size_t fields, fields2, g, partials, sin2, tw, links12a, links12b, g12, kmom, links12fa, links12fb, g12f, total;
 };
 
 Layout layout_for(const gf_params &p, size_t start)
@@ -187,6 +187,8 @@ Layout layout_for(const gf_params &p, size_t start)
     Layout l;
     size_t o = align_up(start);
     l.fields = o;
+    o = align_up(o + kFields * V * csz);
+    l.fields2 = o;
     o = align_up(o + kFields * V * csz);
     l.g = o;
     o = align_up(o + 9 * V * 16);
@@ -962,6 +964,7 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         C.U12f[1] = l.links12fb ? (float2 *)(c->ws + l.links12fb) : nullptr;
         C.g12f = l.g12f ? (float2 *)(c->ws + l.g12f) : nullptr;
         C.fields = c->ws + l.fields;
+        C.fields2 = c->ws + l.fields2;
         C.g = (double2 *)(c->ws + l.g);
         C.partials = (double *)(c->ws + l.partials);
         C.ctrl = (Ctrl *)(c->ws + ctrl_base) + k;
