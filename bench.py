@@ -501,7 +501,7 @@ def _source_hash():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("csrc/gf_kernels.hip", "csrc/gf_device.h", "csrc/gf_internal.h", "build.py"):
+    for f in ("csrc/gf_kernels.hip", "csrc/gf_device.h", "csrc/gf_internal.h", "csrc/gf_runtime.hip", "build.py"):
         with open(os.path.join(ROOT, "paper_1210_8018_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
