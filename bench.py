@@ -195,7 +195,8 @@ def main():
     if os.path.exists(traffic_file):
         try:
             t = json.load(open(traffic_file))
-            if t.get("kernel") == dom_name and t.get("source_hash") == _source_hash():
+            same_shape = t.get("workload", "").split(" ")[0] == "x".join(str(d) for d in dims)
+            if t.get("kernel") == dom_name and t.get("source_hash") == _source_hash() and same_shape:
                 traffic = t.get("bytes_per_launch")
         except Exception:
             traffic = None
