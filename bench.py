@@ -72,6 +72,8 @@ def main():
                     choices=["headline", "batch", "large48", "large64", "diff", "thermal"])
     ap.add_argument("--beta", type=float, default=6.0)
     ap.add_argument("--sweeps", type=int, default=300)
+    ap.add_argument("--fft-schedule", type=int, default=0,
+                    help="transform schedule of the headline contexts (0: autotuned; see gf_params.fft_schedule)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -103,7 +105,7 @@ def main():
         tag = "fp64" if prec == 0 else "fp32_fft"
         # throughput: K iterations regardless of theta
         U = U0.clone()
-        fx = GaugeFixer(U, fft_prec=prec)
+        fx = GaugeFixer(U, fft_prec=prec, fft_schedule=args.fft_schedule)
         log(f"[{tag}] warmup {args.warmup}")
         fx.step(args.warmup)
         torch.cuda.synchronize()
@@ -128,7 +130,7 @@ def main():
         del fx, U
         # time to theta <= 1e-15 from the generated configuration
         U = U0.clone()
-        fx = GaugeFixer(U, fft_prec=prec)
+        fx = GaugeFixer(U, fft_prec=prec, fft_schedule=args.fft_schedule)
         torch.cuda.synchronize()
         log(f"[{tag}] fix_until 1e-15")
         t2 = time.perf_counter()
@@ -146,7 +148,7 @@ def main():
     # in binary32, FP64 arithmetic) with the FP32 transform; fix_until then
     # refines in FP64 storage from theta <= 1e-10 down to 1e-15
     U = U0.clone()
-    fx = GaugeFixer(U, fft_prec=1, link_prec=1)
+    fx = GaugeFixer(U, fft_prec=1, link_prec=1, fft_schedule=args.fft_schedule)
     fx.step(args.warmup)
     torch.cuda.synchronize()
     log(f"[sp_links] timed {args.steps} steps")
@@ -161,7 +163,7 @@ def main():
     fx.close()
     del fx, U
     U = U0.clone()
-    fx = GaugeFixer(U, fft_prec=1, link_prec=1, refine_theta=1e-10)
+    fx = GaugeFixer(U, fft_prec=1, link_prec=1, refine_theta=1e-10, fft_schedule=args.fft_schedule)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     it, F, th = fx.fix_until(1e-15, 100000)

@@ -194,6 +194,23 @@ gf_status gf_fix_until_batch(gf_ctx ctx, double theta_eps, int64_t max_iter, int
                              double *theta);
 /* F and theta of every configuration of a batch context (host arrays). */
 gf_status gf_functional_batch(gf_ctx ctx, double *F, double *theta);
+/* gf_history for configuration k (0 <= k < n_cfg) of a batch context (also
+ * k = 0 of a single-configuration one): the (F, theta) that Alg. 1 monitors
+ * after each of that configuration's updates. GF_ERR_ARG for k out of range. */
+gf_status gf_history_batch(gf_ctx ctx, int32_t k, int64_t cap, double *F_hist, double *theta_hist, int64_t *n);
+
+/*
+ * A context for the differentiable functional only (the two calls below):
+ * its workspace holds g [3][3][V] and the per-block partial sums
+ * (gf_workspace_bytes_functional bytes, about 144 B per site, instead of the
+ * iteration's buffers); init neither measures the links nor plans or tunes
+ * the transform. The iteration and stage calls return GF_ERR_STATE on it.
+ * Arguments as for gf_init; the links are read (never written) by the
+ * functional calls, at whatever they hold when a call is made.
+ */
+size_t gf_workspace_bytes_functional(const gf_params *params);
+gf_status gf_init_functional(gf_ctx *ctx, const gf_params *params, void *d_links, void *d_ws, size_t ws_bytes,
+                             void *stream);
 
 /*
  * Differentiable functional (Eq. 1 as a function of gauge parameters):

@@ -44,6 +44,7 @@ def lib():
             "or_delta": (None, [P, P, P]),
             "or_measure": (None, [P, P, P, P]),
             "or_fft4d": (None, [P, P, ctypes.c_int]),
+            "or_set_fft_axis_order": (None, [P]),
             "or_momentum_factor": (None, [P, D, P]),
             "or_reunit": (None, [P]),
             "or_gauge_from_delta": (None, [P, P, D, P]),
@@ -51,6 +52,7 @@ def lib():
             "or_reunit_links": (None, [P, P]),
             "or_fix": (I64, [P, P, D, D, I64, ctypes.c_int, P, P, I64]),
             "or_fix_f32_storage": (I64, [P, P, D, D, I64, ctypes.c_int, P, P, I64]),
+            "or_fix_two_row": (I64, [P, P, D, D, I64, ctypes.c_int, P, P, I64]),
             "or_store_f32": (None, [P, P, ctypes.c_int]),
             "or_plaquette": (D, [P, P]),
             "or_polyakov": (None, [P, P, P, P]),
@@ -169,22 +171,50 @@ def reunit_links(dims, U):
     return U
 
 
-def fix(dims, U, alpha=0.08, eps=1e-15, max_iter=100000, reunit_every=0, hist_cap=None, f32_storage=False):
+def set_fft_axis_order(order=(0, 1, 2, 3)):
+    """Order in which the 4D transform takes the axes (a permutation of 0..3)."""
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    lib().or_set_fft_axis_order(_p(o))
+
+
+def fix(dims, U, alpha=0.08, eps=1e-15, max_iter=100000, reunit_every=0, hist_cap=None, f32_storage=False,
+        fft_axis_order=None, two_row=False):
     """Alg. 1 on a copy of U. Returns (iters, U_final, F_hist, theta_hist).
 
     f32_storage: links and g kept in single-precision 12-real storage
     (or_fix_f32_storage); U_final is then the stored links.
+    two_row: the 12-real representation kept in FP64 (or_fix_two_row).
+    fft_axis_order: the transform's axis order for this run (default x, y, z, t).
     """
+    if fft_axis_order is not None:
+        set_fft_axis_order(fft_axis_order)
+        try:
+            return fix(dims, U, alpha, eps, max_iter, reunit_every, hist_cap, f32_storage, two_row=two_row)
+        finally:
+            set_fft_axis_order()
     U = np.array(U, dtype=np.complex128, copy=True)
     d = _dims(dims)
     cap = int(max_iter) + 1 if hist_cap is None else int(hist_cap)
     cap = min(cap, 10_000_000)
     Fh = np.zeros(cap, dtype=np.float64)
     Th = np.zeros(cap, dtype=np.float64)
-    f = lib().or_fix_f32_storage if f32_storage else lib().or_fix
+    f = lib().or_fix_f32_storage if f32_storage else (lib().or_fix_two_row if two_row else lib().or_fix)
     n = f(_p(d), _p(U), float(alpha), float(eps), int(max_iter), int(reunit_every), _p(Fh), _p(Th), cap)
     k = min(n + 1, cap)
     return int(n), U, Fh[:k].copy(), Th[:k].copy()
+
+
+def rounding_spread(dims, U, alpha=0.08, eps=1e-15, max_iter=100000, reunit_every=0):
+    """Per-iteration relative differences of F and theta between two FP64 runs of
+    Alg. 1 that differ only in the transform's axis order (x, y, z, t against
+    t, z, y, x): the spread of two correct implementations, over the iterations
+    both made. Returns (dF, dtheta, iters_default, iters_reversed)."""
+    n0, _, F0, T0 = fix(dims, U, alpha, eps, max_iter, reunit_every)
+    n1, _, F1, T1 = fix(dims, U, alpha, eps, max_iter, reunit_every, fft_axis_order=(3, 2, 1, 0))
+    k = min(len(F0), len(F1))
+    dF = np.abs(F1[:k] - F0[:k]) / np.abs(F0[:k]).clip(1e-300)
+    dT = np.abs(T1[:k] - T0[:k]) / np.abs(T0[:k]).clip(1e-300)
+    return dF, dT, n0, n1
 
 
 def store_f32(dims, M):

@@ -250,12 +250,34 @@ static void dft_rec(const cplx *in, int64_t stride, cplx *out, int n, int sign, 
     if (t != tmp) free(t);
 }
 
+/*
+ * Order in which or_fft4d takes the axes (default x, y, z, t). The separable
+ * transform is the same in exact arithmetic for every order; another order
+ * only rounds differently. Test infrastructure uses it to size the spread
+ * between two correct FP64 runs of Alg. 1 (the tolerance of theta at its
+ * rounding floor). Not thread-safe; a permutation of 0..3 or ignored.
+ */
+static int fft_axis_order[4] = {0, 1, 2, 3};
+
+void or_set_fft_axis_order(const int order[4])
+{
+    int seen = 0;
+    for (int a = 0; a < 4; ++a) {
+        if (order[a] < 0 || order[a] > 3) return;
+        seen |= 1 << order[a];
+    }
+    if (seen != 15) return;
+    for (int a = 0; a < 4; ++a) fft_axis_order[a] = order[a];
+}
+
 /* In-place unnormalised 4D transform of one complex field f[s], sign -1 (forward) or +1. */
 void or_fft4d(const int L[4], cplx *f, int sign)
 {
     const int64_t V = vol(L);
-    int64_t stride = 1;
-    for (int mu = 0; mu < 4; ++mu) {
+    for (int a = 0; a < 4; ++a) {
+        const int mu = fft_axis_order[a];
+        int64_t stride = 1; /* distance between consecutive elements along mu */
+        for (int nu = 0; nu < mu; ++nu) stride *= L[nu];
         const int n = L[mu];
         const int64_t inner = stride, outer = V / (stride * n);
         const int64_t pencils = inner * outer;
@@ -277,7 +299,6 @@ void or_fft4d(const int L[4], cplx *f, int sign)
             free(res);
         }
         free(roots);
-        stride *= n;
     }
 }
 
@@ -452,8 +473,32 @@ void or_store_f32(const int L[4], cplx *M, int nmat) { two_row_field(L, M, nmat,
  * stored. On return U holds the stored links. Histories and return value as
  * or_fix.
  */
+static int64_t fix_two_row(const int L[4], cplx *U, double alpha, double eps, int64_t max_iter, int reunit_every,
+                           double *F_hist, double *theta_hist, int64_t hist_cap, int round_f32);
+
 int64_t or_fix_f32_storage(const int L[4], cplx *U, double alpha, double eps, int64_t max_iter, int reunit_every,
                            double *F_hist, double *theta_hist, int64_t hist_cap)
+{
+    return fix_two_row(L, U, alpha, eps, max_iter, reunit_every, F_hist, theta_hist, hist_cap, 1);
+}
+
+/*
+ * Alg. 1 with the 12-real representation of section 2.2 kept in FP64: as
+ * or_fix_f32_storage without the binary32 rounding (every stored link and g
+ * is its two rows, the third rebuilt as conj(r0 x r1)). Equal to or_fix in
+ * exact arithmetic for special unitary links; it rounds differently (each
+ * rebuilt row differs from the full product's by O(1e-16)), which sizes the
+ * spread of theta at its rounding floor between two correct FP64 codes that
+ * store links in the paper's two forms.
+ */
+int64_t or_fix_two_row(const int L[4], cplx *U, double alpha, double eps, int64_t max_iter, int reunit_every,
+                       double *F_hist, double *theta_hist, int64_t hist_cap)
+{
+    return fix_two_row(L, U, alpha, eps, max_iter, reunit_every, F_hist, theta_hist, hist_cap, 0);
+}
+
+static int64_t fix_two_row(const int L[4], cplx *U, double alpha, double eps, int64_t max_iter, int reunit_every,
+                           double *F_hist, double *theta_hist, int64_t hist_cap, int round_f32)
 {
     const int64_t V = vol(L);
     cplx *Delta = malloc(sizeof(cplx) * 9 * V);
@@ -462,7 +507,7 @@ int64_t or_fix_f32_storage(const int L[4], cplx *U, double alpha, double eps, in
     double F, theta;
     memcpy(Ux, U, sizeof(cplx) * 36 * V);
     or_measure(L, Ux, &F, &theta);
-    or_store_f32(L, U, 4);
+    two_row_field(L, U, 4, round_f32);
     if (hist_cap > 0) {
         F_hist[0] = F;
         theta_hist[0] = theta;
@@ -471,7 +516,7 @@ int64_t or_fix_f32_storage(const int L[4], cplx *U, double alpha, double eps, in
     while (!(theta <= eps) && it < max_iter) {
         or_delta(L, Ux, Delta);
         or_gauge_from_delta(L, Delta, alpha, g);
-        or_store_f32(L, g, 1);
+        two_row_field(L, g, 1, round_f32);
         memcpy(Ux, U, sizeof(cplx) * 36 * V);
         or_apply_gauge(L, Ux, g);
         ++it;
@@ -479,7 +524,7 @@ int64_t or_fix_f32_storage(const int L[4], cplx *U, double alpha, double eps, in
         two_row_field(L, Ux, 4, 0);
         or_measure(L, Ux, &F, &theta);
         memcpy(U, Ux, sizeof(cplx) * 36 * V);
-        or_store_f32(L, U, 4);
+        two_row_field(L, U, 4, round_f32);
         if (it < hist_cap) {
             F_hist[it] = F;
             theta_hist[it] = theta;

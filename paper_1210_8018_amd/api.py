@@ -7,6 +7,8 @@ buffers with torch and passes pointers.
 """
 from __future__ import annotations
 
+from collections import OrderedDict
+
 import torch
 
 from . import gf
@@ -140,6 +142,10 @@ class BatchGaugeFixer:
         it, F, th, _ = gf.gf_fix_until_batch(self.ctx, self.n, theta_eps, max_iter, allow_maxiter)
         return it, F, th
 
+    def history(self, k: int):
+        """Lists (F_j, theta_j) of configuration k, j = 0 (initial) .. its number of updates."""
+        return gf.gf_history_batch(self.ctx, k)
+
     @property
     def fft_schedule(self) -> int:
         return gf.gf_fft_schedule(self.ctx)
@@ -165,20 +171,56 @@ class BatchGaugeFixer:
             pass
 
 
+_FN_CACHE_SIZE = 8
+_fn_contexts = OrderedDict()
+
+
+def _functional_context(U: torch.Tensor):
+    """A functional-only library context for links U (cached per device,
+    address, shape and stream; it holds no reference to U, only its address,
+    and every call reads whatever U holds then)."""
+    stream = torch.cuda.current_stream(U.device)
+    key = (U.device.index, U.data_ptr(), dims_of(U), stream.cuda_stream)
+    ent = _fn_contexts.get(key)
+    if ent is not None:
+        _fn_contexts.move_to_end(key)
+        return ent[0]
+    params = gf.make_params(dims_of(U))
+    nbytes = gf.gf_workspace_bytes_functional(params)
+    if nbytes == 0:
+        raise ValueError(f"unsupported dims {dims_of(U)}")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=U.device)
+    ctx = gf.gf_init_functional(params, U, ws, stream)
+    _fn_contexts[key] = (ctx, ws)
+    while len(_fn_contexts) > _FN_CACHE_SIZE:
+        _, (old, _) = _fn_contexts.popitem(last=False)
+        gf.gf_destroy(old)
+    return ctx
+
+
+def _check_omega(omega: torch.Tensor, U: torch.Tensor):
+    V = U.numel() // 36
+    if (omega.dtype != torch.float64 or not omega.is_cuda or omega.device != U.device
+            or omega.dim() < 1 or omega.shape[0] != 8 or omega.numel() != 8 * V):
+        raise ValueError(f"omega must be a float64 tensor of shape (8, V = {V}) on {U.device}")
+
+
 class GaugeFunctional(torch.autograd.Function):
     """F_U[g] of Eq. 1 with g(x) = exp(i sum_a lambda_a omega_a(x)); differentiable in U and omega.
 
-    U: complex128 (4, 3, 3, Lt, Lz, Ly, Lx) CUDA tensor; omega: float64 (8, V).
-    The gradient with respect to U follows torch's convention dF/dRe U + i dF/dIm U.
+    U: complex128 (4, 3, 3, Lt, Lz, Ly, Lx) CUDA tensor; omega: float64 (8, V)
+    on the same device. The gradient with respect to U follows torch's
+    convention dF/dRe U + i dF/dIm U. Forward and backward run in a
+    functional-only context (g and block partials, ~144 B per site), reused
+    while U stays the same tensor.
     """
 
     @staticmethod
     def forward(ctx, U: torch.Tensor, omega: torch.Tensor):
         _check_links(U)
+        _check_omega(omega, U)
         omega = omega.contiguous()
-        fx = GaugeFixer(U)
-        F = gf.gf_functional_g(fx.ctx, omega)
-        fx.close()
+        F = gf.gf_functional_g(_functional_context(U), omega)
         ctx.save_for_backward(U, omega)
         return torch.tensor(F, dtype=torch.float64, device=U.device)
 
@@ -189,9 +231,7 @@ class GaugeFunctional(torch.autograd.Function):
         d_omega = torch.empty_like(omega) if ctx.needs_input_grad[1] else None
         d_U = torch.empty_like(U) if ctx.needs_input_grad[0] else None
         if d_omega is not None or d_U is not None:
-            fx = GaugeFixer(U)
-            gf.gf_functional_g_backward(fx.ctx, omega, g, d_omega, d_U)
-            fx.close()
+            gf.gf_functional_g_backward(_functional_context(U), omega, g, d_omega, d_U)
         return d_U, d_omega
 
 

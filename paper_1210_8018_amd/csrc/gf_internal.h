@@ -50,6 +50,7 @@ struct Ctrl {
     int done;            // kRunning / kConverged / kMaxIter / kNonFinite
     int cur;             // current two-row link buffer, U12[cur]
     int ru_now;          // this iteration also projects the new links (set before the fused pass)
+    int in_caller;       // the current links are the caller's array U (full 3x3), not U12[cur]
     int pad2;
     double hist[kHist][2];  // (F, theta) after update k at slot k % kHist
 };
@@ -77,7 +78,6 @@ struct Cfg {
     int nblk_march;       // nb3 * (Lt / tch): blocks of the marching kernels
     GF_GLOBAL double2 *U;        // links [4][3][3][V] (the caller's array)
     GF_GLOBAL double2 *U12[2];   // two-row links [4][2][3][V], two buffers (workspace)
-    GF_GLOBAL double2 *g12;      // two-row gauge field [2][3][V] (workspace)
     GF_GLOBAL float2 *U12f[2];   // the same two link buffers in single-precision storage (link_prec 1)
     GF_GLOBAL float2 *g12f;      // two-row g in single-precision storage
     GF_GLOBAL void *fields;      // packed transform fields [4][V], double2 or float2
@@ -97,6 +97,8 @@ struct Cfg {
     int ztP, nzt;         // zt pass: P consecutive xy-sites per tile, nzt tiles per field
     int xyPad;            // LDS elements added to every x-row of an xy tile (bank spreading)
     int ztPad;            // LDS elements added to every t-plane of a zt tile
+    int zt_reg;           // the scaled (z, t) pass runs in k_fft_zt_reg (Lz = Lt = 32, ztP = 2)
+    int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 32, xyQ = 2)
 };
 
 // Block-to-configuration maps for every launch shape of a batch: entry e
@@ -127,10 +129,13 @@ struct Launch {
     int ax_p2[4], ax_gen[4];       // same for the 1D passes of each axis
     int xy_tw2, xy_tw_total;       // LDS twiddle layout of the xy pass: y table offset, entries
     int zt_tw2, zt_tw_total;       // same for the zt pass
+    int zt_reg_any, zt_lds_any;    // scaled zt pass: some configuration in k_fft_zt_reg / in k_fft_zt
+    int zt_reg_groups;             // work-groups per tile of k_fft_zt_reg (1, 2 or 4: fields split among them)
+    int xy_reg_any, xy_lds_any;    // iteration's xy passes: some configuration in the register / LDS-staged ones
+    int xy_reg_groups;             // work-groups per tile of the register xy passes
     int max_lds_elems;    // 1D passes: largest P * L
     int fp32;             // transform precision
     int fused;            // iterations use the fused update + divergence kernel
-    int xchg;             // ... in its LDS neighbour-exchange form
     int link_f32;         // links and g held in single-precision two-row storage (this phase)
     int any_reunit;       // some configuration projects its links every R updates
     int ncfg;
@@ -138,6 +143,8 @@ struct Launch {
 };
 
 hipError_t launch_arm(const Launch &L, int ncfg, double eps, long long add_iters, int reset_iter);
+// the same for configuration k alone
+hipError_t launch_arm_one(const Launch &L, int k, double eps, long long add_iters, int reset_iter);
 hipError_t launch_delta(const Launch &L, int respect_done, double2 *full_delta);
 hipError_t launch_reduce(const Launch &L, int ncfg, int count_iter, int respect_done);
 hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *fields_override,
@@ -153,7 +160,12 @@ hipError_t launch_fft_zt_scale(const Launch &L, int respect_done);
 hipError_t set_lds_limits();
 hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override);
 hipError_t launch_update(const Launch &L, int respect_done, const double2 *g_override);
-hipError_t launch_update_delta(const Launch &L);
+// Where the fused pass of an update takes the old links from and puts the
+// new ones (FP64 link storage): the two-row buffers, or the caller's array
+// for the first update of a call (old links) or the last of a gf_step call
+// (new links).
+enum : int { kLinksBuffers = 0, kLinksFromCaller = 1, kLinksToCaller = 2 };
+hipError_t launch_update_delta(const Launch &L, int link_io);
 hipError_t launch_pack_links(const Launch &L);
 hipError_t launch_momentum_table(const Launch &L);
 hipError_t launch_heatbath_sweep(const Launch &L, int V, int mode, double beta, uint64_t seed, long long n);

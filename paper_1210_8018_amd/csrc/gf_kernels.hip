@@ -1060,6 +1060,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(CAP / TH >= 
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     if (P2 != xy_is_p2(C)) return;  // the other instance takes it
+    if (C.xy_reg && !fields_override) return;  // k_fft_xy_reg takes it
     const int t = tile - B->off_xy[c];
     const int n = C.xyQ * C.V2;
     T2 *buf = (T2 *)smem;
@@ -1105,6 +1106,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(CAP / TH >= 
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     if (P2 != zt_is_p2(C)) return;  // the other instance takes it
+    if (mode == 1 && C.zt_reg) return;  // k_fft_zt_reg takes it
     const int t = tile - B->off_zt[c];
     const int P = C.ztP, Lz = C.dims[2], Lt = C.dims[3], V2 = C.V2;
     const int n = P * Lz * Lt;
@@ -1199,6 +1201,361 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(CAP / TH >= 
     }
 }
 
+// ============================================================ (z, t) pass, 32 x 32 planes, radix stages in registers
+// For Lz = Lt = 32 the scaled (z, t) pass (forward, K(p), backward) keeps
+// each 32-point pencil in the registers of four lanes of one wave (lane
+// offsets 0, 16, 32, 48; 8 elements each) and runs both radix stages of an
+// axis there: an 8-point DFT per lane, the twiddles exp(-2 pi i j k1 / 32),
+// an exchange among the four lanes by the gfx950 lane-swap instructions (no
+// LDS, no barrier), and 4-point DFTs. LDS is used only to move the tile from
+// z-pencils to t-pencils and back (two transposes per field) instead of one
+// round trip per radix stage. The forward transform leaves its outputs in the
+// order the exchange produces; the backward transform takes them in that
+// order (the stages mirrored), so no reordering pass is needed.
+
+// Swap of `a`'s lanes 32..63 with `b`'s lanes 0..31, and of `a`'s odd
+// 16-lane rows with `b`'s even rows, per 32-bit word.
+__device__ __forceinline__ void lane_swap32(unsigned &a, unsigned &b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+}
+__device__ __forceinline__ void lane_swap16(unsigned &a, unsigned &b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+}
+template <bool W32>
+__device__ __forceinline__ void lane_swap(double &a, double &b)
+{
+    unsigned long long ua = __builtin_bit_cast(unsigned long long, a), ub = __builtin_bit_cast(unsigned long long, b);
+    unsigned alo = (unsigned)ua, ahi = (unsigned)(ua >> 32), blo = (unsigned)ub, bhi = (unsigned)(ub >> 32);
+    if constexpr (W32) {
+        lane_swap32(alo, blo);
+        lane_swap32(ahi, bhi);
+    } else {
+        lane_swap16(alo, blo);
+        lane_swap16(ahi, bhi);
+    }
+    a = __builtin_bit_cast(double, (unsigned long long)alo | ((unsigned long long)ahi << 32));
+    b = __builtin_bit_cast(double, (unsigned long long)blo | ((unsigned long long)bhi << 32));
+}
+template <bool W32>
+__device__ __forceinline__ void lane_swap(float &a, float &b)
+{
+    unsigned ua = __builtin_bit_cast(unsigned, a), ub = __builtin_bit_cast(unsigned, b);
+    if constexpr (W32)
+        lane_swap32(ua, ub);
+    else
+        lane_swap16(ua, ub);
+    a = __builtin_bit_cast(float, ua);
+    b = __builtin_bit_cast(float, ub);
+}
+template <bool W32, typename T2>
+__device__ __forceinline__ void lane_swap(T2 &a, T2 &b)
+{
+    lane_swap<W32>(a.x, b.x);
+    lane_swap<W32>(a.y, b.y);
+}
+
+// The exchange among the four lanes j = 2 a + c (lane offset 32 a + 16 c) of
+// a pencil: before, lane j holds Y_j[k1] at R[k1] (k1 = 0..7); after, lane j
+// holds Y_jj[2 j + e] at R[2 jj + e] (jj = 0..3, e = 0, 1). First the lanes
+// 32 apart trade the halves k1 >= 4 (a = 0) and k1 < 4 (a = 1), leaving
+// R[m + 4 a'] = Y_{2 a' + c}[4 a + m]; then the lanes 16 apart trade the
+// quarters the same way. Each step is its own inverse, so the reverse
+// exchange runs them in the opposite order.
+template <typename T2>
+__device__ __forceinline__ void pencil_exchange(T2 (&R)[8])
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m) lane_swap<true>(R[m], R[m + 4]);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) lane_swap<false>(R[4 * a + e], R[4 * a + 2 + e]);
+}
+template <typename T2>
+__device__ __forceinline__ void pencil_exchange_back(T2 (&R)[8])
+{
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) lane_swap<false>(R[4 * a + e], R[4 * a + 2 + e]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) lane_swap<true>(R[m], R[m + 4]);
+}
+
+// Forward 32-point DFT X[k] = sum_n x[n] exp(-2 pi i n k / 32) of a pencil
+// spread over four lanes, n = 4 n2 + j:
+//   X[k1 + 8 k2] = sum_j exp(-2 pi i j k2 / 4) exp(-2 pi i j k1 / 32) Y_j[k1],
+//   Y_j[k1] = sum_n2 x[4 n2 + j] exp(-2 pi i n2 k1 / 8).
+// On entry R[n2] = x[4 n2 + j]; on return R[2 k2 + e] = X[2 j + e + 8 k2].
+// tw[k1] = exp(-2 pi i j k1 / 32) for this lane's j.
+template <typename T2>
+__device__ __forceinline__ void pencil32_forward(T2 (&R)[8], const T2 (&tw)[8])
+{
+    dft8(R, -1);
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) R[k1] = t_mul(R[k1], tw[k1]);
+    pencil_exchange(R);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) dft4r(R[e], R[2 + e], R[4 + e], R[6 + e], -1);
+}
+
+// Backward 32-point DFT x[n] = sum_k X[k] exp(+2 pi i n k / 32) (unnormalised)
+// from the layout pencil32_forward leaves, back to R[n2] = x[4 n2 + j]:
+//   x[4 n2 + j] = sum_k1 exp(2 pi i n2 k1 / 8) exp(2 pi i j k1 / 32) Z_k1[j],
+//   Z_k1[j] = sum_k2 X[k1 + 8 k2] exp(2 pi i j k2 / 4).
+template <typename T2>
+__device__ __forceinline__ void pencil32_backward(T2 (&R)[8], const T2 (&tw)[8])
+{
+#pragma unroll
+    for (int e = 0; e < 2; ++e) dft4r(R[e], R[2 + e], R[4 + e], R[6 + e], +1);
+    pencil_exchange_back(R);
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) {
+        T2 w = tw[k1];
+        w.y = -w.y;
+        R[k1] = t_mul(R[k1], w);
+    }
+    dft8(R, +1);
+}
+
+// LDS layout of a 2 x 32 x 32 tile (p, z, t): p + 2 z + kZtRegTp t. The
+// t-plane stride is 2 (mod 8) elements, so the 8 lanes an LDS access serves
+// together (2 values of p times 4 t-planes when z-pencils write, 2 p times 4
+// z when t-pencils read) fall on distinct banks.
+#ifndef GF_ZT_REG_TP
+#define GF_ZT_REG_TP 66
+#endif
+constexpr int kZtRegTp = GF_ZT_REG_TP;
+constexpr int kZtRegP = 2;  // xy-sites per tile
+
+// The scaled (z, t) pass over configurations with Lz = Lt = 32 (C.zt_reg):
+// a work-group of 256 work-items (four waves) transforms kFields / ngroups
+// of the four fields of its tile, kZtRegP consecutive xy-sites times the
+// (z, t) plane, one after the other; the ngroups work-groups of a tile are
+// consecutive (one XCD, whose L2 then serves the tile's K(p) to all of
+// them). Work-item (w, q, j), lane q + 16 j of wave w, holds the pencil
+// (p, r) = (q mod 2, 8 w + q / 2) along z (elements z = 4 n2 + j, r = t),
+// then along t (elements t = 4 n2 + j, r = z).
+template <typename T2>
+__global__ __launch_bounds__(256) void k_fft_zt_reg(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                    int respect_done, int ngroups)
+{
+    using T = typename Cx<T2>::T;
+    __shared__ T2 buf[32 * kZtRegTp];
+    const int rb = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = rb / ngroups, grp = rb - tile * ngroups;
+    const int nfg = kFields / ngroups, f0 = grp * nfg;
+    const int c = find_cfg(B->off_zt, B->n, tile);
+    const Cfg &C = cfgs[B->idx[c]];
+    if (respect_done && C.ctrl->done) return;
+    if (!C.zt_reg) return;  // the LDS-staged pass takes it
+    const int V2 = C.V2;
+    const int i0 = (tile - B->off_zt[c]) * kZtRegP;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane & 15, j = lane >> 4;
+    const int p = q & 1, r = 8 * w + (q >> 1);
+    // twiddles exp(-2 pi i j k1 / 32), the same table for z and t
+    T2 tw[8];
+    {
+        const T2 *__restrict__ tz = (const T2 *)C.tw + C.tw_off[2];
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) tw[k1] = tz[(j * k1) & 31];
+    }
+    // K(p) of the elements a work-item holds after the forward t transform:
+    // momentum (xy-site i0 + p, kz = r, kt = 2 j + e + 8 k2) at R[2 k2 + e]
+    T kreg[8];
+    {
+        const T *__restrict__ Km = (const T *)C.kmom + i0 + p;
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) kreg[2 * k2 + e] = Km[(size_t)(r + 32 * (2 * j + e + 8 * k2)) * V2];
+    }
+    // z-pencil element n2 (z = 4 n2 + j, t = r) of field f0 in global memory
+    T2 *__restrict__ g = (T2 *)C.fields + (size_t)f0 * C.V + i0 + p + (size_t)V2 * (32 * r + j);
+    const size_t gz = (size_t)4 * V2;  // z -> z + 4
+    // the next field's elements are fetched while the current one is
+    // transformed (a barrier waits only for LDS operations)
+    T2 Rn[8];
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) Rn[n2] = g[n2 * gz];
+    for (int f = 0; f < nfg; ++f, g += C.V) {
+        T2 R[8];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) R[n2] = Rn[n2];
+        if (f + 1 < nfg) {
+#pragma unroll
+            for (int n2 = 0; n2 < 8; ++n2) Rn[n2] = g[C.V + n2 * gz];
+        }
+        pencil32_forward(R, tw);  // R[2 k2 + e] = (kz = 2 j + e + 8 k2, t = r)
+        if (f) __syncthreads();   // the previous field's t -> z reads are done
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) buf[p + 2 * (2 * j + e + 8 * k2) + kZtRegTp * r] = R[2 * k2 + e];
+        __syncthreads();
+        // t-pencil (p, kz = r): elements t = 4 n2 + j
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) R[n2] = buf[p + 2 * r + kZtRegTp * (4 * n2 + j)];
+        pencil32_forward(R, tw);  // R[2 k2 + e] = (kz = r, kt = 2 j + e + 8 k2)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            R[k].x *= kreg[k];
+            R[k].y *= kreg[k];
+        }
+        pencil32_backward(R, tw);  // R[n2] = (kz = r, t = 4 n2 + j)
+        __syncthreads();           // every z -> t read is done
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) buf[p + 2 * r + kZtRegTp * (4 * n2 + j)] = R[n2];
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) R[2 * k2 + e] = buf[p + 2 * (2 * j + e + 8 * k2) + kZtRegTp * r];
+        pencil32_backward(R, tw);  // R[n2] = (z = 4 n2 + j, t = r)
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) g[n2 * gz] = R[n2];
+    }
+}
+
+// ============================================================ (x, y) passes, 32 x 32 planes, radix stages in registers
+// The same scheme as k_fft_zt_reg for the (x, y) passes of configurations
+// with Lx = Ly = 32 (C.xy_reg): a tile is two consecutive xy-planes of one
+// field; x-pencils (rows) and y-pencils (columns) are held by four lanes
+// each, 8 elements per lane; LDS only moves the tile between the two.
+// Global memory stays in natural order, so the (z, t) pass and K(p) see the
+// layout the LDS-staged passes produce.
+constexpr int kXyRegYs = 33;  // LDS row stride of a plane: the 16 lanes of an access hit distinct banks
+
+// Forward (x, y) transform of the four fields. Work-item (w, q, j) holds
+// plane w / 2 of the tile and row (then column) r = 16 (w mod 2) + q: x-pencil
+// elements x = 4 n2 + j of row y = r, then y-pencil elements y = 4 n2 + j of
+// column kx = r. fold != 0: the work-groups past the tiles do the final
+// reduction of the previous update, as k_fft_xy's.
+template <typename T2>
+__global__ __launch_bounds__(256) void k_fft_xy_reg(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                    int respect_done, int ngroups, int fold)
+{
+    __shared__ T2 buf[2 * 32 * kXyRegYs];
+    const int ntiles = B->off_xy[B->n] * ngroups;
+    if ((int)blockIdx.x >= ntiles) {
+        const Cfg &R = cfgs[B->idx[blockIdx.x - ntiles]];
+        if (R.ctrl->done) return;
+        finalize_config(R, R.nblk_march, 1, fold == 2, (dd *)buf);
+        return;
+    }
+    const int rb = xcd_remap(blockIdx.x, ntiles);
+    const int tile = rb / ngroups, grp = rb - tile * ngroups;
+    const int nfg = kFields / ngroups, f0 = grp * nfg;
+    const int c = find_cfg(B->off_xy, B->n, tile);
+    const Cfg &C = cfgs[B->idx[c]];
+    if (respect_done && C.ctrl->done) return;
+    if (!C.xy_reg) return;  // the LDS-staged pass takes it
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane & 15, j = lane >> 4;
+    const int pl = w >> 1, r = 16 * (w & 1) + q;
+    T2 tw[8];
+    {
+        const T2 *__restrict__ tx = (const T2 *)C.tw + C.tw_off[0];
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) tw[k1] = tx[(j * k1) & 31];
+    }
+    T2 *__restrict__ plane = (T2 *)C.fields + (size_t)f0 * C.V + (size_t)((tile - B->off_xy[c]) * 2 + pl) * 1024;
+    T2 *__restrict__ sb = buf + pl * 32 * kXyRegYs;
+    T2 Rn[8];
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) Rn[n2] = plane[r * 32 + 4 * n2 + j];
+    for (int f = 0; f < nfg; ++f, plane += C.V) {
+        T2 R[8];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) R[n2] = Rn[n2];
+        if (f + 1 < nfg) {
+#pragma unroll
+            for (int n2 = 0; n2 < 8; ++n2) Rn[n2] = plane[C.V + r * 32 + 4 * n2 + j];
+        }
+        pencil32_forward(R, tw);  // R[2 k2 + e] = (y = r, kx = 2 j + e + 8 k2)
+        if (f) __syncthreads();   // the previous field's reads of the tile are done
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) sb[r * kXyRegYs + 2 * j + e + 8 * k2] = R[2 * k2 + e];
+        __syncthreads();
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) R[n2] = sb[(4 * n2 + j) * kXyRegYs + r];
+        pencil32_forward(R, tw);  // R[2 k2 + e] = (ky = 2 j + e + 8 k2, kx = r)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) plane[(2 * j + e + 8 * k2) * 32 + r] = R[2 * k2 + e];
+    }
+}
+
+// Inverse (x, y) transform of the four fields of a tile, written to fields2
+// (the filtered fields the fused pass forms g from; FP64 link storage).
+// Columns first (the layout pencil32_backward takes, read from natural
+// order), then rows.
+template <typename T2>
+__global__ __launch_bounds__(256) void k_fft_xy_inv_reg(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                        int respect_done, int ngroups)
+{
+    __shared__ T2 buf[2 * 32 * kXyRegYs];
+    const int ntiles = B->off_xy[B->n] * ngroups;
+    const int rb = xcd_remap(blockIdx.x, ntiles);
+    const int tile = rb / ngroups, grp = rb - tile * ngroups;
+    const int nfg = kFields / ngroups, f0 = grp * nfg;
+    const int c = find_cfg(B->off_xy, B->n, tile);
+    const Cfg &C = cfgs[B->idx[c]];
+    if (respect_done && C.ctrl->done) return;
+    if (!C.xy_reg) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane & 15, j = lane >> 4;
+    const int pl = w >> 1, r = 16 * (w & 1) + q;
+    T2 tw[8];
+    {
+        const T2 *__restrict__ tx = (const T2 *)C.tw + C.tw_off[0];
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) tw[k1] = tx[(j * k1) & 31];
+    }
+    const size_t po = (size_t)f0 * C.V + (size_t)((tile - B->off_xy[c]) * 2 + pl) * 1024;
+    const T2 *__restrict__ src = (const T2 *)C.fields + po;
+    T2 *__restrict__ dst = (T2 *)C.fields2 + po;
+    T2 *__restrict__ sb = buf + pl * 32 * kXyRegYs;
+    T2 Rn[8];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) Rn[2 * k2 + e] = ld_stream(src + (2 * j + e + 8 * k2) * 32 + r);
+    for (int f = 0; f < nfg; ++f, src += C.V, dst += C.V) {
+        T2 R[8];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) R[n2] = Rn[n2];
+        if (f + 1 < nfg) {
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) Rn[2 * k2 + e] = ld_stream(src + C.V + (2 * j + e + 8 * k2) * 32 + r);
+        }
+        pencil32_backward(R, tw);  // R[n2] = (y = 4 n2 + j, kx = r)
+        if (f) __syncthreads();
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) sb[(4 * n2 + j) * kXyRegYs + r] = R[n2];
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) R[2 * k2 + e] = sb[r * kXyRegYs + 2 * j + e + 8 * k2];
+        pencil32_backward(R, tw);  // R[n2] = (y = r, x = 4 n2 + j)
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) dst[r * 32 + 4 * n2 + j] = R[n2];
+    }
+}
+
 // ============================================================ S4: g = 1 + Delta~, projected
 // Rebuilds the filtered traceless anti-hermitian matrix from the four packed
 // fields (Delta~_10 = -conj(Delta~_01), Delta~_00 = i Re f3, Delta~_11 = i Im f3,
@@ -1226,18 +1583,16 @@ __device__ __forceinline__ M3 gauge_from_fields(T2 a, T2 b, T2 d, T2 e)
 }
 
 // g goes to g_override (caller, full matrices) if given, else to the
-// workspace: two_row 1 in two-row form (g12, fused path without exchange),
-// 2 in two-row single-precision storage (g12f), 0 full (g). two_row 3: the
-// gauge steps write the filtered fields Delta~ to fields2 instead, and the
-// fused exchange pass (FP64 link storage) forms each g it needs from them.
+// workspace: two_row 2 in two-row single-precision storage (g12f), 0 full
+// (g). two_row 3: the gauge steps write the filtered fields Delta~ to fields2
+// instead, and the fused pass (FP64 link storage) forms each g it needs from
+// them.
 __device__ __forceinline__ void store_gauge(const Cfg &C, double2 *g_override, int two_row, int s, const M3 &m)
 {
     if (g_override)
         m3_store(g_override, C.V, s, m);
     else if (two_row == 2)
         m3_store12s(C.g12f, C.V, s, m);
-    else if (two_row)
-        m3_store12(C.g12, C.V, s, m);
     else
         m3_store(C.g, C.V, s, m);
 }
@@ -1282,6 +1637,7 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     if (P2 != xy_is_p2(C)) return;  // the other instance takes it
+    if (C.xy_reg && two_row == 3 && !g_override) return;  // k_fft_xy_inv_reg takes it
     const int t = tile - B->off_xy[c];
     const int n = C.xyQ * C.V2;
     const size_t site0 = (size_t)t * n;
@@ -1382,123 +1738,12 @@ __global__ __launch_bounds__(kSiteBlock) void k_update(const Cfg *__restrict__ c
 // Links and g are held in two-row form (the 12-real parametrisation of the
 // paper's section 2.2; the third row is rebuilt on load). Old links are read
 // from one buffer and the new ones written to the other, so no block ever
-// reads a link another block has already replaced. The
-// backward neighbours U'_nu(x - nu), nu = x, y, z, are recomputed from the old
-// links; U'_t(x - t) is the U'_t(x) of the previous t-slice, kept in registers
-// (recomputed once at the first slice of a block). Also writes the packed
-// transform fields and the per-block sums for F (of the new links) and theta.
-// RU: the variant for iterations that also project the new links to SU(3)
-// (reunit_every > 0); each variant returns at once on the other iterations.
-template <typename T2, bool RU>
-__global__ __launch_bounds__(kSiteBlock) void k_update_delta(const Cfg *__restrict__ cfgs,
-                                                             const Batch *__restrict__ B)
-{
-    __shared__ dd red[2 * (kSiteBlock / 64)];
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int c = find_cfg(B->off_march, B->n, blk);
-    const Cfg &C = cfgs[B->idx[c]];
-    const Ctrl *ct = C.ctrl;
-    if (ct->done) return;
-    const int V = C.V, V3 = C.V3;
-    const double2 *__restrict__ Uo = C.U12[ct->cur];
-    double2 *__restrict__ Un = C.U12[ct->cur ^ 1];
-    const double2 *__restrict__ G = C.g12;
-    // decided before this iteration's fused launches, so that the two
-    // variants agree whatever runs in between
-    const bool reunit = C.reunit_every > 0 && ct->ru_now;
-    if (reunit != RU) return;
-    const int lb = blk - B->off_march[c];
-    const int b3 = lb % C.nb3, tc = lb / C.nb3;
-    int x, y, z;
-    const bool inside = march_xyz(C, b3, threadIdx.x, x, y, z);
-    dd fs = {0.0, 0.0}, ts = {0.0, 0.0};
-    if (inside) {
-        const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
-        const int s3 = x + Lx * (y + Ly * z);
-        int fwd3[3], back3[3];
-        fwd3[0] = (x == Lx - 1) ? s3 - (Lx - 1) : s3 + 1;
-        fwd3[1] = (y == Ly - 1) ? s3 - (Ly - 1) * Lx : s3 + Lx;
-        fwd3[2] = (z == Lz - 1) ? s3 - (Lz - 1) * C.V2 : s3 + C.V2;
-        back3[0] = (x == 0) ? s3 + (Lx - 1) : s3 - 1;
-        back3[1] = (y == 0) ? s3 + (Ly - 1) * Lx : s3 - Lx;
-        back3[2] = (z == 0) ? s3 + (Lz - 1) * C.V2 : s3 - C.V2;
-        const int t0 = tc * C.tch;
-        M3 gx = m3_load12(G, V, s3 + V3 * t0);
-        M3 utp;  // U'_t(x, t - 1)
-        {
-            const int sp = s3 + V3 * ((t0 == 0) ? Lt - 1 : t0 - 1);
-            utp = m3_mul_dag(m3_mul(m3_load12(G, V, sp), m3_load12(Uo + (size_t)18 * V, V, sp)), gx);
-            if (RU) m3_reunit(utp);
-        }
-        T2 *__restrict__ f = (T2 *)C.fields;
-        for (int t = t0; t < t0 + C.tch; ++t) {
-            const int s = s3 + V3 * t;
-            M3 D = utp;
-            double fsum = 0.0;
-#pragma unroll
-            for (int mu = 0; mu < 3; ++mu) {
-                const size_t off = (size_t)mu * 6 * V;
-                M3 w = m3_mul_dag(m3_mul(gx, m3_load12(Uo + off, V, s)), m3_load12(G, V, fwd3[mu] + V3 * t));
-                if (RU) m3_reunit(w);
-                m3_store12(Un + off, V, s, w);
-                fsum += w.e[0].x + w.e[4].x + w.e[8].x;
-#pragma unroll
-                for (int k = 0; k < 9; ++k) D.e[k] = csub(D.e[k], w.e[k]);
-                // keep the phases in order: bounds the loads in flight (registers)
-                __builtin_amdgcn_sched_barrier(0);
-                const int sb = back3[mu] + V3 * t;
-                M3 wb = m3_mul_dag(m3_mul(m3_load12(G, V, sb), m3_load12(Uo + off, V, sb)), gx);
-                if (RU) m3_reunit(wb);
-#pragma unroll
-                for (int k = 0; k < 9; ++k) D.e[k] = cadd(D.e[k], wb.e[k]);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            {
-                const int tn = (t + 1 == Lt) ? 0 : t + 1;
-                const M3 gn = m3_load12(G, V, s3 + V3 * tn);
-                const size_t off = (size_t)18 * V;
-                M3 w = m3_mul_dag(m3_mul(gx, m3_load12(Uo + off, V, s)), gn);
-                if (RU) m3_reunit(w);
-                m3_store12(Un + off, V, s, w);
-                fsum += w.e[0].x + w.e[4].x + w.e[8].x;
-#pragma unroll
-                for (int k = 0; k < 9; ++k) D.e[k] = csub(D.e[k], w.e[k]);
-                utp = w;
-                gx = gn;
-            }
-            double2 A[9];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) A[i * 3 + j] = csub(D.e[i * 3 + j], cconj(D.e[j * 3 + i]));
-            const double tr3 = (A[0].y + A[4].y + A[8].y) * (1.0 / 3.0);
-            A[0] = make_double2(0.0, A[0].y - tr3);
-            A[4] = make_double2(0.0, A[4].y - tr3);
-            A[8] = make_double2(0.0, A[8].y - tr3);
-            double tsum = 0.0;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) tsum += cnorm2(A[k]);
-            f[s].x = A[1].x;
-            f[s].y = A[1].y;
-            f[(size_t)V + s].x = A[2].x;
-            f[(size_t)V + s].y = A[2].y;
-            f[(size_t)2 * V + s].x = A[5].x;
-            f[(size_t)2 * V + s].y = A[5].y;
-            f[(size_t)3 * V + s].x = A[0].y;
-            f[(size_t)3 * V + s].y = A[4].y;
-            fs = dd_add(fs, dd{fsum, 0.0});
-            ts = dd_add(ts, dd{tsum, 0.0});
-        }
-    }
-    block_sum2(fs, ts, red);
-    if (threadIdx.x == 0) {
-        double *p = C.partials + (size_t)lb * 4;
-        p[0] = fs.hi;
-        p[1] = fs.lo;
-        p[2] = ts.hi;
-        p[3] = ts.lo;
-    }
-}
+// reads a link another block has already replaced. U'_t(x - t) is the U'_t(x)
+// of the previous t-slice, kept in registers (recomputed once at the first
+// slice of a block). Also writes the packed transform fields and the
+// per-block sums for F (of the new links) and theta. RU: the variant for
+// iterations that also project the new links to SU(3) (reunit_every > 0);
+// each variant returns at once on the other iterations.
 
 // Two-row link buffer b and two-row g of a configuration, in storage S2.
 template <typename S2>
@@ -1516,15 +1761,14 @@ __device__ __forceinline__ float2 *links12<float2>(const Cfg &C, int b) { return
 // U'_mu(x) - U'_mu(x)^dag for mu = x, y; a neighbour inside the block reads
 // them instead of loading g(x + mu) and recomputing U'_nu(x - nu) from the old
 // links. The z-neighbours, and x and y neighbours in other blocks (the edge
-// rows of a linear site set, the faces of a box), are loaded and recomputed as
-// in k_update_delta. (Exchanging z too, for boxes and for sets longer than an
+// rows of a linear site set, the faces of a box), are recomputed from the old
+// links and g. (Exchanging z too, for boxes and for sets longer than an
 // xy-plane, needs a third LDS array: 80 KB per block, and the single-precision
 // storage pass 3 % slower at 32^4 where no block holds a z-neighbour.) The new
 // links are formed by their first two rows (m3_mul_mul_dag_rows), exactly what
 // is stored, so a recomputed backward link equals the one its owner writes
 // (with contraction of multiply-adds fixed by the source, every inlined copy
-// rounds alike). Divergence and sums as in k_update_delta; D is accumulated
-// as its anti-hermitian part.
+// rounds alike). D is accumulated as its anti-hermitian part.
 //
 // Slot of the site (xn, yn, zn), flat index s3n, among the work-items of
 // marching block b3 (march_xyz's numbering), or -1 if another block owns it.
@@ -1571,11 +1815,29 @@ __device__ __forceinline__ M3 fused_gauge(const Cfg &C, int s)
         return gauge_at<T2, S2>((const T2 *)C.fields2, C.V, s);
 }
 
+// A new link of the fused pass: rows 0 and 1 in two-row storage S2, or, with
+// FULL (FP64 storage only), all three rows in the layout of the caller's array
+// (row 2 as the two-row form rebuilds it on load: w's own row 2, see m3_row2).
+template <typename S2, bool FULL>
+__device__ __forceinline__ void store_new_link(S2 *__restrict__ base, int V, int s, const M3 &w)
+{
+    m3_store12s_stream(base, V, s, w);
+    if constexpr (FULL) {
+#pragma unroll
+        for (int k = 6; k < 9; ++k) st_stream(base + (size_t)k * V + s, w.e[k]);
+    }
+}
+
 // S2: storage of links and g, double2 or float2 (single-precision storage).
-template <typename T2, bool RU, typename S2>
+// SRC / DST (FP64 storage): the first update of a call reads the old links
+// from the caller's array, the last update of a gf_step call writes the new
+// ones there, so that a call copies no links in or out; the updates in
+// between use the two-row buffers (these instances run inside the graphs).
+template <typename T2, bool RU, typename S2, bool SRC = false, bool DST = false>
 __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__restrict__ cfgs,
                                                                const Batch *__restrict__ B)
 {
+    static_assert(!(SRC || DST) || std::is_same<S2, double2>::value, "caller layout: FP64 storage only");
     __shared__ dd red[2 * (kSiteBlock / 64)];
     __shared__ double2 sg[6][kSiteBlock];    // g(x), rows 0 and 1, of the block's sites at this slice
     __shared__ double sa[2][9][kSiteBlock];  // U'_mu(x) - U'_mu(x)^dag (AH order), mu = x, y
@@ -1585,13 +1847,20 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
     const Ctrl *ct = C.ctrl;
     if (ct->done) return;  // the whole block leaves together
     const int V = C.V, V3 = C.V3;
-    const S2 *__restrict__ Uo = links12<S2>(C, ct->cur);
-    S2 *__restrict__ Un = links12<S2>(C, ct->cur ^ 1);
+    // SRC: the old links are the caller's full matrices (rows 0 and 1 read,
+    // row 2 rebuilt: the values a two-row copy holds); DST: the new links go
+    // to the caller's array as full matrices. Per direction, element k of a
+    // link sits at base + k V + s in both layouts.
+    constexpr size_t kOs = SRC ? 9 : 6, kNs = DST ? 9 : 6;
+    const S2 *__restrict__ Uo = SRC ? (const S2 *)C.U : links12<S2>(C, ct->cur);
+    S2 *__restrict__ Un = DST ? (S2 *)C.U : links12<S2>(C, ct->cur ^ 1);
     const bool reunit = C.reunit_every > 0 && ct->ru_now;
     if (reunit != RU) return;
     const int lb = blk - B->off_march[c];
     const int b3 = lb % C.nb3, tc = lb / C.nb3;
     const int tid = threadIdx.x;
+    // where the links are after this update (read by k_unpack_links only)
+    if (lb == 0 && tid == 0) C.ctrl->in_caller = DST ? 1 : 0;
     int x, y, z;
     const bool inside = march_xyz(C, b3, tid, x, y, z);
     const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
@@ -1617,7 +1886,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
     if (inside) {
         gx = fused_gauge<T2, S2>(C, s3 + V3 * t0);
         const int sp = s3 + V3 * ((t0 == 0) ? Lt - 1 : t0 - 1);
-        M3 w = m3_mul_mul_dag_rows(fused_gauge<T2, S2>(C, sp), m3_load12s(Uo + (size_t)18 * V, V, sp), gx);
+        M3 w = m3_mul_mul_dag_rows(fused_gauge<T2, S2>(C, sp), m3_load12s(Uo + kOs * 3 * V, V, sp), gx);
         if (RU) m3_reunit(w);
         utp = ah_of(w);
     }
@@ -1636,7 +1905,6 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
             D = utp;
 #pragma unroll
             for (int mu = 0; mu < 3; ++mu) {
-                const size_t off = (size_t)mu * 6 * V;
                 M3 gf;
                 if (mu < 2 && sf[mu] >= 0) {
 #pragma unroll
@@ -1648,10 +1916,11 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                 // U_x(x) and U_y(x) are read again only at the block's edge
                 // rows; U_z(x) is the backward neighbour of the next
                 // work-group in z, which reads it in the same slice
+                const size_t off = (size_t)mu * kOs * V;
                 const M3 u = (mu < 2) ? m3_load12s_stream(Uo + off, V, s) : m3_load12s(Uo + off, V, s);
                 M3 w = m3_mul_mul_dag_rows(gx, u, gf);
                 if (RU) m3_reunit(w);
-                m3_store12s_stream(Un + off, V, s, w);
+                store_new_link<S2, DST>(Un + (size_t)mu * kNs * V, V, s, w);
                 fsum += w.e[0].x + w.e[4].x + w.e[8].x;
                 const AH a = ah_of(w);
                 ah_acc(D, a, -1.0);
@@ -1670,10 +1939,9 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
             {
                 const int tn = (t + 1 == Lt) ? 0 : t + 1;
                 gn = fused_gauge<T2, S2>(C, s3 + V3 * tn);
-                const size_t off = (size_t)18 * V;
-                M3 w = m3_mul_mul_dag_rows(gx, m3_load12s_stream(Uo + off, V, s), gn);
+                M3 w = m3_mul_mul_dag_rows(gx, m3_load12s_stream(Uo + kOs * 3 * V, V, s), gn);
                 if (RU) m3_reunit(w);
-                m3_store12s_stream(Un + off, V, s, w);
+                store_new_link<S2, DST>(Un + kNs * 3 * V, V, s, w);
                 fsum += w.e[0].x + w.e[4].x + w.e[8].x;
                 utp = ah_of(w);
                 ah_acc(D, utp, -1.0);
@@ -1694,7 +1962,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                     a.d2 = sa[nu][8][o];
                 } else {
                     const int sbk = back3[nu] + V3 * t;
-                    M3 wb = m3_mul_mul_dag_rows(fused_gauge<T2, S2>(C, sbk), m3_load12s(Uo + (size_t)nu * 6 * V, V, sbk), gx);
+                    M3 wb = m3_mul_mul_dag_rows(fused_gauge<T2, S2>(C, sbk), m3_load12s(Uo + (size_t)nu * kOs * V, V, sbk), gx);
                     if (RU) m3_reunit(wb);
                     a = ah_of(wb);
                 }
@@ -1779,6 +2047,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_unpack_links(const Cfg *__restri
     const Cfg &C = cfgs[B->idx[c]];
     const int s = (blk - B->off_site[c]) * kSiteBlock + threadIdx.x;
     if (s >= C.V) return;
+    if (C.ctrl->in_caller) return;  // the last update wrote them there
     const S2 *__restrict__ src = links12<S2>(C, C.ctrl->cur);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
@@ -1797,10 +2066,16 @@ __global__ void k_mark_reunit(const Cfg *__restrict__ cfgs, const Batch *__restr
     ct->ru_now = C.reunit_every > 0 && ((ct->iter + 1) % (long long)C.reunit_every) == 0;
 }
 
-__global__ void k_set_cur(const Cfg *__restrict__ cfgs, int ncfg, int v)
+// Start of an iterating call: links in buffer 0 (binary32 storage, copied by
+// k_pack_links) or in the caller's array (FP64 storage, read there by the
+// first update).
+__global__ void k_begin_call(const Cfg *__restrict__ cfgs, int ncfg, int in_caller)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < ncfg) cfgs[c].ctrl->cur = v;
+    if (c >= ncfg) return;
+    Ctrl *ct = cfgs[c].ctrl;
+    ct->cur = 0;
+    ct->in_caller = in_caller;
 }
 
 // ============================================================ differentiable functional
@@ -2032,6 +2307,13 @@ hipError_t launch_arm(const Launch &L, int ncfg, double eps, long long add_iters
     return hipGetLastError();
 }
 
+hipError_t launch_arm_one(const Launch &L, int k, double eps, long long add_iters, int reset_iter)
+{
+    if (k < 0 || k >= L.ncfg) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, L.stream, L.cfgs + k, 1, eps, add_iters, reset_iter);
+    return hipGetLastError();
+}
+
 hipError_t launch_delta(const Launch &L, int respect_done, double2 *full_delta)
 {
     if (L.fp32)
@@ -2075,9 +2357,10 @@ hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *
     return hipGetLastError();
 }
 
-// Where the gauge passes put g: 0 full (g), 1 two-row FP64 (g12), 2 two-row
-// single-precision storage (g12f).
-static int gauge_store_mode(const Launch &L) { return L.fused ? (L.link_f32 ? 2 : (L.xchg ? 3 : 1)) : 0; }
+// Where the gauge passes put g: 0 full (g), 2 two-row single-precision
+// storage (g12f), 3 the filtered fields (fields2) from which the fused pass
+// forms g.
+static int gauge_store_mode(const Launch &L) { return L.fused ? (L.link_f32 ? 2 : 3) : 0; }
 
 // (tile capacity, work-group size) instances of the 2D passes: 4 or 8
 // elements per work-item.
@@ -2102,6 +2385,14 @@ static hipError_t run_xy(const Launch &L, int nf, int sign, void *fo, int rd, in
     const int fpb = std::max(1, std::min(L.xy_fpb, nf));
     const size_t sh = lds2d<T2>(L.xy_cap, L.xy_tw2, L.xy_tw_total);
     int launched = 0;
+    if (!fo && L.xy_reg_any) {  // the iteration's forward pass
+        if (sign != -1 || nf != kFields) return hipErrorInvalidValue;
+        const int ng = L.xy_reg_groups;
+        hipLaunchKernelGGL(k_fft_xy_reg<T2>, dim3(L.total_xy_tiles * ng + (fold ? L.ncfg : 0)), dim3(256), 0,
+                           L.stream, L.cfgs, L.batch, rd, ng, fold);
+        ++launched;
+        if (!L.xy_lds_any) return hipGetLastError();
+    }
     // a batch mixing power-of-two and general extents launches both
     // instances; only the first carries the folded reduction
 #define X(C_, T_, P2_)                                                                                            \
@@ -2124,6 +2415,13 @@ static hipError_t run_zt(const Launch &L, int nf, int mode, int sign, void *fo, 
     const dim3 grid(L.total_zt_tiles, (nf + fpb - 1) / fpb);
     const size_t sh = lds2d<T2>(L.zt_cap, L.zt_tw2, L.zt_tw_total);
     int launched = 0;
+    if (mode == 1 && L.zt_reg_any) {
+        const int ng = L.zt_reg_groups;
+        hipLaunchKernelGGL(k_fft_zt_reg<T2>, dim3(L.total_zt_tiles * ng), dim3(256), 0, L.stream, L.cfgs, L.batch, rd,
+                           ng);
+        ++launched;
+        if (!L.zt_lds_any) return hipGetLastError();
+    }
 #define X(C_, T_, P2_)                                                                                            \
     if (L.zt_cap == C_ && L.zt_th == T_ && (P2_ ? L.zt_p2 : L.zt_gen)) {                                          \
         hipLaunchKernelGGL((k_fft_zt<T2, C_, T_, P2_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, mode, sign,   \
@@ -2140,6 +2438,13 @@ static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
 {
     const size_t sh = lds2d<T2>(L.xy_cap, L.xy_tw2, L.xy_tw_total);
     int launched = 0;
+    if (!go && gauge_store_mode(L) == 3 && L.xy_reg_any) {
+        const int ng = L.xy_reg_groups;
+        hipLaunchKernelGGL(k_fft_xy_inv_reg<T2>, dim3(L.total_xy_tiles * ng), dim3(256), 0, L.stream, L.cfgs, L.batch,
+                           rd, ng);
+        ++launched;
+        if (!L.xy_lds_any) return hipGetLastError();
+    }
 #define X(C_, T_, P2_)                                                                                            \
     if (L.xy_cap == C_ && L.xy_th == T_ && (P2_ ? L.xy_p2 : L.xy_gen)) {                                          \
         hipLaunchKernelGGL((k_fft_xy_inv_gauge<T2, C_, T_, P2_>), dim3(L.total_xy_tiles), dim3(T_), sh, L.stream,    \
@@ -2151,7 +2456,9 @@ static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
     return launched ? hipGetLastError() : hipErrorInvalidValue;
 }
 
-bool can_fold_reduce(const Launch &L) { return L.xy_th >= kReduceLanes; }
+// The register xy pass (256 work-items) carries the fold whenever it runs
+// (it is launched first); the LDS-staged one needs kReduceLanes work-items.
+bool can_fold_reduce(const Launch &L) { return L.xy_reg_any || L.xy_th >= kReduceLanes; }
 
 hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done,
                          int fold_reduce)
@@ -2217,50 +2524,49 @@ hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override)
     return hipGetLastError();
 }
 
-hipError_t launch_update_delta(const Launch &L)
+hipError_t launch_update_delta(const Launch &L, int link_io)
 {
     const dim3 grid(L.total_march_blocks), blk(kSiteBlock);
     if (L.any_reunit) hipLaunchKernelGGL(k_mark_reunit, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.batch);
-    if (L.xchg || L.link_f32) {
-#define GF_UPD(T2_, S2_)                                                                                      \
-    do {                                                                                                       \
-        hipLaunchKernelGGL((k_update_delta_x<T2_, false, S2_>), grid, blk, 0, L.stream, L.cfgs, L.batch);     \
-        if (L.any_reunit)                                                                                      \
-            hipLaunchKernelGGL((k_update_delta_x<T2_, true, S2_>), grid, blk, 0, L.stream, L.cfgs, L.batch);  \
+#define GF_UPD(T2_, S2_, SRC_, DST_)                                                                                  \
+    do {                                                                                                              \
+        hipLaunchKernelGGL((k_update_delta_x<T2_, false, S2_, SRC_, DST_>), grid, blk, 0, L.stream, L.cfgs, L.batch); \
+        if (L.any_reunit)                                                                                             \
+            hipLaunchKernelGGL((k_update_delta_x<T2_, true, S2_, SRC_, DST_>), grid, blk, 0, L.stream, L.cfgs,        \
+                               L.batch);                                                                              \
     } while (0)
-        if (L.fp32) {
-            if (L.link_f32)
-                GF_UPD(float2, float2);
-            else
-                GF_UPD(float2, double2);
-        } else {
-            if (L.link_f32)
-                GF_UPD(double2, float2);
-            else
-                GF_UPD(double2, double2);
-        }
-#undef GF_UPD
-        return hipGetLastError();
-    }
+#define GF_UPD_IO(T2_)                                    \
+    do {                                                  \
+        if (link_io == kLinksFromCaller)                  \
+            GF_UPD(T2_, double2, true, false);            \
+        else if (link_io == kLinksToCaller)               \
+            GF_UPD(T2_, double2, false, true);            \
+        else                                              \
+            GF_UPD(T2_, double2, false, false);           \
+    } while (0)
+    if (L.link_f32 && link_io != kLinksBuffers) return hipErrorInvalidValue;
     if (L.fp32) {
-        hipLaunchKernelGGL((k_update_delta<float2, false>), grid, blk, 0, L.stream, L.cfgs, L.batch);
-        if (L.any_reunit) hipLaunchKernelGGL((k_update_delta<float2, true>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+        if (L.link_f32)
+            GF_UPD(float2, float2, false, false);
+        else
+            GF_UPD_IO(float2);
     } else {
-        hipLaunchKernelGGL((k_update_delta<double2, false>), grid, blk, 0, L.stream, L.cfgs, L.batch);
-        if (L.any_reunit)
-            hipLaunchKernelGGL((k_update_delta<double2, true>), grid, blk, 0, L.stream, L.cfgs, L.batch);
+        if (L.link_f32)
+            GF_UPD(double2, float2, false, false);
+        else
+            GF_UPD_IO(double2);
     }
+#undef GF_UPD_IO
+#undef GF_UPD
     return hipGetLastError();
 }
 
 hipError_t launch_pack_links(const Launch &L)
 {
-    hipLaunchKernelGGL(k_set_cur, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.ncfg, 0);
+    hipLaunchKernelGGL(k_begin_call, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.ncfg,
+                       L.link_f32 ? 0 : 1);
     if (L.link_f32)
         hipLaunchKernelGGL(k_pack_links<float2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
-                           L.batch);
-    else
-        hipLaunchKernelGGL(k_pack_links<double2>, dim3(L.total_site_blocks), dim3(kSiteBlock), 0, L.stream, L.cfgs,
                            L.batch);
     return hipGetLastError();
 }

@@ -193,7 +193,7 @@ FftAxis plan_axis(const int dims[4], int mu)
 }
 
 struct Layout {
-    size_t fields, fields2, g, partials, sin2, tw, links12a, links12b, g12, kmom, links12fa, links12fb, g12f, total;
+    size_t fields, fields2, g, partials, sin2, tw, links12a, links12b, kmom, links12fa, links12fb, g12f, total;
 };
 
 Layout layout_for(const gf_params &p, size_t start)
@@ -219,13 +219,11 @@ Layout layout_for(const gf_params &p, size_t start)
     o = align_up(o + sumL * sizeof(double));
     l.tw = o;
     o = align_up(o + sumL * csz);
-    // two-row (12-real) links, two buffers, and two-row g of the fused pass
+    // two-row (12-real) links, two buffers
     l.links12a = o;
     o = align_up(o + 24 * V * 16);
     l.links12b = o;
     o = align_up(o + 24 * V * 16);
-    l.g12 = o;
-    o = align_up(o + 6 * V * 16);
     // K(p) table in the transform's precision
     l.kmom = o;
     o = align_up(o + V * (csz / 2));
@@ -259,14 +257,28 @@ struct KTime {
 
 // Tile choices of the 2D passes: target elements per tile and elements per
 // work-item (the work-group size is the tile capacity divided by it).
+// zt_reg: the scaled (z, t) pass of configurations with Lz = Lt = 32 runs
+// in k_fft_zt_reg (radix stages in registers) instead of the LDS-staged pass,
+// with zt_reg work-groups per tile (1, 2 or 4, the four fields split among
+// them); 0: the LDS-staged pass.
+// xy_reg: the same for the iteration's (x, y) passes of configurations with
+// Lx = Ly = 32 (k_fft_xy_reg, k_fft_xy_inv_reg).
 struct Tiles {
     int xy_target = 1024, xy_ept = 4;
     int zt_target = 4096, zt_ept = 8;
+    int zt_reg = 2;
+    int xy_reg = 1;
     bool operator==(const Tiles &o) const
     {
-        return xy_target == o.xy_target && xy_ept == o.xy_ept && zt_target == o.zt_target && zt_ept == o.zt_ept;
+        return xy_target == o.xy_target && xy_ept == o.xy_ept && zt_target == o.zt_target && zt_ept == o.zt_ept &&
+               zt_reg == o.zt_reg && xy_reg == o.xy_reg;
     }
 };
+
+// Whether a configuration's scaled (z, t) pass can run in k_fft_zt_reg, and
+// its (x, y) passes in k_fft_xy_reg / k_fft_xy_inv_reg (tiles of two planes).
+bool zt_reg_fits(const Cfg &C) { return C.dims[2] == 32 && C.dims[3] == 32 && C.V2 % 2 == 0; }
+bool xy_reg_fits(const Cfg &C) { return C.dims[0] == 32 && C.dims[1] == 32 && (C.dims[2] * C.dims[3]) % 2 == 0; }
 
 struct gf_ctx_s {
     int ncfg = 0;
@@ -301,6 +313,12 @@ struct gf_ctx_s {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     int sched = kSched1D;
     Tiles tiles;
+    // a context that allocates nothing (no stream, event, graph or pinned
+    // host memory); iterations are launched directly on `stream`
+    bool noalloc = false;
+    // gf_init_functional: only the differentiable functional's buffers (g,
+    // block partials); no transform plan, no measurement
+    bool functional_only = false;
 };
 
 namespace {
@@ -420,14 +438,17 @@ bool fold_ok(gf_ctx c)
 // done. fold_prev: the previous iteration's final reduction is done by this
 // iteration's first pass; reduce_after: this iteration's own is launched
 // (else the next iteration folds it).
-hipError_t enqueue_iteration(gf_ctx c, hipStream_t s, int fold_prev = 0, int reduce_after = 1)
+// link_io: where the fused pass takes the old links from and puts the new
+// ones (kLinksBuffers inside graphs; see launch_update_delta).
+hipError_t enqueue_iteration(gf_ctx c, hipStream_t s, int fold_prev = 0, int reduce_after = 1,
+                             int link_io = kLinksBuffers)
 {
     Launch L = c->Lact;
     L.stream = s;
     hipError_t e = enqueue_gauge_steps(c, s, 1, nullptr, fold_prev);
     if (e != hipSuccess) return e;
     if (L.fused) {
-        GF_TRY(K_UPDATE_DELTA, launch_update_delta(L));
+        GF_TRY(K_UPDATE_DELTA, launch_update_delta(L, link_io));
     } else {
         GF_TRY(K_UPDATE, launch_update(L, 1, nullptr));
         GF_TRY(K_DELTA, launch_delta(L, 1, nullptr));
@@ -492,6 +513,7 @@ gf_status read_ctrl(gf_ctx c)
 }
 
 gf_status run_chunks(gf_ctx c);
+gf_status run_exact(gf_ctx c, long long n, long long pending);
 gf_status reset_active(gf_ctx c);
 gf_status compact_active(gf_ctx c);
 void drop_graph(gf_ctx c);
@@ -509,25 +531,53 @@ void set_link_storage(gf_ctx c, int f32)
     drop_graph(c);
 }
 
-gf_status run_until_done(gf_ctx c)
+// Iterations of a call. FP64 link storage: the first update reads the
+// caller's links (no copy in), and with n_exact > 1 (gf_step: exactly that
+// many updates) the last one writes them back (no copy out); the updates in
+// between run as graph chunks. Binary32 storage copies the links into the
+// two-row buffer first. At the end, configurations whose links are in the
+// two-row buffer (the call stopped on its rule, or made one update) are
+// written back to the caller's array, third rows rebuilt.
+gf_status run_until_done(gf_ctx c, long long n_exact = 0)
 {
     gf_status st = reset_active(c);
     if (st != GF_OK) return st;
     if (c->L.fused) HIPCHK(c, launch_pack_links(c->L));
-    st = run_chunks(c);
-    if (st != GF_OK) return st;
+    const bool io = c->L.fused && !c->L.link_f32;
+    long long first = 0;
+    if (io) {
+        HIPCHK(c, enqueue_iteration(c, c->stream, 0, 1, kLinksFromCaller));
+        first = 1;
+    }
+    if (n_exact > 0) {
+        const bool last = io && n_exact >= 2;
+        st = run_exact(c, n_exact - first - (last ? 1 : 0), first);
+        if (st != GF_OK) return st;
+        if (last) HIPCHK(c, enqueue_iteration(c, c->stream, 0, 1, kLinksToCaller));
+        if ((st = read_ctrl(c)) != GF_OK) return st;
+        if (c->timing && (st = collect_timing(c)) != GF_OK) return st;
+    } else {
+        st = run_chunks(c);
+        if (st != GF_OK) return st;
+    }
     if (c->L.fused) {
-        HIPCHK(c, launch_unpack_links(c->L));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+        bool all_there = true;
+        for (int k = 0; k < c->ncfg; ++k) all_there = all_there && c->h_ctrl[k].in_caller;
+        if (!all_there) {
+            HIPCHK(c, launch_unpack_links(c->L));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
     }
     return GF_OK;
 }
 
 // gf_fix_until and its batch form: with link_prec 1, iterations in
 // single-precision storage until theta <= refine_theta, then (if theta_eps
-// is below it and every configuration got there) a measurement of the stored
-// links and iterations in FP64 storage down to theta_eps. max_iter bounds
-// the updates of both phases together.
+// is below it) a measurement of the stored links and iterations in FP64
+// storage down to theta_eps for every configuration that got there.
+// Configurations that stopped in the first phase at the cap or on a
+// non-finite value keep that outcome. max_iter bounds the updates of both
+// phases together, per configuration.
 gf_status fix_phases(gf_ctx c, double theta_eps, int64_t max_iter)
 {
     std::vector<long long> before(c->ncfg);
@@ -537,22 +587,71 @@ gf_status fix_phases(gf_ctx c, double theta_eps, int64_t max_iter)
     HIPCHK(c, launch_arm(c->L, c->ncfg, two ? c->refine_theta : theta_eps, max_iter, 0));
     gf_status st = run_until_done(c);
     if (st != GF_OK || !two) return st;
-    bool all = true;
-    long long used = 0;
+    std::vector<int> go(c->ncfg, 0);
+    bool any = false;
     for (int k = 0; k < c->ncfg; ++k) {
-        all = all && c->h_ctrl[k].done == kConverged;
-        used = std::max(used, c->h_ctrl[k].iter - before[k]);
+        go[k] = c->h_ctrl[k].done == kConverged;
+        any = any || go[k];
     }
-    if (!all) return GF_OK;
+    if (!any) return GF_OK;
     set_link_storage(c, 0);
-    // the caller's links now hold the stored links: measure them (not an update)
-    HIPCHK(c, enqueue_measure(c));
-    HIPCHK(c, launch_arm(c->L, c->ncfg, theta_eps, max_iter - used, 0));
+    // the caller's links now hold the stored links: measure those of the
+    // configurations that go on (not an update; the others keep their
+    // stopping state and their last values), then apply the stopping rule
+    // to the new measurement
+    for (int k = 0; k < c->ncfg; ++k)
+        if (go[k]) HIPCHK(c, launch_arm_one(c->L, k, theta_eps, max_iter - (c->h_ctrl[k].iter - before[k]), 0));
+    HIPCHK(c, launch_delta(c->L, 1, nullptr));
+    HIPCHK(c, launch_reduce(c->L, c->ncfg, 0, 1));
+    for (int k = 0; k < c->ncfg; ++k)
+        if (go[k]) HIPCHK(c, launch_arm_one(c->L, k, theta_eps, max_iter - (c->h_ctrl[k].iter - before[k]), 0));
     st = read_ctrl(c);
     if (st != GF_OK) return st;
     return run_until_done(c);
 }
 
+// n updates after `pending` ones already launched and not yet read back:
+// whole chunks as graphs, the rest launched directly (iterations past the
+// last would only launch passes that return at once); the control block is
+// read back before the history ring could overflow. The caller reads it at
+// the end.
+gf_status run_exact(gf_ctx c, long long n, long long pending)
+{
+    if (n <= 0) return GF_OK;
+    gf_status st;
+    if (c->timing) {
+        for (long long i = 0; i < n; ++i) {
+            HIPCHK(c, enqueue_iteration(c, c->stream));
+            if ((st = read_ctrl(c)) != GF_OK) return st;
+            if ((st = collect_timing(c)) != GF_OK) return st;
+        }
+        return GF_OK;
+    }
+    if (n >= c->chunk && (st = build_graph(c)) != GF_OK) return st;
+    const bool fold = fold_ok(c);
+    long long left = n, since = pending;
+    while (left > 0) {
+        if (since + c->chunk + 2 > kHist) {
+            if ((st = read_ctrl(c)) != GF_OK) return st;
+            since = 0;
+        }
+        if (left >= c->chunk) {
+            HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+            left -= c->chunk;
+            since += c->chunk;
+        } else {
+            const int r = (int)left;
+            for (int i = 0; i < r; ++i)
+                HIPCHK(c, enqueue_iteration(c, c->stream, fold && i > 0, !(fold && i + 1 < r)));
+            since += left;
+            left = 0;
+        }
+    }
+    return GF_OK;
+}
+
+// Iterations until every configuration is done (the stopping rule, the cap
+// or a non-finite value), a chunk at a time.
 gf_status run_chunks(gf_ctx c)
 {
     if (c->timing) {
@@ -568,6 +667,20 @@ gf_status run_chunks(gf_ctx c)
             for (int k = 0; k < c->ncfg; ++k) all = all && c->h_ctrl[k].done != kRunning;
             if (all) return GF_OK;
             if (c->batch && (st = compact_active(c)) != GF_OK) return st;
+        }
+    }
+    if (c->noalloc) {
+        // the iterations of a chunk launched one after the other on the
+        // caller's stream (the same kernels and reduction order as a graph)
+        const bool fold = fold_ok(c);
+        for (;;) {
+            for (int i = 0; i < c->chunk; ++i)
+                HIPCHK(c, enqueue_iteration(c, c->stream, fold && i > 0, !(fold && i + 1 < c->chunk)));
+            gf_status st = read_ctrl(c);
+            if (st != GF_OK) return st;
+            bool all = true;
+            for (int k = 0; k < c->ncfg; ++k) all = all && c->h_ctrl[k].done != kRunning;
+            if (all) return GF_OK;
         }
     }
     gf_status st = build_graph(c);
@@ -659,13 +772,16 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
     for (int k = 0; k < c->ncfg; ++k) {
         Cfg &C = c->cfg[k];
         C.xyQ = xy_feasible(C.dims) ? plan_xyQ(C.dims, tl.xy_target) : 1;
+        C.xy_reg = ((sched == kSchedXYZT || sched == kSchedXY1D) && tl.xy_reg && xy_reg_fits(C)) ? 1 : 0;
+        if (C.xy_reg) C.xyQ = 2;  // the register passes' tile: 2 planes
         C.nxy = xy_feasible(C.dims) ? (C.dims[2] * C.dims[3]) / C.xyQ : 0;
         C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims, tl.zt_target) : 1;
+        C.zt_reg = (sched == kSchedXYZT && tl.zt_reg && zt_reg_fits(C)) ? 1 : 0;
+        if (C.zt_reg) C.ztP = 2;  // the register pass's tile: 2 xy-sites
         C.nzt = zt_feasible(C.dims) ? C.V2 / C.ztP : 0;
         // bank-spreading pads, kept inside the 1/8 slack of the LDS tile
-        const char *np = getenv("GF_NO_LDS_PAD");
         const int xycap = C.xyQ * C.V2 <= 1024 ? 1024 : (C.xyQ * C.V2 <= 2048 ? 2048 : 4096);
-        C.xyPad = (!np && C.dims[1] * C.xyQ <= xycap / 8) ? 1 : 0;
+        C.xyPad = (C.dims[1] * C.xyQ <= xycap / 8) ? 1 : 0;
         // zt tile: t-planes Tp = P Lz + ztPad elements apart with Tp = P (mod
         // 32), so that the lanes of one z-pencil access (p fastest, then t)
         // fall on distinct LDS banks: 16 consecutive lanes for 16-byte
@@ -675,7 +791,7 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
         const int r = C.ztP - C.ztP * C.dims[2];
         int zp = ((r % 32) + 32) % 32;
         if (zp * C.dims[3] > ztcap / 8) zp = ((r % 16) + 16) % 16;
-        C.ztPad = (!np && zp * C.dims[3] <= ztcap / 8) ? zp : 0;
+        C.ztPad = (zp * C.dims[3] <= ztcap / 8) ? zp : 0;
     }
     std::vector<int> all(c->ncfg);
     for (int k = 0; k < c->ncfg; ++k) all[k] = k;
@@ -695,19 +811,24 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
         mz = std::max(mz, C.dims[2]);
         mt = std::max(mt, C.dims[3]);
     }
+    c->L.zt_reg_any = c->L.zt_lds_any = 0;
+    c->L.zt_reg_groups = tl.zt_reg > 0 ? tl.zt_reg : 1;
+    c->L.xy_reg_any = c->L.xy_lds_any = 0;
+    c->L.xy_reg_groups = tl.xy_reg > 0 ? tl.xy_reg : 1;
+    for (int k = 0; k < c->ncfg; ++k) {
+        const Cfg &C = c->cfg[k];
+        if (C.nzt) (C.zt_reg ? c->L.zt_reg_any : c->L.zt_lds_any) = 1;
+        if (C.nxy) (C.xy_reg ? c->L.xy_reg_any : c->L.xy_lds_any) = 1;
+    }
     auto cap_for = [](int n) { return n <= 1024 ? 1024 : (n <= 2048 ? 2048 : 4096); };
     c->L.xy_cap = cap_for(xy_max);
     c->L.zt_cap = cap_for(zt_max);
     c->L.xy_th = c->L.xy_cap / tl.xy_ept;
     c->L.zt_th = c->L.zt_cap / tl.zt_ept;
-    // fields per work-group of the 2D passes (GF_XY_FPB, GF_ZT_FPB: 1 to 4)
-    auto fpb = [](const char *name) {
-        const char *e = getenv(name);
-        const int v = e ? atoi(e) : kFields;
-        return (v >= 1 && v <= kFields) ? v : kFields;
-    };
-    c->L.xy_fpb = fpb("GF_XY_FPB");
-    c->L.zt_fpb = fpb("GF_ZT_FPB");
+    // a work-group of the 2D passes transforms the four fields of its tile
+    // one after the other (the next one prefetched)
+    c->L.xy_fpb = kFields;
+    c->L.zt_fpb = kFields;
     c->L.xy_p2 = xy_p2;
     c->L.zt_p2 = zt_p2;
     c->L.xy_gen = xy_gen;
@@ -801,8 +922,8 @@ std::vector<TuneEntry> &tune_cache()
             if (f) {
                 char key[4096];
                 TuneEntry e;
-                while (fscanf(f, "%4095s %d %d %d %d %d", key, &e.sched, &e.tiles.xy_target, &e.tiles.xy_ept,
-                              &e.tiles.zt_target, &e.tiles.zt_ept) == 6) {
+                while (fscanf(f, "%4095s %d %d %d %d %d %d %d", key, &e.sched, &e.tiles.xy_target, &e.tiles.xy_ept,
+                              &e.tiles.zt_target, &e.tiles.zt_ept, &e.tiles.zt_reg, &e.tiles.xy_reg) == 8) {
                     e.key = key;
                     cache.push_back(e);
                 }
@@ -817,7 +938,8 @@ bool valid_tiles(const Tiles &t)
 {
     auto ok_target = [](int v) { return v == 1024 || v == 2048 || v == 4096; };
     return ok_target(t.xy_target) && ok_target(t.zt_target) && (t.xy_ept == 4 || t.xy_ept == 8) &&
-           (t.zt_ept == 4 || t.zt_ept == 8);
+           (t.zt_ept == 4 || t.zt_ept == 8) && (t.zt_reg == 0 || t.zt_reg == 1 || t.zt_reg == 2 || t.zt_reg == 4) &&
+           (t.xy_reg == 0 || t.xy_reg == 1 || t.xy_reg == 2 || t.xy_reg == 4);
 }
 
 // Tile choices of a fixed schedule: defaults, overridden by GF_XY_TARGET,
@@ -833,6 +955,8 @@ Tiles env_tiles()
     rd("GF_XY_EPT", t.xy_ept);
     rd("GF_ZT_TARGET", t.zt_target);
     rd("GF_ZT_EPT", t.zt_ept);
+    rd("GF_ZT_REG", t.zt_reg);
+    rd("GF_XY_REG", t.xy_reg);
     return valid_tiles(t) ? t : Tiles();
 }
 
@@ -840,6 +964,10 @@ Tiles env_tiles()
 // feasible candidates timed on this context's fields, cached per shape.
 gf_status choose_schedule(gf_ctx c, int requested)
 {
+    if (requested == kSchedAuto && c->noalloc) {
+        // no timing without events: the 2D passes wherever they fit
+        requested = sched_feasible(c, kSchedXYZT) ? kSchedXYZT : sched_feasible(c, kSchedXY1D) ? kSchedXY1D : kSched1D;
+    }
     if (requested != kSchedAuto) return apply_schedule(c, requested, env_tiles());
     const std::string key = tune_key(c);
     for (auto &e : tune_cache())
@@ -850,20 +978,56 @@ gf_status choose_schedule(gf_ctx c, int requested)
         Tiles tiles;
     };
     std::vector<Cand> cands = {{kSched1D, Tiles()}};
+    bool any_zreg = false, any_xreg = false;
+    for (int k = 0; k < c->ncfg; ++k) {
+        any_zreg = any_zreg || zt_reg_fits(c->cfg[k]);
+        any_xreg = any_xreg || xy_reg_fits(c->cfg[k]);
+    }
+    // (x, y) choices: LDS tiles (target, elements per work-item), or the
+    // register passes with 1 or 2 work-groups per tile; (z, t) choices: LDS
+    // tiles, or the register pass with 1, 2 or 4 (the LDS tile then serves
+    // only the plain transform calls)
+    std::vector<Tiles> xs, zs;
     for (int xt : {1024, 4096})
         for (int xe : {4, 8}) {
             Tiles t;
             t.xy_target = xt;
             t.xy_ept = xe;
-            if (sched_feasible(c, kSchedXY1D)) cands.push_back({kSchedXY1D, t});
-            if (!sched_feasible(c, kSchedXYZT)) continue;
-            for (int zt : {2048, 4096})
-                for (int ze : {4, 8}) {
-                    t.zt_target = zt;
-                    t.zt_ept = ze;
-                    cands.push_back({kSchedXYZT, t});
-                }
+            t.xy_reg = 0;
+            xs.push_back(t);
         }
+    if (any_xreg)
+        for (int g : {1, 2}) {
+            Tiles t;
+            t.xy_reg = g;
+            xs.push_back(t);
+        }
+    for (int zt : {2048, 4096})
+        for (int ze : {4, 8}) {
+            Tiles t;
+            t.zt_target = zt;
+            t.zt_ept = ze;
+            t.zt_reg = 0;
+            zs.push_back(t);
+        }
+    if (any_zreg)
+        for (int g : {1, 2, 4}) {
+            Tiles t;
+            t.zt_reg = g;
+            zs.push_back(t);
+        }
+    for (const Tiles &x : xs) {
+        Tiles t = x;
+        t.zt_reg = 0;
+        if (sched_feasible(c, kSchedXY1D)) cands.push_back({kSchedXY1D, t});
+        if (!sched_feasible(c, kSchedXYZT)) continue;
+        for (const Tiles &z : zs) {
+            t.zt_target = z.zt_target;
+            t.zt_ept = z.zt_ept;
+            t.zt_reg = z.zt_reg;
+            cands.push_back({kSchedXYZT, t});
+        }
+    }
     hipEvent_t e0 = take_event(c), e1 = take_event(c);
     if (!e0 || !e1) return GF_ERR_HIP;
     const bool timing = c->timing;
@@ -919,8 +1083,8 @@ gf_status choose_schedule(gf_ctx c, int requested)
     if (path) {
         FILE *f = fopen(path, "a");
         if (f) {
-            fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), pick.sched, pick.tiles.xy_target, pick.tiles.xy_ept,
-                    pick.tiles.zt_target, pick.tiles.zt_ept);
+            fprintf(f, "%s %d %d %d %d %d %d %d\n", key.c_str(), pick.sched, pick.tiles.xy_target, pick.tiles.xy_ept,
+                    pick.tiles.zt_target, pick.tiles.zt_ept, pick.tiles.zt_reg, pick.tiles.xy_reg);
             fclose(f);
         }
     }
@@ -936,8 +1100,12 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
     c->ws = (char *)d_ws;
     c->ws_bytes = ws_bytes;
     c->chunk = params[0].chunk > 0 ? params[0].chunk : kDefaultChunk;
-    HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    HIPCHK(c, hipHostMalloc((void **)&c->h_ctrl, sizeof(Ctrl) * ncfg, hipHostMallocDefault));
+    if (c->noalloc) {
+        c->h_ctrl = new Ctrl[ncfg];
+    } else {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipHostMalloc((void **)&c->h_ctrl, sizeof(Ctrl) * ncfg, hipHostMallocDefault));
+    }
     c->histF.assign(ncfg, {});
     c->histT.assign(ncfg, {});
     c->kt.resize(K_N);
@@ -985,7 +1153,6 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         C.U = (double2 *)links[k];
         C.U12[0] = (double2 *)(c->ws + l.links12a);
         C.U12[1] = (double2 *)(c->ws + l.links12b);
-        C.g12 = (double2 *)(c->ws + l.g12);
         C.U12f[0] = l.links12fa ? (float2 *)(c->ws + l.links12fa) : nullptr;
         C.U12f[1] = l.links12fb ? (float2 *)(c->ws + l.links12fb) : nullptr;
         C.g12f = l.g12f ? (float2 *)(c->ws + l.g12f) : nullptr;
@@ -1039,7 +1206,6 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
     c->L.link_f32 = 0;
     c->link_prec = params[0].link_prec;
     c->refine_theta = params[0].refine_theta > 0.0 ? params[0].refine_theta : 1e-10;
-    c->L.xchg = getenv("GF_NOXCHG") ? 0 : 1;
     c->L.any_reunit = 0;
     for (int k = 0; k < ncfg; ++k) c->L.any_reunit |= params[k].reunit_every > 0;
     c->L.ncfg = ncfg;
@@ -1061,6 +1227,67 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
     gf_status st = read_ctrl(c);
     if (st != GF_OK) return st;
     return choose_schedule(c, params[0].fft_schedule);
+}
+
+// Workspace of a functional-only context: the header, g [3][3][V] and the
+// partial sums of the site blocks.
+struct FnLayout {
+    size_t g, partials, total;
+};
+
+FnLayout fn_layout(const gf_params &p)
+{
+    const size_t V = (size_t)p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
+    FnLayout l;
+    size_t o = header_bytes(1) + align_up(sizeof(Ctrl));
+    l.g = o;
+    o = align_up(o + 9 * V * 16);
+    l.partials = o;
+    o = align_up(o + ((V + kSiteBlock - 1) / kSiteBlock) * 4 * sizeof(double));
+    l.total = o;
+    return l;
+}
+
+gf_status setup_functional(gf_ctx c, const gf_params *p, void *links, void *d_ws, void *stream)
+{
+    c->functional_only = true;
+    c->noalloc = true;
+    c->ncfg = 1;
+    c->params.assign(p, p + 1);
+    c->stream = (hipStream_t)stream;
+    c->ws = (char *)d_ws;
+    c->histF.assign(1, {});
+    c->histT.assign(1, {});
+    c->kt.resize(K_N);
+    for (int k = 0; k < K_N; ++k) c->kt[k].name = kNames[k];
+    size_t o = 0;
+    c->d_cfgs = (Cfg *)(c->ws + o);
+    o += align_up(sizeof(Cfg));
+    c->d_batch = (Batch *)(c->ws + o);
+    o += align_up(sizeof(Batch));
+    c->d_batch_act = (Batch *)(c->ws + o);
+    o += align_up(sizeof(Batch));
+    c->d_scalar = (double *)(c->ws + o);
+    o += align_up(64);
+    const FnLayout l = fn_layout(*p);
+    c->cfg.assign(1, Cfg{});
+    Cfg &C = c->cfg[0];
+    for (int mu = 0; mu < 4; ++mu) C.dims[mu] = p->dims[mu];
+    C.V = p->dims[0] * p->dims[1] * p->dims[2] * p->dims[3];
+    C.V2 = p->dims[0] * p->dims[1];
+    C.V3 = C.V2 * p->dims[2];
+    C.nblk_site = (C.V + kSiteBlock - 1) / kSiteBlock;
+    C.U = (double2 *)links;
+    C.g = (double2 *)(c->ws + l.g);
+    C.partials = (double *)(c->ws + l.partials);
+    C.ctrl = (Ctrl *)(c->ws + o);
+    c->L.cfgs = c->d_cfgs;
+    c->L.batch = c->d_batch;
+    c->L.ncfg = 1;
+    c->L.stream = c->stream;
+    HIPCHK(c, hipMemcpyAsync(c->d_cfgs, c->cfg.data(), sizeof(Cfg), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GF_OK;
 }
 
 size_t workspace_total(int ncfg, const gf_params *params)
@@ -1106,7 +1333,7 @@ size_t gf_workspace_bytes_batch(int32_t n_cfg, const gf_params *params)
 }
 
 static gf_status init_common(gf_ctx *out, int32_t n_cfg, const gf_params *params, void *const *links, void *d_ws,
-                             size_t ws_bytes, void *stream, bool batch)
+                             size_t ws_bytes, void *stream, bool batch, bool noalloc = false)
 {
     if (!out || !params || !links || !d_ws) return GF_ERR_ARG;
     *out = nullptr;
@@ -1119,6 +1346,7 @@ static gf_status init_common(gf_ctx *out, int32_t n_cfg, const gf_params *params
     if (((uintptr_t)d_ws) % kAlign) return GF_ERR_ARG;
     gf_ctx c = new gf_ctx_s();
     c->batch = batch;
+    c->noalloc = noalloc;
     gf_status st = setup(c, n_cfg, params, links, d_ws, ws_bytes, stream);
     if (st != GF_OK) {
         std::string e = c->err;
@@ -1136,6 +1364,30 @@ gf_status gf_init(gf_ctx *ctx, const gf_params *params, void *d_links, void *d_w
     return init_common(ctx, 1, params, l, d_ws, ws_bytes, stream, false);
 }
 
+size_t gf_workspace_bytes_functional(const gf_params *params)
+{
+    if (!valid_params(params)) return 0;
+    return fn_layout(*params).total;
+}
+
+gf_status gf_init_functional(gf_ctx *ctx, const gf_params *params, void *d_links, void *d_ws, size_t ws_bytes,
+                             void *stream)
+{
+    if (!ctx || !params || !d_links || !d_ws) return GF_ERR_ARG;
+    *ctx = nullptr;
+    if (!valid_params(params)) return GF_ERR_SHAPE;
+    if (ws_bytes < fn_layout(*params).total) return GF_ERR_SHAPE;
+    if (((uintptr_t)d_ws) % kAlign) return GF_ERR_ARG;
+    gf_ctx c = new gf_ctx_s();
+    gf_status st = setup_functional(c, params, d_links, d_ws, stream);
+    if (st != GF_OK) {
+        gf_destroy(c);
+        return st;
+    }
+    *ctx = c;
+    return GF_OK;
+}
+
 gf_status gf_init_batch(gf_ctx *ctx, int32_t n_cfg, const gf_params *params, void *const *d_links, void *d_ws,
                         size_t ws_bytes, void *stream)
 {
@@ -1146,6 +1398,7 @@ gf_status gf_init_batch(gf_ctx *ctx, int32_t n_cfg, const gf_params *params, voi
 gf_status gf_functional(gf_ctx c, double *F, double *theta)
 {
     if (!c) return GF_ERR_ARG;
+    if (c->functional_only) return GF_ERR_STATE;
     if (c->batch) return GF_ERR_STATE;
     HIPCHK(c, enqueue_measure(c));
     HIPCHK(c, hipMemcpyAsync(c->h_ctrl, c->cfg[0].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
@@ -1159,6 +1412,7 @@ gf_status gf_functional(gf_ctx c, double *F, double *theta)
 gf_status gf_functional_batch(gf_ctx c, double *F, double *theta)
 {
     if (!c) return GF_ERR_ARG;
+    if (c->functional_only) return GF_ERR_STATE;
     HIPCHK(c, enqueue_measure(c));
     HIPCHK(c, hipMemcpyAsync(c->h_ctrl, c->cfg[0].ctrl, sizeof(Ctrl) * c->ncfg, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1174,11 +1428,12 @@ gf_status gf_functional_batch(gf_ctx c, double *F, double *theta)
 gf_status gf_step(gf_ctx c, int32_t n, double *F, double *theta)
 {
     if (!c || n < 0) return GF_ERR_ARG;
+    if (c->functional_only) return GF_ERR_STATE;
     if (c->batch) return GF_ERR_STATE;
     if (n > 0) {
         set_link_storage(c, c->link_prec == 1 ? 1 : 0);
         HIPCHK(c, launch_arm(c->L, c->ncfg, -1.0, n, 0));
-        gf_status st = run_until_done(c);
+        gf_status st = run_until_done(c, n);
         if (st != GF_OK) return st;
     }
     if (F) *F = c->h_ctrl[0].F;
@@ -1189,6 +1444,7 @@ gf_status gf_step(gf_ctx c, int32_t n, double *F, double *theta)
 gf_status gf_fix_until(gf_ctx c, double theta_eps, int64_t max_iter, int64_t *iters, double *F, double *theta)
 {
     if (!c || max_iter < 0) return GF_ERR_ARG;
+    if (c->functional_only) return GF_ERR_STATE;
     if (c->batch) return GF_ERR_STATE;
     const long long before = c->h_ctrl[0].iter;
     gf_status st = fix_phases(c, theta_eps, max_iter);
@@ -1202,6 +1458,7 @@ gf_status gf_fix_until(gf_ctx c, double theta_eps, int64_t max_iter, int64_t *it
 gf_status gf_fix_until_batch(gf_ctx c, double theta_eps, int64_t max_iter, int64_t *iters, double *F, double *theta)
 {
     if (!c || max_iter < 0) return GF_ERR_ARG;
+    if (c->functional_only) return GF_ERR_STATE;
     std::vector<long long> before(c->ncfg);
     for (int k = 0; k < c->ncfg; ++k) before[k] = c->h_ctrl[k].iter;
     gf_status st = fix_phases(c, theta_eps, max_iter);
@@ -1214,12 +1471,10 @@ gf_status gf_fix_until_batch(gf_ctx c, double theta_eps, int64_t max_iter, int64
     return status_from_done(c, true);
 }
 
-gf_status gf_history(gf_ctx c, int64_t cap, double *F_hist, double *theta_hist, int64_t *n)
+static gf_status history_of(gf_ctx c, int k, int64_t cap, double *F_hist, double *theta_hist, int64_t *n)
 {
-    if (!c || cap < 0) return GF_ERR_ARG;
-    if (c->batch) return GF_ERR_STATE;
-    const auto &F = c->histF[0];
-    const auto &T = c->histT[0];
+    const auto &F = c->histF[k];
+    const auto &T = c->histT[k];
     const int64_t avail = (int64_t)F.size();
     if (n) *n = avail;
     const int64_t m = cap < avail ? cap : avail;
@@ -1230,9 +1485,23 @@ gf_status gf_history(gf_ctx c, int64_t cap, double *F_hist, double *theta_hist, 
     return GF_OK;
 }
 
+gf_status gf_history(gf_ctx c, int64_t cap, double *F_hist, double *theta_hist, int64_t *n)
+{
+    if (!c || cap < 0) return GF_ERR_ARG;
+    if (c->batch) return GF_ERR_STATE;
+    return history_of(c, 0, cap, F_hist, theta_hist, n);
+}
+
+gf_status gf_history_batch(gf_ctx c, int32_t k, int64_t cap, double *F_hist, double *theta_hist, int64_t *n)
+{
+    if (!c || cap < 0 || k < 0 || k >= c->ncfg) return GF_ERR_ARG;
+    return history_of(c, k, cap, F_hist, theta_hist, n);
+}
+
 gf_status gf_delta(gf_ctx c, void *d_delta)
 {
     if (!c || !d_delta) return GF_ERR_ARG;
+    if (c->functional_only) return GF_ERR_STATE;
     if (c->batch) return GF_ERR_STATE;
     HIPCHK(c, launch_delta(c->L, 0, (double2 *)d_delta));
     HIPCHK(c, launch_reduce(c->L, 1, 0, 0));
@@ -1243,6 +1512,7 @@ gf_status gf_delta(gf_ctx c, void *d_delta)
 gf_status gf_gauge(gf_ctx c, void *d_g)
 {
     if (!c || !d_g) return GF_ERR_ARG;
+    if (c->functional_only) return GF_ERR_STATE;
     if (c->batch) return GF_ERR_STATE;
     HIPCHK(c, launch_delta(c->L, 0, nullptr));
     HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, (double2 *)d_g));
@@ -1253,6 +1523,7 @@ gf_status gf_gauge(gf_ctx c, void *d_g)
 gf_status gf_apply_gauge(gf_ctx c, const void *d_g)
 {
     if (!c || !d_g) return GF_ERR_ARG;
+    if (c->functional_only) return GF_ERR_STATE;
     if (c->batch) return GF_ERR_STATE;
     HIPCHK(c, launch_update(c->L, 0, (const double2 *)d_g));
     HIPCHK(c, enqueue_measure(c));
@@ -1263,6 +1534,7 @@ gf_status gf_apply_gauge(gf_ctx c, const void *d_g)
 gf_status gf_heatbath(gf_ctx c, double beta, int32_t n_sweeps, int32_t n_or, uint64_t seed, int64_t sweep0)
 {
     if (!c || n_sweeps < 0 || n_or < 0 || !(beta >= 0.0) || sweep0 < 0) return GF_ERR_ARG;
+    if (c->functional_only) return GF_ERR_STATE;
     if (c->batch) return GF_ERR_STATE;
     const Cfg &C = c->cfg[0];
     for (int mu = 0; mu < 4; ++mu)
@@ -1292,6 +1564,7 @@ gf_status gf_plaquette(gf_ctx c, double *P)
 gf_status gf_fft(gf_ctx c, void *d_fields, int32_t nfields, int32_t sign)
 {
     if (!c || !d_fields || nfields < 1 || nfields > 65535 || (sign != 1 && sign != -1)) return GF_ERR_ARG;
+    if (c->functional_only) return GF_ERR_STATE;
     if (c->batch) return GF_ERR_STATE;
     const Launch &L = c->L;
     switch (c->sched) {
@@ -1344,7 +1617,12 @@ gf_status gf_destroy(gf_ctx c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+    if (c->h_ctrl) {
+        if (c->noalloc)
+            delete[] c->h_ctrl;
+        else
+            (void)hipHostFree(c->h_ctrl);
+    }
     delete c;
     return GF_OK;
 }

@@ -61,6 +61,8 @@ def lib():
             "gf_workspace_bytes": (S, [PP]),
             "gf_workspace_bytes_batch": (S, [I32, PP]),
             "gf_init": (st, [ctypes.POINTER(P), PP, P, P, S, P]),
+            "gf_workspace_bytes_functional": (S, [PP]),
+            "gf_init_functional": (st, [ctypes.POINTER(P), PP, P, P, S, P]),
             "gf_init_batch": (st, [ctypes.POINTER(P), I32, PP, ctypes.POINTER(P), P, S, P]),
             "gf_functional": (st, [P, PD, PD]),
             "gf_functional_batch": (st, [P, PD, PD]),
@@ -68,6 +70,7 @@ def lib():
             "gf_fix_until": (st, [P, D, I64, PI64, PD, PD]),
             "gf_fix_until_batch": (st, [P, D, I64, PI64, PD, PD]),
             "gf_history": (st, [P, I64, PD, PD, PI64]),
+            "gf_history_batch": (st, [P, I32, I64, PD, PD, PI64]),
             "gf_delta": (st, [P, P]),
             "gf_gauge": (st, [P, P]),
             "gf_apply_gauge": (st, [P, P]),
@@ -148,6 +151,18 @@ def gf_init(params: gf_params, links: torch.Tensor, ws: torch.Tensor, stream=Non
     return ctx
 
 
+def gf_workspace_bytes_functional(params: gf_params) -> int:
+    return int(lib().gf_workspace_bytes_functional(ctypes.byref(params)))
+
+
+def gf_init_functional(params: gf_params, links: torch.Tensor, ws: torch.Tensor, stream=None):
+    ctx = ctypes.c_void_p()
+    st = lib().gf_init_functional(ctypes.byref(ctx), ctypes.byref(params), _ptr(links), _ptr(ws),
+                                  ws.numel() * ws.element_size(), _stream_ptr(stream))
+    _check(st, "gf_init_functional")
+    return ctx
+
+
 def gf_init_batch(params_list, links_list, ws: torch.Tensor, stream=None):
     n = len(params_list)
     arr = (gf_params * n)(*params_list)
@@ -203,6 +218,15 @@ def gf_history(ctx):
     F = (ctypes.c_double * max(1, n.value))()
     T = (ctypes.c_double * max(1, n.value))()
     _check(lib().gf_history(ctx, n.value, F, T, ctypes.byref(n)), "gf_history", ctx)
+    return list(F)[: n.value], list(T)[: n.value]
+
+
+def gf_history_batch(ctx, k: int):
+    n = ctypes.c_int64()
+    _check(lib().gf_history_batch(ctx, int(k), 0, None, None, ctypes.byref(n)), "gf_history_batch", ctx)
+    F = (ctypes.c_double * max(1, n.value))()
+    T = (ctypes.c_double * max(1, n.value))()
+    _check(lib().gf_history_batch(ctx, int(k), n.value, F, T, ctypes.byref(n)), "gf_history_batch", ctx)
     return list(F)[: n.value], list(T)[: n.value]
 
 

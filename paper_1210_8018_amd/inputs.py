@@ -77,29 +77,42 @@ def _workers() -> int:
 _POOL_MIN = 1 << 20  # sites from which the per-matrix arithmetic is spread over processes
 
 
-def _shm_put(arr, owned):
-    from multiprocessing import shared_memory
+# Shared blocks between the generator and its worker processes are plain
+# files in /dev/shm (memory-backed), mapped by both sides: unlike
+# multiprocessing.shared_memory this starts no resource-tracker process that
+# could outlive the caller. The parent creates and removes every file.
+def _shm_dir() -> str:
+    return "/dev/shm" if os.path.isdir("/dev/shm") else __import__("tempfile").gettempdir()
 
-    shm = shared_memory.SharedMemory(create=True, size=max(1, arr.nbytes))
-    owned.append(shm)
-    np.ndarray(arr.shape, arr.dtype, buffer=shm.buf)[...] = arr
-    return (shm.name, arr.shape, arr.dtype.str)
+
+def _shm_put(arr, owned):
+    import mmap
+    import tempfile
+
+    fd, path = tempfile.mkstemp(prefix="gf_gen_", dir=_shm_dir())
+    owned.append(path)
+    try:
+        os.ftruncate(fd, max(1, arr.nbytes))
+        with mmap.mmap(fd, max(1, arr.nbytes)) as m:
+            np.ndarray(arr.shape, arr.dtype, buffer=m)[...] = arr
+    finally:
+        os.close(fd)
+    return (path, arr.shape, arr.dtype.str)
 
 
 def _shm_get(desc, keep):
-    from multiprocessing import resource_tracker, shared_memory
+    import mmap
 
-    name, shape, dt = desc
+    path, shape, dt = desc
     shape = tuple(shape)
-    shm = shared_memory.SharedMemory(name=name)
-    # the parent owns (and unlinks) every block; do not let this process's
-    # resource tracker claim it
+    nbytes = int(np.prod(shape, dtype=np.int64)) * np.dtype(dt).itemsize
+    fd = os.open(path, os.O_RDWR)
     try:
-        resource_tracker.unregister(shm._name, "shared_memory")
-    except Exception:
-        pass
-    keep.append(shm)
-    return np.ndarray(shape, np.dtype(dt), buffer=shm.buf)
+        m = mmap.mmap(fd, max(1, nbytes))
+    finally:
+        os.close(fd)
+    keep.append(m)
+    return np.ndarray(shape, np.dtype(dt), buffer=m)
 
 
 def _worker_main():
@@ -113,18 +126,16 @@ def _worker_main():
 
     job = json.loads(sys.stdin.read())
     keep = []
-    try:
-        arrs = [_shm_get(tuple(d), keep) for d in job["descs"]]
-        a, b = job["a"], job["b"]
-        if job["kind"] == "haar":
-            z, out = arrs
-            out[a:b] = _haar_from_ginibre(z[a:b])
-        else:
-            h, w, fwd, out = arrs
-            out[a:b] = _link_block(h[a:b], job["eps"] * w[a:b], h[fwd[a:b]])
-    finally:
-        for m in keep:
-            m.close()
+    arrs = [_shm_get(tuple(d), keep) for d in job["descs"]]
+    a, b = job["a"], job["b"]
+    if job["kind"] == "haar":
+        z, out = arrs
+        out[a:b] = _haar_from_ginibre(z[a:b])
+    else:
+        h, w, fwd, out = arrs
+        out[a:b] = _link_block(h[a:b], job["eps"] * w[a:b], h[fwd[a:b]])
+    for m in keep:
+        m.flush()
 
 
 def _parallel(kind, n, inputs, out_shape, eps=0.0):
@@ -157,15 +168,17 @@ def _parallel(kind, n, inputs, out_shape, eps=0.0):
         for p in procs:
             if p.wait(timeout=1800) != 0:
                 raise RuntimeError(f"input generator worker failed with status {p.returncode}")
-        return np.array(np.ndarray(out_shape, np.complex128, buffer=owned[-1].buf))
+        return np.fromfile(owned[-1], dtype=np.complex128).reshape(out_shape)
     finally:
         for p in procs:
             if p.poll() is None:
                 p.kill()
                 p.wait()
-        for m in owned:
-            m.close()
-            m.unlink()
+        for path in owned:
+            try:
+                os.unlink(path)
+            except OSError:
+                pass
 
 
 def _haar_from_ginibre(z: np.ndarray) -> np.ndarray:

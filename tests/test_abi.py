@@ -44,6 +44,9 @@ def test_host_only_calls_without_gpu():
     pl[1] = gf.make_params((8, 8, 8, 16), fft_prec=0)  # one precision per batch
     assert gf.gf_workspace_bytes_batch(pl) == 0
     assert gf.lib().gf_init(None, None, None, None, 0, None) == gf.GF_ERR_ARG
+    # functional-only contexts need g and the block partials, not the iteration's buffers
+    fp = gf.make_params((24, 24, 24, 24))
+    assert 144 * 24**4 < gf.gf_workspace_bytes_functional(fp) < 160 * 24**4 < gf.gf_workspace_bytes(fp)
 
 
 def test_params_layout_and_link_storage_options():

@@ -85,3 +85,37 @@ def test_central_differences_24x4():
             wm[a] -= h
             fd = (oracle.local_functional_g(dims, U, om, s, wp) - oracle.local_functional_g(dims, U, om, s, wm)) / (2 * h)
             assert abs(fd - got[k, a]) < 1e-7 * max(1.0, abs(fd)), (s, a, fd, got[k, a])
+
+
+def test_functional_context_is_light_reused_and_checks_omega():
+    """Forward and backward share one functional-only context (g and block
+    partials, no iteration workspace, no measurement); the iteration calls are
+    refused on it; omega of the wrong type, shape or device is rejected before
+    any kernel reads it."""
+    from paper_1210_8018_amd import api
+
+    dims = (6, 4, 4, 8)
+    V = int(np.prod(dims))
+    p = gf.make_params(dims)
+    assert gf.gf_workspace_bytes_functional(p) < 160 * V + 65536 < gf.gf_workspace_bytes(p)
+    U = random_links(dims, 0.3, 54)
+    om = random_omega(dims, 0.2, 55)
+    Ud, omd = dev(U), dev(om)
+    omd.requires_grad_(True)
+    api._fn_contexts.clear()
+    F = GaugeFunctional.apply(Ud, omd)
+    F.backward()
+    assert len(api._fn_contexts) == 1
+    ctx = next(iter(api._fn_contexts.values()))[0]
+    assert gf.lib().gf_step(ctx, 1, None, None) == gf.GF_ERR_STATE
+    assert gf.lib().gf_functional(ctx, None, None) == gf.GF_ERR_STATE
+    assert abs(float(F) - oracle.functional_g(dims, U, om)) < 1e-14
+    # the context reads the links as they are at each call
+    U2 = random_links(dims, 0.3, 56)
+    Ud.copy_(dev(U2))
+    F2 = GaugeFunctional.apply(Ud, omd.detach())
+    assert abs(float(F2) - oracle.functional_g(dims, U2, om)) < 1e-14
+    assert len(api._fn_contexts) == 1
+    for bad in (omd.detach().float(), omd.detach()[:, : V - 1], omd.detach().cpu(), omd.detach().reshape(-1)):
+        with pytest.raises(ValueError):
+            GaugeFunctional.apply(Ud, bad)

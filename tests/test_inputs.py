@@ -40,3 +40,28 @@ def test_batch_workload_eps_range():
     for dims, eps, seed, U in got:
         assert 0.2 <= eps < 0.6
         assert U.shape[3:] == tuple(dims[::-1])
+
+
+def test_worker_pool_is_bitwise_serial_and_leaves_nothing(monkeypatch):
+    """The per-matrix arithmetic spread over worker processes (used for large
+    lattices) gives bitwise the serial result and leaves no process and no
+    shared file behind."""
+    import glob
+    import os
+
+    import psutil
+
+    from paper_1210_8018_amd import inputs
+
+    def draw():
+        return inputs.random_links((6, 4, 4, 4), 0.3, 9)
+
+    monkeypatch.setattr(inputs, "_POOL_MIN", 1 << 40)
+    serial = draw()
+    monkeypatch.setattr(inputs, "_POOL_MIN", 100)
+    monkeypatch.setenv("GF_GEN_PROCS", "3")
+    before = set(glob.glob(os.path.join(inputs._shm_dir(), "gf_gen_*")))
+    pooled = draw()
+    assert np.array_equal(pooled, serial)
+    assert psutil.Process().children(recursive=True) == []
+    assert set(glob.glob(os.path.join(inputs._shm_dir(), "gf_gen_*"))) == before

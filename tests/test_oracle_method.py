@@ -288,3 +288,36 @@ def test_single_precision_storage_iteration(orc):
     one = unit_links(dims)
     n1, U1, _, T1 = orc.fix(dims, one, eps=EPS, f32_storage=True)
     assert n1 == 0 and np.array_equal(U1, one)
+
+
+def test_two_row_storage_and_axis_order_only_round_differently(orc):
+    """The 12-real FP64 representation (section 2.2: two rows stored, the
+    third rebuilt) and a permuted order of the transform's axes are the same
+    iteration in exact arithmetic: same count, F to rounding, theta to
+    rounding while it is well above its floor; the stored links are exactly
+    two-row (third row = conj(r0 x r1))."""
+    dims = (8, 4, 6, 4)
+    U = random_links(dims, 0.3, 11)
+    n0, U0, F0, T0 = orc.fix(dims, U)
+    n1, U1, F1, T1 = orc.fix(dims, U, two_row=True)
+    n2, U2, F2, T2 = orc.fix(dims, U, fft_axis_order=(2, 0, 3, 1))
+    assert n0 == n1 == n2
+    for F, T in ((F1, T1), (F2, T2)):
+        assert np.max(np.abs(F - F0)) < 1e-15
+        big = T0 > 1e-8
+        assert np.max(np.abs(T[big] - T0[big]) / T0[big]) < 1e-12
+        assert np.any(T != T0)  # they do round differently
+    M = links_aos(U1).reshape(-1, 3, 3)
+    r2 = np.conj(np.cross(M[:, 0], M[:, 1]))
+    assert np.max(np.abs(r2 - M[:, 2])) < 1e-15  # numpy's cross product rounds in its own order
+    assert np.max(np.abs(U1 - U0)) < 1e-13 and np.max(np.abs(U2 - U0)) < 1e-13
+    # the transform itself with a permuted axis order still equals the DFT
+    V = int(np.prod(dims))
+    f = np.random.default_rng(3).standard_normal(V) + 1j * np.random.default_rng(4).standard_normal(V)
+    ref = orc.fft4d(dims, f, -1)
+    orc.set_fft_axis_order((3, 1, 0, 2))
+    try:
+        got = orc.fft4d(dims, f, -1)
+    finally:
+        orc.set_fft_axis_order()
+    assert np.max(np.abs(got - ref)) < 1e-12 and not np.array_equal(got, ref)
