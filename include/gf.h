@@ -230,6 +230,28 @@ gf_status gf_functional_g(gf_ctx ctx, const double *d_omega, double *F);
 gf_status gf_functional_g_backward(gf_ctx ctx, const double *d_omega, double grad_out, double *d_dF_domega,
                                    void *d_dF_dU);
 
+/*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): gf_init +
+ * gf_fix_until + gf_destroy in one call that allocates nothing. Its
+ * workspace is a static device array of GF_STATIC_SCRATCH_BYTES inside the
+ * library, one per GPU, held until the process ends; the call creates no
+ * stream, event or graph and no pinned host memory, launches every kernel on
+ * `stream` and reads the stopping flag back with plain copies. Lattices
+ * whose gf_workspace_bytes(params) exceeds GF_STATIC_SCRATCH_BYTES are
+ * rejected with GF_ERR_SHAPE (64 MiB holds up to about 58 000 sites with the
+ * FP64 transform: 8^4, 12^4, 16^3 x 12). params->fft_schedule 0 takes the
+ * 2D passes wherever they fit (no autotuning: that needs timing events).
+ * d_links, theta_eps, max_iter and the outputs are as for gf_init and
+ * gf_fix_until. Every call on one GPU uses that GPU's array and leaves its
+ * contents behind (each call initialises what it reads): calls that overlap
+ * on one GPU, from any thread or stream, race and must be serialised by the
+ * caller. Synchronises.
+ */
+#define GF_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+gf_status gf_fix_until_static(const gf_params *params, void *d_links, double theta_eps, int64_t max_iter,
+                              int64_t *iters, double *F, double *theta, void *stream);
+
 /* Release the context (host state and graphs only). */
 gf_status gf_destroy(gf_ctx ctx);
 

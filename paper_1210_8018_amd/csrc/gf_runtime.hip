@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1311,6 +1312,36 @@ gf_status status_from_done(gf_ctx c, bool want_eps)
     return st;
 }
 
+// Workspace of gf_fix_until_static: one array per GPU, held by the loaded
+// library until the process ends. In host code `scratch` names a host-side
+// stand-in, not device memory: only the address returned by
+// hipGetSymbolAddress for the current device may be handed to kernels or
+// copies.
+static __device__ __align__(256) unsigned char scratch[GF_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+hipError_t static_scratch(void **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1393,6 +1424,24 @@ gf_status gf_init_batch(gf_ctx *ctx, int32_t n_cfg, const gf_params *params, voi
 {
     if (n_cfg < 1 || n_cfg > kMaxCfg) return GF_ERR_ARG;
     return init_common(ctx, n_cfg, params, d_links, d_ws, ws_bytes, stream, true);
+}
+
+gf_status gf_fix_until_static(const gf_params *params, void *d_links, double theta_eps, int64_t max_iter,
+                              int64_t *iters, double *F, double *theta, void *stream)
+{
+    if (!params || !d_links || max_iter < 0) return GF_ERR_ARG;
+    const size_t need = gf_workspace_bytes(params);
+    if (need == 0) return GF_ERR_SHAPE;
+    if (need > (size_t)GF_STATIC_SCRATCH_BYTES) return GF_ERR_SHAPE;  // lattice too large for the scratch
+    void *ws = nullptr;
+    if (static_scratch(&ws) != hipSuccess) return GF_ERR_HIP;
+    gf_ctx c = nullptr;
+    void *l[1] = {d_links};
+    gf_status st = init_common(&c, 1, params, l, ws, (size_t)GF_STATIC_SCRATCH_BYTES, stream, false, true);
+    if (st != GF_OK) return st;
+    st = gf_fix_until(c, theta_eps, max_iter, iters, F, theta);
+    gf_destroy(c);
+    return st;
 }
 
 gf_status gf_functional(gf_ctx c, double *F, double *theta)

@@ -69,6 +69,7 @@ def lib():
             "gf_step": (st, [P, I32, PD, PD]),
             "gf_fix_until": (st, [P, D, I64, PI64, PD, PD]),
             "gf_fix_until_batch": (st, [P, D, I64, PI64, PD, PD]),
+            "gf_fix_until_static": (st, [PP, P, D, I64, PI64, PD, PD, P]),
             "gf_history": (st, [P, I64, PD, PD, PI64]),
             "gf_history_batch": (st, [P, I32, I64, PD, PD, PI64]),
             "gf_delta": (st, [P, P]),
@@ -199,6 +200,21 @@ def gf_fix_until(ctx, theta_eps: float, max_iter: int, allow_maxiter: bool = Fal
     ok = (GF_OK, GF_ERR_MAXITER) if allow_maxiter else (GF_OK,)
     st = lib().gf_fix_until(ctx, float(theta_eps), int(max_iter), ctypes.byref(it), ctypes.byref(F), ctypes.byref(th))
     _check(st, "gf_fix_until", ctx, ok)
+    return int(it.value), F.value, th.value, st
+
+
+GF_STATIC_SCRATCH_BYTES = 64 * 1024 * 1024  # include/gf.h
+
+
+def gf_fix_until_static(params: gf_params, links: torch.Tensor, theta_eps: float, max_iter: int,
+                        allow_maxiter: bool = False, stream=None):
+    """The allocation-free gf_init + gf_fix_until + gf_destroy (workspace in the library's static array)."""
+    it = ctypes.c_int64()
+    F, th = ctypes.c_double(), ctypes.c_double()
+    ok = (GF_OK, GF_ERR_MAXITER) if allow_maxiter else (GF_OK,)
+    st = lib().gf_fix_until_static(ctypes.byref(params), _ptr(links), float(theta_eps), int(max_iter),
+                                   ctypes.byref(it), ctypes.byref(F), ctypes.byref(th), _stream_ptr(stream))
+    _check(st, "gf_fix_until_static", None, ok)
     return int(it.value), F.value, th.value, st
 
 

@@ -44,9 +44,18 @@ def test_host_only_calls_without_gpu():
     pl[1] = gf.make_params((8, 8, 8, 16), fft_prec=0)  # one precision per batch
     assert gf.gf_workspace_bytes_batch(pl) == 0
     assert gf.lib().gf_init(None, None, None, None, 0, None) == gf.GF_ERR_ARG
+    # the allocation-free call checks its arguments and the size of its static
+    # array on the host before any HIP call
+    assert gf.lib().gf_fix_until_static(None, None, 1e-15, 10, None, None, None, None) == gf.GF_ERR_ARG
+    big = gf.make_params((32, 32, 16, 16))
+    assert gf.gf_workspace_bytes(big) > gf.GF_STATIC_SCRATCH_BYTES
+    assert gf.lib().gf_fix_until_static(ctypes.byref(big), ctypes.c_void_p(256), 1e-15, 10, None, None, None,
+                                        None) == gf.GF_ERR_SHAPE
     # functional-only contexts need g and the block partials, not the iteration's buffers
     fp = gf.make_params((24, 24, 24, 24))
     assert 144 * 24**4 < gf.gf_workspace_bytes_functional(fp) < 160 * 24**4 < gf.gf_workspace_bytes(fp)
+    small = gf.make_params((12, 12, 12, 12))
+    assert 0 < gf.gf_workspace_bytes(small) <= gf.GF_STATIC_SCRATCH_BYTES
 
 
 def test_params_layout_and_link_storage_options():
