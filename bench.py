@@ -72,6 +72,8 @@ def main():
                     choices=["headline", "batch", "large48", "large64", "diff", "thermal"])
     ap.add_argument("--beta", type=float, default=6.0)
     ap.add_argument("--sweeps", type=int, default=300)
+    ap.add_argument("--oracle-iters", type=int, default=20,
+                    help="large48/large64: iterations compared with the oracle")
     ap.add_argument("--fft-schedule", type=int, default=0,
                     help="transform schedule of the headline contexts (0: autotuned; see gf_params.fft_schedule)")
     args = ap.parse_args()
@@ -216,6 +218,18 @@ def main():
                "sample": f"{args.cpu_iters} iterations of Alg. 1 on the same {'x'.join(map(str, dims))} "
                          f"configuration (FP64 C oracle, OpenMP), {dcpu:.1f} s",
                "cpu_model": _cpu_model()}
+        # the same oracle on one host thread, a shorter sample
+        n1 = max(1, args.cpu_iters // 20)
+        oracle.set_num_threads(1)
+        try:
+            log(f"cpu oracle: {n1} iterations at {dims} on 1 thread")
+            t4 = time.perf_counter()
+            oracle.fix(dims, U_host, alpha=0.08, eps=-1.0, max_iter=n1)
+            d1 = time.perf_counter() - t4
+        finally:
+            oracle.set_num_threads(nthr)
+        cpu["single_thread"] = {"value": n1 / d1, "unit": "iters/s", "cores": 1,
+                                "sample": f"{n1} iterations, {d1:.1f} s"}
 
     f64 = res["fp64"]
     f32 = res["fp32_fft"]
@@ -233,7 +247,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, dims))} SU(3) links, generator eps={args.eps} seed={args.seed}, "
-                               f"alpha=0.08, FP64 (plain method)",
+                               f"alpha=0.08, FP64 transform and arithmetic, links stored as two FP64 rows "
+                               f"(12-real form, third row rebuilt)",
                    "dims": list(dims), "alpha": 0.08, "theta_eps": 1e-15},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -373,16 +388,32 @@ def bench_large(args):
     if not args.no_cpu:
         import oracle
 
-        k = 2
+        # the first k iterations against the FP64 oracle: per-iteration F and
+        # theta, and the plaquette of the links after k updates (gauge
+        # invariant: equal to the initial one up to rounding)
+        k = args.oracle_iters
+        plaq = {}
+        for prec, tag in ((1, "fp32_fft"), (0, "fp64")):
+            U = U0.clone()
+            fx = GaugeFixer(U, fft_prec=prec, reunit_every=100)
+            fx.step(k)
+            plaq[tag] = fx.plaquette()
+            fx.close()
+            del fx, U
         log(f"cpu oracle: {k} iterations at {dims}")
         t2 = time.perf_counter()
-        _, _, Fo, To = oracle.fix(dims, U_host, alpha=0.08, eps=-1.0, max_iter=k, reunit_every=100)
+        _, Uo, Fo, To = oracle.fix(dims, U_host, alpha=0.08, eps=-1.0, max_iter=k, reunit_every=100)
         dcpu = time.perf_counter() - t2
+        P0, Pk = oracle.plaquette(dims, U_host), oracle.plaquette(dims, Uo)
+        del Uo
         cpu = {"value": k / dcpu, "unit": "iters/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"{k} iterations at {L}^4", "F_rel_err_fp32_fft": float(np.max(np.abs(Fa[:k + 1] - Fo) / np.abs(Fo))),
+               "sample": f"{k} iterations at {L}^4, {dcpu:.1f} s",
+               "F_rel_err_fp32_fft": float(np.max(np.abs(Fa[:k + 1] - Fo) / np.abs(Fo))),
                "theta_rel_err_fp32_fft": float(np.max(np.abs(Ta[:k + 1] - To) / To)),
                "F_rel_err_fp64": float(np.max(np.abs(Fb[:k + 1] - Fo) / np.abs(Fo))),
-               "theta_rel_err_fp64": float(np.max(np.abs(Tb[:k + 1] - To) / To))}
+               "theta_rel_err_fp64": float(np.max(np.abs(Tb[:k + 1] - To) / To)),
+               "plaquette_initial": P0, "plaquette_oracle_after": Pk,
+               "plaquette_err_fp32_fft": plaq["fp32_fft"] - Pk, "plaquette_err_fp64": plaq["fp64"] - Pk}
     out = {
         "metric": f"time to theta<=1e-15 at {L}^4 SU(3), FP32 transform (FP64 links/Delta/update/sums)",
         "value": round(a["seconds"], 4), "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
@@ -427,8 +458,26 @@ def bench_diff(args):
         gf.gf_functional_g_backward(fx.ctx, om, 1.0, d_om, d_U)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    fx.close()
+    # the autograd function end to end (functional-only context, reused)
+    from paper_1210_8018_amd.api import GaugeFunctional
+
+    Ug = U.clone().requires_grad_(True)
+    omg = om.clone().requires_grad_(True)
+    for _ in range(3):
+        GaugeFunctional.apply(Ug, omg).backward()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(n):
+        Ug.grad = None
+        omg.grad = None
+        Fa = GaugeFunctional.apply(Ug, omg)
+        Fa.backward()
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
     out = {"metric": "differentiable functional at 24^4: forward and backward time", "value": round((t1 - t0) / n * 1e3, 4),
-           "unit": "ms (forward)", "backward_ms": round((t2 - t1) / n * 1e3, 4), "n_gpus": 1, "higher_is_better": False,
+           "unit": "ms (forward)", "backward_ms": round((t2 - t1) / n * 1e3, 4),
+           "autograd_forward_backward_ms": round((t4 - t3) / n * 1e3, 4), "n_gpus": 1, "higher_is_better": False,
            "data": "synthetic", "dtype": "f64", "F": F,
            "config": {"workload": "24^4 links eps 0.3 seed 5, omega ~ N(0, 0.1^2) seed 6"}}
     print(json.dumps(out), flush=True)

@@ -100,14 +100,18 @@ size_t gf_workspace_bytes(const gf_params *params);
 /*
  * Create a context for one configuration and measure it: computes Delta,
  * F and theta of the given links (the first line of Alg. 1).
- * d_links: device links (layout above), updated in place by later calls.
+ * d_links: device links (layout above), updated in place by later calls;
+ * between calls they hold the current links. An iterating call starts from
+ * the last measurement: after changing the links outside the library, call
+ * gf_functional, which measures them again.
  * d_ws: device workspace of at least gf_workspace_bytes(params) bytes,
  * 256-byte aligned. stream: the hipStream_t all work is ordered on.
  */
 gf_status gf_init(gf_ctx *ctx, const gf_params *params, void *d_links, void *d_ws, size_t ws_bytes,
                   void *stream);
 
-/* F (Eq. 1 at g = 1) and theta (Eq. 4) of the current links; synchronises. */
+/* F (Eq. 1 at g = 1) and theta (Eq. 4) of the current links, measured
+ * anew (Delta recomputed too); synchronises. */
 gf_status gf_functional(gf_ctx ctx, double *F, double *theta);
 
 /*
@@ -130,9 +134,11 @@ gf_status gf_fix_until(gf_ctx ctx, double theta_eps, int64_t max_iter, int64_t *
                        double *theta);
 
 /*
- * (F, theta) after every update since gf_init: entry 0 is the initial
- * measurement, entry k the values after update k. Copies
- * min(cap, available) entries; *n receives the number available.
+ * The quantities Alg. 1 monitors (F of Eq. 1 at g = 1 and theta of Eq. 4)
+ * after every update since gf_init: entry 0 is the initial measurement,
+ * entry k the values after update k (a library addition: the paper only
+ * tests theta against eps). Copies min(cap, available) entries; *n receives
+ * the number available. GF_ERR_STATE on a batch context (gf_history_batch).
  */
 gf_status gf_history(gf_ctx ctx, int64_t cap, double *F_hist, double *theta_hist, int64_t *n);
 
@@ -152,7 +158,8 @@ gf_status gf_gauge(gf_ctx ctx, void *d_g);
 gf_status gf_apply_gauge(gf_ctx ctx, const void *d_g);
 
 /*
- * The context's 4D transform applied in place to nfields complex fields
+ * The context's 4D transform (the FFT steps of Alg. 1, done as 2D + 2D or 1D
+ * passes as in section 2.2) applied in place to nfields complex fields
  * d_fields[f*V + s] (complex128 if fft_prec = 0, complex64 if 1); sign -1
  * forward exp(-i p.x), +1 backward exp(+i p.x); unnormalised.
  */
@@ -176,14 +183,21 @@ gf_status gf_fft(gf_ctx ctx, void *d_fields, int32_t nfields, int32_t sign);
 gf_status gf_heatbath(gf_ctx ctx, double beta, int32_t n_sweeps, int32_t n_or, uint64_t seed, int64_t sweep0);
 
 /* Average plaquette (1/(18 V)) sum_x sum_{mu<nu} Re Tr U_mu(x) U_nu(x+mu)
- * U_mu^dag(x+nu) U_nu^dag(x) of the context's links; synchronises. */
+ * U_mu^dag(x+nu) U_nu^dag(x) of the context's links: the gauge-invariant
+ * observable of the Wilson action of section 3 (unchanged by Alg. 1, so also
+ * a check of the link update). Synchronises. */
 gf_status gf_plaquette(gf_ctx ctx, double *P);
 
 /*
- * Batches: n_cfg independent configurations of possibly different dims in
- * one context. Every kernel launch covers the tiles of every configuration
- * still iterating; each configuration has its own device-side stopping test.
- * params and d_links are arrays of n_cfg entries (n_cfg <= 64).
+ * Batches (a library addition; each configuration is fixed by Alg. 1 with
+ * its own stopping rule theta <= eps, section 1): n_cfg independent
+ * configurations of possibly different dims in one context. Every kernel
+ * launch covers the tiles of every configuration still iterating; each
+ * configuration has its own device-side stopping test. params and d_links
+ * are arrays of n_cfg entries (n_cfg <= 64); all params must share fft_prec,
+ * chunk, fft_schedule, link_prec and refine_theta (else
+ * gf_workspace_bytes_batch returns 0 and gf_init_batch GF_ERR_SHAPE). The
+ * workspace layout is as for single contexts, one region per configuration.
  */
 size_t gf_workspace_bytes_batch(int32_t n_cfg, const gf_params *params);
 gf_status gf_init_batch(gf_ctx *ctx, int32_t n_cfg, const gf_params *params, void *const *d_links,
@@ -260,9 +274,10 @@ const char *gf_strerror(gf_status status);
 const char *gf_last_error(gf_ctx ctx);
 
 /*
- * Per-kernel timing. With timing on, iterations are launched one kernel at
- * a time (no graph) and every launch is bracketed by hipEvents on the
- * context's stream; the accumulated time per kernel is readable below.
+ * Per-kernel timing (a library addition, for measurement). With timing on,
+ * iterations are launched one kernel at a time (no graph) and every launch
+ * is bracketed by hipEvents on the context's stream; the accumulated time
+ * per kernel is readable below.
  */
 gf_status gf_set_timing(gf_ctx ctx, int32_t on);
 int32_t gf_kernel_count(gf_ctx ctx);
@@ -271,7 +286,8 @@ const char *gf_kernel_name(gf_ctx ctx, int32_t k);
 gf_status gf_kernel_time(gf_ctx ctx, int32_t k, double *total_ms, int64_t *launches);
 gf_status gf_reset_timing(gf_ctx ctx);
 
-/* The transform schedule in use (1, 2 or 3; see gf_params.fft_schedule). */
+/* The transform schedule in use (1, 2 or 3; see gf_params.fft_schedule;
+ * the 2D + 2D grouping of section 2.2 is schedule 3). */
 int32_t gf_fft_schedule(gf_ctx ctx);
 
 #ifdef __cplusplus

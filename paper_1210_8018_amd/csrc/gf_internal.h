@@ -97,7 +97,7 @@ struct Cfg {
     int ztP, nzt;         // zt pass: P consecutive xy-sites per tile, nzt tiles per field
     int xyPad;            // LDS elements added to every x-row of an xy tile (bank spreading)
     int ztPad;            // LDS elements added to every t-plane of a zt tile
-    int zt_reg;           // the scaled (z, t) pass runs in k_fft_zt_reg (Lz = Lt = 32, ztP = 2)
+    int zt_reg;           // the scaled (z, t) pass runs in k_fft_zt_reg (Lz = Lt = 32, ztP = 2 or 4)
     int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 32, xyQ = 2)
 };
 
@@ -131,6 +131,7 @@ struct Launch {
     int zt_tw2, zt_tw_total;       // same for the zt pass
     int zt_reg_any, zt_lds_any;    // scaled zt pass: some configuration in k_fft_zt_reg / in k_fft_zt
     int zt_reg_groups;             // work-groups per tile of k_fft_zt_reg (1, 2 or 4: fields split among them)
+    int zt_reg_p;                  // xy-sites per tile of k_fft_zt_reg (2 or 4)
     int xy_reg_any, xy_lds_any;    // iteration's xy passes: some configuration in the register / LDS-staged ones
     int xy_reg_groups;             // work-groups per tile of the register xy passes
     int max_lds_elems;    // 1D passes: largest P * L
@@ -168,6 +169,8 @@ enum : int { kLinksBuffers = 0, kLinksFromCaller = 1, kLinksToCaller = 2 };
 hipError_t launch_update_delta(const Launch &L, int link_io);
 hipError_t launch_pack_links(const Launch &L);
 hipError_t launch_momentum_table(const Launch &L);
+// reads every configuration's two-row link buffers (cache eviction before a timed pass)
+hipError_t launch_touch_links(const Launch &L);
 hipError_t launch_heatbath_sweep(const Launch &L, int V, int mode, double beta, uint64_t seed, long long n);
 hipError_t launch_plaquette(const Launch &L, int nblk, double *out);
 hipError_t launch_unpack_links(const Launch &L);

@@ -268,17 +268,18 @@ struct Tiles {
     int xy_target = 1024, xy_ept = 4;
     int zt_target = 4096, zt_ept = 8;
     int zt_reg = 2;
+    int zt_reg_p = 4;  // xy-sites per tile of the register (z, t) pass (2, 4 or 8)
     int xy_reg = 1;
     bool operator==(const Tiles &o) const
     {
         return xy_target == o.xy_target && xy_ept == o.xy_ept && zt_target == o.zt_target && zt_ept == o.zt_ept &&
-               zt_reg == o.zt_reg && xy_reg == o.xy_reg;
+               zt_reg == o.zt_reg && zt_reg_p == o.zt_reg_p && xy_reg == o.xy_reg;
     }
 };
 
 // Whether a configuration's scaled (z, t) pass can run in k_fft_zt_reg, and
 // its (x, y) passes in k_fft_xy_reg / k_fft_xy_inv_reg (tiles of two planes).
-bool zt_reg_fits(const Cfg &C) { return C.dims[2] == 32 && C.dims[3] == 32 && C.V2 % 2 == 0; }
+bool zt_reg_fits(const Cfg &C, int P) { return C.dims[2] == 32 && C.dims[3] == 32 && C.V2 % P == 0; }
 bool xy_reg_fits(const Cfg &C) { return C.dims[0] == 32 && C.dims[1] == 32 && (C.dims[2] * C.dims[3]) % 2 == 0; }
 
 struct gf_ctx_s {
@@ -777,8 +778,11 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
         if (C.xy_reg) C.xyQ = 2;  // the register passes' tile: 2 planes
         C.nxy = xy_feasible(C.dims) ? (C.dims[2] * C.dims[3]) / C.xyQ : 0;
         C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims, tl.zt_target) : 1;
-        C.zt_reg = (sched == kSchedXYZT && tl.zt_reg && zt_reg_fits(C)) ? 1 : 0;
-        if (C.zt_reg) C.ztP = 2;  // the register pass's tile: 2 xy-sites
+        // the register pass's tile: zt_reg_p xy-sites (one width per
+        // launch); a configuration whose Lx Ly it does not divide takes the
+        // LDS-staged pass
+        C.zt_reg = (sched == kSchedXYZT && tl.zt_reg && zt_reg_fits(C, tl.zt_reg_p)) ? 1 : 0;
+        if (C.zt_reg) C.ztP = tl.zt_reg_p;
         C.nzt = zt_feasible(C.dims) ? C.V2 / C.ztP : 0;
         // bank-spreading pads, kept inside the 1/8 slack of the LDS tile
         const int xycap = C.xyQ * C.V2 <= 1024 ? 1024 : (C.xyQ * C.V2 <= 2048 ? 2048 : 4096);
@@ -814,6 +818,7 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
     }
     c->L.zt_reg_any = c->L.zt_lds_any = 0;
     c->L.zt_reg_groups = tl.zt_reg > 0 ? tl.zt_reg : 1;
+    c->L.zt_reg_p = tl.zt_reg_p;
     c->L.xy_reg_any = c->L.xy_lds_any = 0;
     c->L.xy_reg_groups = tl.xy_reg > 0 ? tl.xy_reg : 1;
     for (int k = 0; k < c->ncfg; ++k) {
@@ -848,6 +853,8 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
     HIPCHK(c, hipMemcpyAsync(c->d_cfgs, c->cfg.data(), sizeof(Cfg) * c->ncfg, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_batch, &c->bmap, sizeof(Batch), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_batch_act, &c->bact, sizeof(Batch), hipMemcpyHostToDevice, c->stream));
+    // the K(p) table's layout follows the (z, t) pass chosen
+    HIPCHK(c, launch_momentum_table(c->L));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
     return GF_OK;
@@ -923,8 +930,9 @@ std::vector<TuneEntry> &tune_cache()
             if (f) {
                 char key[4096];
                 TuneEntry e;
-                while (fscanf(f, "%4095s %d %d %d %d %d %d %d", key, &e.sched, &e.tiles.xy_target, &e.tiles.xy_ept,
-                              &e.tiles.zt_target, &e.tiles.zt_ept, &e.tiles.zt_reg, &e.tiles.xy_reg) == 8) {
+                while (fscanf(f, "%4095s %d %d %d %d %d %d %d %d", key, &e.sched, &e.tiles.xy_target,
+                              &e.tiles.xy_ept, &e.tiles.zt_target, &e.tiles.zt_ept, &e.tiles.zt_reg, &e.tiles.zt_reg_p,
+                              &e.tiles.xy_reg) == 9) {
                     e.key = key;
                     cache.push_back(e);
                 }
@@ -940,7 +948,7 @@ bool valid_tiles(const Tiles &t)
     auto ok_target = [](int v) { return v == 1024 || v == 2048 || v == 4096; };
     return ok_target(t.xy_target) && ok_target(t.zt_target) && (t.xy_ept == 4 || t.xy_ept == 8) &&
            (t.zt_ept == 4 || t.zt_ept == 8) && (t.zt_reg == 0 || t.zt_reg == 1 || t.zt_reg == 2 || t.zt_reg == 4) &&
-           (t.xy_reg == 0 || t.xy_reg == 1 || t.xy_reg == 2 || t.xy_reg == 4);
+           (t.xy_reg == 0 || t.xy_reg == 1 || t.xy_reg == 2 || t.xy_reg == 4) && (t.zt_reg_p == 2 || t.zt_reg_p == 4 || t.zt_reg_p == 8);
 }
 
 // Tile choices of a fixed schedule: defaults, overridden by GF_XY_TARGET,
@@ -958,6 +966,7 @@ Tiles env_tiles()
     rd("GF_ZT_EPT", t.zt_ept);
     rd("GF_ZT_REG", t.zt_reg);
     rd("GF_XY_REG", t.xy_reg);
+    rd("GF_ZT_REG_P", t.zt_reg_p);
     return valid_tiles(t) ? t : Tiles();
 }
 
@@ -981,7 +990,7 @@ gf_status choose_schedule(gf_ctx c, int requested)
     std::vector<Cand> cands = {{kSched1D, Tiles()}};
     bool any_zreg = false, any_xreg = false;
     for (int k = 0; k < c->ncfg; ++k) {
-        any_zreg = any_zreg || zt_reg_fits(c->cfg[k]);
+        any_zreg = any_zreg || zt_reg_fits(c->cfg[k], 2);
         any_xreg = any_xreg || xy_reg_fits(c->cfg[k]);
     }
     // (x, y) choices: LDS tiles (target, elements per work-item), or the
@@ -1012,11 +1021,13 @@ gf_status choose_schedule(gf_ctx c, int requested)
             zs.push_back(t);
         }
     if (any_zreg)
-        for (int g : {1, 2, 4}) {
-            Tiles t;
-            t.zt_reg = g;
-            zs.push_back(t);
-        }
+        for (int P : {2, 4, 8})
+            for (int g : {1, 2, 4}) {
+                Tiles t;
+                t.zt_reg = g;
+                t.zt_reg_p = P;
+                zs.push_back(t);
+            }
     for (const Tiles &x : xs) {
         Tiles t = x;
         t.zt_reg = 0;
@@ -1033,18 +1044,26 @@ gf_status choose_schedule(gf_ctx c, int requested)
     if (!e0 || !e1) return GF_ERR_HIP;
     const bool timing = c->timing;
     c->timing = false;
-    // time of `reps` transform passes (after one warm-up pass) of a candidate
+    // mean time of `reps` transform passes (after one warm-up pass) of a
+    // candidate, each after a read of the link buffers: in an iteration the
+    // fused pass streams them between the transform passes, so the fields
+    // are not in L2 or the infinity cache when a transform pass starts
     auto time_cand = [&](const Cand &cd, int reps, double &ms_out) -> gf_status {
         gf_status st = apply_schedule(c, cd.sched, cd.tiles);
         if (st != GF_OK) return st;
         HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, nullptr));
-        HIPCHK(c, hipEventRecord(e0, c->stream));
-        for (int r = 0; r < reps; ++r) HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, nullptr));
-        HIPCHK(c, hipEventRecord(e1, c->stream));
-        HIPCHK(c, hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-        ms_out = ms / reps;
+        double total = 0.0;
+        for (int r = 0; r < reps; ++r) {
+            HIPCHK(c, launch_touch_links(c->L));
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            HIPCHK(c, enqueue_gauge_steps(c, c->stream, 0, nullptr));
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            total += ms;
+        }
+        ms_out = total / reps;
         return GF_OK;
     };
     // first pass: every candidate briefly; then the four fastest twice more
@@ -1084,8 +1103,9 @@ gf_status choose_schedule(gf_ctx c, int requested)
     if (path) {
         FILE *f = fopen(path, "a");
         if (f) {
-            fprintf(f, "%s %d %d %d %d %d %d %d\n", key.c_str(), pick.sched, pick.tiles.xy_target, pick.tiles.xy_ept,
-                    pick.tiles.zt_target, pick.tiles.zt_ept, pick.tiles.zt_reg, pick.tiles.xy_reg);
+            fprintf(f, "%s %d %d %d %d %d %d %d %d\n", key.c_str(), pick.sched, pick.tiles.xy_target,
+                    pick.tiles.xy_ept, pick.tiles.zt_target, pick.tiles.zt_ept, pick.tiles.zt_reg, pick.tiles.zt_reg_p,
+                    pick.tiles.xy_reg);
             fclose(f);
         }
     }
@@ -1222,7 +1242,6 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
                                  c->stream));
     }
     HIPCHK(c, set_lds_limits());
-    HIPCHK(c, launch_momentum_table(c->L));
     HIPCHK(c, launch_arm(c->L, ncfg, 0.0, 0, 1));
     HIPCHK(c, enqueue_measure(c));
     gf_status st = read_ctrl(c);

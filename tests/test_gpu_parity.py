@@ -32,10 +32,11 @@ EPS = 1e-15
 # (256); t extents 2, 4, 16, 256 (last radix 2 or 4: the t-axis centre stage
 # with 1, 2 or 3 stages) and 8 (last radix 8: separate scaling step); 48 x 48
 # planes (a general-extent tile filling 56 % of its 4096-element capacity) in
-# the xy and in the zt pass
+# the xy and in the zt pass; 64 x 64 planes (the 64^4 workload's, filling
+# the 4096-element tile exactly)
 SHAPES = [(8, 8, 8, 8), (12, 8, 6, 4), (6, 6, 6, 2), (2, 2, 2, 2), (24, 4, 2, 6), (4, 12, 4, 8),
           (27, 2, 4, 6), (3, 9, 2, 4), (256, 4, 2, 2), (2, 2, 2, 256), (4, 4, 4, 4), (4, 2, 4, 16),
-          (48, 48, 2, 2), (2, 2, 48, 48)]
+          (48, 48, 2, 2), (2, 2, 48, 48), (64, 64, 2, 2), (2, 2, 64, 64)]
 
 
 def dev(a):
@@ -135,7 +136,8 @@ def check_2d_passes(dims, prec):
             assert np.max(np.abs(got[k] - ref)) < tol * np.max(np.abs(ref)), (sign, k)
 
 
-@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (12, 8, 6, 4), (24, 4, 2, 6), (4, 12, 4, 8), (16, 8, 4, 32)])
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (12, 8, 6, 4), (24, 4, 2, 6), (4, 12, 4, 8), (16, 8, 4, 32),
+                                  (64, 64, 2, 2), (2, 2, 64, 64)])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("tiles", TILE_VARIANTS)
 def test_2d_tile_variants_match_oracle(monkeypatch, dims, prec, tiles):
@@ -561,19 +563,23 @@ def test_single_precision_storage_batch_equals_single(monkeypatch):
 
 # ---------------------------------------------------------------- 32 x 32 (z, t) planes
 
-ZT32_SHAPES = [(2, 2, 32, 32), (4, 2, 32, 32), (6, 4, 32, 32), (8, 8, 32, 32)]
+ZT32_SHAPES = [(2, 2, 32, 32), (4, 2, 32, 32), (6, 4, 32, 32), (8, 8, 32, 32), (16, 2, 32, 32)]
 
 
 @pytest.mark.parametrize("dims", ZT32_SHAPES)
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("reg", ["1", "2", "4", "0"])
+@pytest.mark.parametrize("reg", ["1", "2", "4", "0", "1/4", "2/8", "4/8"])
 def test_zt_register_pass_matches_oracle(monkeypatch, dims, prec, reg):
     """The scaled (z, t) pass of 32 x 32 planes with its radix stages in
-    registers (GF_ZT_REG = work-groups per tile, 1, 2 or 4) and LDS-staged
-    (GF_ZT_REG=0): the
+    registers (GF_ZT_REG = work-groups per tile, 1, 2 or 4; after the slash
+    GF_ZT_REG_P = xy-sites per tile, 2, 4 or 8, where it divides Lx Ly) and
+    LDS-staged (GF_ZT_REG=0): the
     gauge vector of the xy + zt schedule against the oracle; 6 x 4 xy-planes
     take the general-extent xy instances beside it."""
-    monkeypatch.setenv("GF_ZT_REG", reg)
+    g, _, P = reg.partition("/")
+    monkeypatch.setenv("GF_ZT_REG", g)
+    if P:
+        monkeypatch.setenv("GF_ZT_REG_P", P)
     U = random_links(dims, 0.4, 47)
     fx = GaugeFixer(dev(U), fft_prec=prec, fft_schedule=3)
     g = host(fx.gauge())
@@ -581,8 +587,10 @@ def test_zt_register_pass_matches_oracle(monkeypatch, dims, prec, reg):
     assert np.max(np.abs(g - gref)) < (fp32_gauge_tolerance(dims) if prec else 1e-13)
 
 
-@pytest.mark.parametrize("dims,seed", [((4, 2, 32, 32), 48), ((6, 4, 32, 32), 49)])
-def test_zt_register_pass_trajectory(dims, seed):
+@pytest.mark.parametrize("dims,seed,P", [((4, 2, 32, 32), 48, "2"), ((6, 4, 32, 32), 49, "4"),
+                                         ((16, 2, 32, 32), 50, "8")])
+def test_zt_register_pass_trajectory(monkeypatch, dims, seed, P):
+    monkeypatch.setenv("GF_ZT_REG_P", P)
     U = random_links(dims, 0.3, seed)
     n_ref, _, Fr, Tr, spread = oracle_reference(dims, U, max_iter=5000)
     fx = GaugeFixer(dev(U), fft_schedule=3)
