@@ -26,7 +26,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # Algorithmic HBM bytes per site per launch of each kernel, for FP64 and
 # FP32 transform fields (c = bytes per complex transform element):
 #   divergence: read 4 links (576) + write 4 packed fields (4c)
-#   transform pass: read + write 4 fields (8c)
+#   transform pass: read + write 4 fields (8c); the (z, t) pass with the
+#     scaling also reads K(p), one real of the transform precision (c/2)
 #   gauge: read 4 fields (4c) + write g (144); the inverse (x, y) pass, which
 #     ends the transform, writes the 4 filtered fields (4c) for the fused pass
 #   link update: read 4 links (576) + g(x) (144) + write 4 links (576);
@@ -43,6 +44,8 @@ def kernel_bytes_per_site(name: str, c: int) -> float:
         return 8 * c
     if name.startswith("delta"):
         return 576 + 4 * c
+    if name == "fft_zt_scale":  # (z, t) forward, K(p) (one real of the transform precision), backward
+        return 8 * c + c // 2
     if name.startswith("fft"):
         return 8 * c
     if name.startswith("gauge"):

@@ -1740,7 +1740,8 @@ __global__ __launch_bounds__(kSiteBlock) void k_update(const Cfg *__restrict__ c
 // from one buffer and the new ones written to the other, so no block ever
 // reads a link another block has already replaced. U'_t(x - t) is the U'_t(x)
 // of the previous t-slice, kept in registers (recomputed once at the first
-// slice of a block). Also writes the packed transform fields and the
+// slice of a block); U'_t(x) itself is formed one slice late, once g(x + t)
+// is read as the next slice's own g. Also writes the packed transform fields and the
 // per-block sums for F (of the new links) and theta. RU: the variant for
 // iterations that also project the new links to SU(3) (reunit_every > 0);
 // each variant returns at once on the other iterations.
@@ -1881,78 +1882,122 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
     sb[1] = inside ? block_slot(C, b3, back3[1], x, yb, z) : -1;
     const int t0 = tc * C.tch;
     dd fs = {0.0, 0.0}, ts = {0.0, 0.0};
-    M3 gx;
-    AH utp;  // U'_t(x - t) - h.c.
-    if (inside) {
-        gx = fused_gauge<T2, S2>(C, s3 + V3 * t0);
-        const int sp = s3 + V3 * ((t0 == 0) ? Lt - 1 : t0 - 1);
-        M3 w = m3_mul_mul_dag_rows(fused_gauge<T2, S2>(C, sp), m3_load12s(Uo + kOs * 3 * V, V, sp), gx);
-        if (RU) m3_reunit(w);
-        utp = ah_of(w);
-    }
+    // Slice t forms g(x, t) and completes the site (x, t - 1): its forward
+    // t-link needs g(x, t), so it is formed one slice late, and the slice's
+    // other links are formed while g(x, t) and the neighbours' g(x +- z, t)
+    // are read. Every block then reads a slice's filtered fields in the same
+    // slice of its walk, as its z-neighbours and the blocks of its edge rows
+    // read them, instead of one slice apart (the fields of slice t + 1 were
+    // the owner's g(x + t) of slice t).
+    M3 gp;   // g(x, t - 1)
+    AH dc;   // D(x, t - 1) without its -(U'_t(x, t - 1) - h.c.)
+    AH utp;  // U'_t(x, t - 1) - h.c., the backward t-link of (x, t)
+    if (inside) gp = fused_gauge<T2, S2>(C, s3 + V3 * ((t0 == 0) ? Lt - 1 : t0 - 1));
     T2 *__restrict__ f = (T2 *)C.fields;
-    for (int t = t0; t < t0 + C.tch; ++t) {
-        const int s = s3 + V3 * t;
+    for (int t = t0; t <= t0 + C.tch; ++t) {
+        const int s = s3 + V3 * ((t == Lt) ? 0 : t);
+        const int sp = s3 + V3 * ((t == 0) ? Lt - 1 : t - 1);
+        M3 gx;
+        double fsum = 0.0;
         if (inside) {
+            gx = fused_gauge<T2, S2>(C, s);
+            // U'_t(x, t - 1); at the walk's first slice the owner of (x, t0 - 1)
+            // stores it, this block only needs its anti-hermitian part
+            const M3 u = (t == t0) ? m3_load12s(Uo + kOs * 3 * V, V, sp) : m3_load12s_stream(Uo + kOs * 3 * V, V, sp);
+            M3 w = m3_mul_mul_dag_rows(gp, u, gx);
+            if (RU) m3_reunit(w);
+            utp = ah_of(w);
+            if (t > t0) {
+                store_new_link<S2, DST>(Un + kNs * 3 * V, V, sp, w);
+                fsum += w.e[0].x + w.e[4].x + w.e[8].x;
+                AH D = dc;
+                ah_acc(D, utp, -1.0);
+                // Delta = A - Tr(A)/3 with A = D - D^dag
+                const double tr3 = (D.d0 + D.d1 + D.d2) * (1.0 / 3.0);
+                const double e0 = D.d0 - tr3, e1 = D.d1 - tr3, e2 = D.d2 - tr3;
+                const double tsum =
+                    2.0 * (cnorm2(D.o01) + cnorm2(D.o02) + cnorm2(D.o12)) + e0 * e0 + e1 * e1 + e2 * e2;
+                T2 fv;
+                fv.x = D.o01.x;
+                fv.y = D.o01.y;
+                st_stream(f + sp, fv);
+                fv.x = D.o02.x;
+                fv.y = D.o02.y;
+                st_stream(f + (size_t)V + sp, fv);
+                fv.x = D.o12.x;
+                fv.y = D.o12.y;
+                st_stream(f + (size_t)2 * V + sp, fv);
+                fv.x = e0;
+                fv.y = e1;
+                st_stream(f + (size_t)3 * V + sp, fv);
+                ts = dd_add(ts, dd{tsum, 0.0});
+            }
+        }
+        if (t == t0 + C.tch) {  // the walk's last slice: (x, t) belongs to the next block in t
+            if (inside) fs = dd_add(fs, dd{fsum, 0.0});
+            break;
+        }
+        if (inside) {
+            // the z-links first: they need no neighbour from LDS, so their
+            // loads are in flight with the t-link's before the first barrier
+            dc = utp;
+            {
+                // U_z(x) is the backward neighbour of the next work-group in z,
+                // which reads it in the same slice
+                const M3 gf = fused_gauge<T2, S2>(C, fwd3[2] + V3 * t);
+                M3 w = m3_mul_mul_dag_rows(gx, m3_load12s(Uo + (size_t)2 * kOs * V, V, s), gf);
+                if (RU) m3_reunit(w);
+                store_new_link<S2, DST>(Un + (size_t)2 * kNs * V, V, s, w);
+                fsum += w.e[0].x + w.e[4].x + w.e[8].x;
+                ah_acc(dc, ah_of(w), -1.0);
+            }
+            {
+                const int sbk = back3[2] + V3 * t;
+                M3 wb = m3_mul_mul_dag_rows(fused_gauge<T2, S2>(C, sbk), m3_load12s(Uo + (size_t)2 * kOs * V, V, sbk), gx);
+                if (RU) m3_reunit(wb);
+                ah_acc(dc, ah_of(wb), 1.0);
+            }
 #pragma unroll
             for (int k = 0; k < 6; ++k) sg[k][tid] = gx.e[k];
         }
         __syncthreads();
-        AH D;
-        M3 gn;
-        double fsum = 0.0;
         if (inside) {
-            D = utp;
 #pragma unroll
-            for (int mu = 0; mu < 3; ++mu) {
+            for (int mu = 0; mu < 2; ++mu) {
                 M3 gf;
-                if (mu < 2 && sf[mu] >= 0) {
+                if (sf[mu] >= 0) {
 #pragma unroll
                     for (int k = 0; k < 6; ++k) gf.e[k] = sg[k][sf[mu]];
                     m3_row2(gf);
                 } else {
                     gf = fused_gauge<T2, S2>(C, fwd3[mu] + V3 * t);
                 }
-                // U_x(x) and U_y(x) are read again only at the block's edge
-                // rows; U_z(x) is the backward neighbour of the next
-                // work-group in z, which reads it in the same slice
-                const size_t off = (size_t)mu * kOs * V;
-                const M3 u = (mu < 2) ? m3_load12s_stream(Uo + off, V, s) : m3_load12s(Uo + off, V, s);
+                // U_x(x) and U_y(x) are read again only at the block's edge rows
+                const M3 u = m3_load12s_stream(Uo + (size_t)mu * kOs * V, V, s);
                 M3 w = m3_mul_mul_dag_rows(gx, u, gf);
                 if (RU) m3_reunit(w);
                 store_new_link<S2, DST>(Un + (size_t)mu * kNs * V, V, s, w);
                 fsum += w.e[0].x + w.e[4].x + w.e[8].x;
                 const AH a = ah_of(w);
-                ah_acc(D, a, -1.0);
-                if (mu < 2) {
-                    sa[mu][0][tid] = a.o01.x;
-                    sa[mu][1][tid] = a.o01.y;
-                    sa[mu][2][tid] = a.o02.x;
-                    sa[mu][3][tid] = a.o02.y;
-                    sa[mu][4][tid] = a.o12.x;
-                    sa[mu][5][tid] = a.o12.y;
-                    sa[mu][6][tid] = a.d0;
-                    sa[mu][7][tid] = a.d1;
-                    sa[mu][8][tid] = a.d2;
-                }
+                ah_acc(dc, a, -1.0);
+                sa[mu][0][tid] = a.o01.x;
+                sa[mu][1][tid] = a.o01.y;
+                sa[mu][2][tid] = a.o02.x;
+                sa[mu][3][tid] = a.o02.y;
+                sa[mu][4][tid] = a.o12.x;
+                sa[mu][5][tid] = a.o12.y;
+                sa[mu][6][tid] = a.d0;
+                sa[mu][7][tid] = a.d1;
+                sa[mu][8][tid] = a.d2;
             }
-            {
-                const int tn = (t + 1 == Lt) ? 0 : t + 1;
-                gn = fused_gauge<T2, S2>(C, s3 + V3 * tn);
-                M3 w = m3_mul_mul_dag_rows(gx, m3_load12s_stream(Uo + kOs * 3 * V, V, s), gn);
-                if (RU) m3_reunit(w);
-                store_new_link<S2, DST>(Un + kNs * 3 * V, V, s, w);
-                fsum += w.e[0].x + w.e[4].x + w.e[8].x;
-                utp = ah_of(w);
-                ah_acc(D, utp, -1.0);
-            }
+            fs = dd_add(fs, dd{fsum, 0.0});
         }
         __syncthreads();
         if (inside) {
 #pragma unroll
-            for (int nu = 0; nu < 3; ++nu) {
+            for (int nu = 0; nu < 2; ++nu) {
                 AH a;
-                if (nu < 2 && sb[nu] >= 0) {
+                if (sb[nu] >= 0) {
                     const int o = sb[nu];
                     a.o01 = make_double2(sa[nu][0][o], sa[nu][1][o]);
                     a.o02 = make_double2(sa[nu][2][o], sa[nu][3][o]);
@@ -1966,28 +2011,9 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
                     if (RU) m3_reunit(wb);
                     a = ah_of(wb);
                 }
-                ah_acc(D, a, 1.0);
+                ah_acc(dc, a, 1.0);
             }
-            // Delta = A - Tr(A)/3 with A = D - D^dag
-            const double tr3 = (D.d0 + D.d1 + D.d2) * (1.0 / 3.0);
-            const double e0 = D.d0 - tr3, e1 = D.d1 - tr3, e2 = D.d2 - tr3;
-            const double tsum = 2.0 * (cnorm2(D.o01) + cnorm2(D.o02) + cnorm2(D.o12)) + e0 * e0 + e1 * e1 + e2 * e2;
-            T2 fv;
-            fv.x = D.o01.x;
-            fv.y = D.o01.y;
-            st_stream(f + s, fv);
-            fv.x = D.o02.x;
-            fv.y = D.o02.y;
-            st_stream(f + (size_t)V + s, fv);
-            fv.x = D.o12.x;
-            fv.y = D.o12.y;
-            st_stream(f + (size_t)2 * V + s, fv);
-            fv.x = e0;
-            fv.y = e1;
-            st_stream(f + (size_t)3 * V + s, fv);
-            fs = dd_add(fs, dd{fsum, 0.0});
-            ts = dd_add(ts, dd{tsum, 0.0});
-            gx = gn;
+            gp = gx;
         }
     }
     block_sum2(fs, ts, red);

@@ -1246,7 +1246,12 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
     HIPCHK(c, enqueue_measure(c));
     gf_status st = read_ctrl(c);
     if (st != GF_OK) return st;
-    return choose_schedule(c, params[0].fft_schedule);
+    if ((st = choose_schedule(c, params[0].fft_schedule)) != GF_OK) return st;
+    // the chunk graph of FP64 link storage is captured and instantiated here,
+    // not inside the first call that runs a whole chunk (about 0.3 ms, more
+    // than an iteration)
+    if (!c->noalloc && c->link_prec == 0) return build_graph(c);
+    return GF_OK;
 }
 
 // Workspace of a functional-only context: the header, g [3][3][V] and the

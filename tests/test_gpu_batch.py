@@ -61,7 +61,7 @@ def test_batch_members_match_oracle(oracle_runs, prec):
         Uf = host(Ubs[k])
         if prec == 0:
             assert abs(its[k] - n_ref) <= max(0, int(0.01 * n_ref)), (dims, its[k], n_ref)
-            compare_trajectory(Fh, Th, Fr, Tr, spread, f"batch member {dims}")
+            compare_trajectory(Fh, Th, Fr, Tr, spread, dims, f"batch member {dims}")
             assert abs(Fs[k] - Fr[-1]) <= 1e-10 * Fr[-1]
             assert np.max(np.abs(Uf.reshape(U_ref.shape) - U_ref)) < 1e-11
         else:
