@@ -99,6 +99,7 @@ struct Cfg {
     int ztPad;            // LDS elements added to every t-plane of a zt tile
     int zt_reg;           // the scaled (z, t) pass runs in k_fft_zt_reg (Lz = Lt = 32, ztP = 2 or 4)
     int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 32, xyQ = 2)
+    int line_reg;         // the 1D z and t passes run in k_fft_line64 (Lz = Lt = 64, Lx Ly a multiple of 16)
 };
 
 // Block-to-configuration maps for every launch shape of a batch: entry e
@@ -111,6 +112,7 @@ struct Batch {
     int off_fft[4][kMaxCfg + 1];
     int off_xy[kMaxCfg + 1];
     int off_zt[kMaxCfg + 1];
+    int off_line[kMaxCfg + 1];  // k_fft_line64 work-groups (configurations with line_reg)
 };
 
 struct Launch {
@@ -134,6 +136,7 @@ struct Launch {
     int zt_reg_p;                  // xy-sites per tile of k_fft_zt_reg (2 or 4)
     int xy_reg_any, xy_lds_any;    // iteration's xy passes: some configuration in the register / LDS-staged ones
     int xy_reg_groups;             // work-groups per tile of the register xy passes
+    int total_line;                // work-groups of k_fft_line64 (0: no configuration with line_reg)
     int max_lds_elems;    // 1D passes: largest P * L
     int fp32;             // transform precision
     int fused;            // iterations use the fused update + divergence kernel

@@ -107,7 +107,10 @@ int plan_tile(const int dims[4], int tile[3], int ntile[3])
 // at or above the target, the first whose last round of `resident` blocks
 // (those the device holds at once) is at least 90 % full is taken, else the
 // fullest: at 48^4 the 3456 blocks of 6 slices (96 %) run the fused pass 7 %
-// faster than the 1296 of 16 slices (84 %).
+// faster than the 1296 of 16 slices (84 %). A walk is at most 8 slices: at
+// 64^4 the 8192 blocks of 8 slices run it 2.7 % faster than the 1024 that
+// walk all 64.
+constexpr int kMaxTchunk = 8;
 int plan_tchunk(const int dims[4], int nb3, int target, int resident)
 {
     const char *env = getenv("GF_TCHUNK");
@@ -119,7 +122,7 @@ int plan_tchunk(const int dims[4], int nb3, int target, int resident)
     double best_fill = -1.0;
     for (int nT = 1; nT <= dims[3]; ++nT) {
         const long long nb = (long long)nb3 * nT;
-        if (dims[3] % nT || nb < target) continue;
+        if (dims[3] % nT || nb < target || dims[3] / nT > kMaxTchunk) continue;
         const long long rounds = (nb + resident - 1) / resident;
         const double fill = (double)nb / (double)(rounds * resident);
         if (fill >= 0.9) return dims[3] / nT;
@@ -270,10 +273,11 @@ struct Tiles {
     int zt_reg = 2;
     int zt_reg_p = 4;  // xy-sites per tile of the register (z, t) pass (2, 4 or 8)
     int xy_reg = 1;
+    int line_reg = 1;  // 1D z and t passes of 64-point lines in k_fft_line64
     bool operator==(const Tiles &o) const
     {
         return xy_target == o.xy_target && xy_ept == o.xy_ept && zt_target == o.zt_target && zt_ept == o.zt_ept &&
-               zt_reg == o.zt_reg && zt_reg_p == o.zt_reg_p && xy_reg == o.xy_reg;
+               zt_reg == o.zt_reg && zt_reg_p == o.zt_reg_p && xy_reg == o.xy_reg && line_reg == o.line_reg;
     }
 };
 
@@ -281,6 +285,8 @@ struct Tiles {
 // its (x, y) passes in k_fft_xy_reg / k_fft_xy_inv_reg (tiles of two planes).
 bool zt_reg_fits(const Cfg &C, int P) { return C.dims[2] == 32 && C.dims[3] == 32 && C.V2 % P == 0; }
 bool xy_reg_fits(const Cfg &C) { return C.dims[0] == 32 && C.dims[1] == 32 && (C.dims[2] * C.dims[3]) % 2 == 0; }
+// and its 1D z and t passes in k_fft_line64 (16 xy-sites per row of a wave)
+bool line_reg_fits(const Cfg &C) { return C.dims[2] == 64 && C.dims[3] == 64 && C.V2 % 16 == 0; }
 
 struct gf_ctx_s {
     int ncfg = 0;
@@ -743,7 +749,11 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
         b.idx[e] = list[e];
         b.off_site[e + 1] = b.off_site[e] + C.nblk_site;
         b.off_march[e + 1] = b.off_march[e] + C.nblk_march;
-        for (int mu = 0; mu < 4; ++mu) b.off_fft[mu][e + 1] = b.off_fft[mu][e] + C.ax[mu].ntile;
+        // the z and t passes of a configuration with line_reg run in k_fft_line64:
+        // 16 xy-sites times 4 lines per work-group
+        for (int mu = 0; mu < 4; ++mu)
+            b.off_fft[mu][e + 1] = b.off_fft[mu][e] + ((mu >= 2 && C.line_reg) ? 0 : C.ax[mu].ntile);
+        b.off_line[e + 1] = b.off_line[e] + (C.line_reg ? (C.V2 / 16) * (C.dims[3] / 4) : 0);
         b.off_xy[e + 1] = b.off_xy[e] + C.nxy;
         b.off_zt[e + 1] = b.off_zt[e] + C.nzt;
     }
@@ -751,6 +761,7 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
     L.total_march_blocks = b.off_march[b.n];
     for (int mu = 0; mu < 4; ++mu) L.total_fft_tiles[mu] = b.off_fft[mu][b.n];
     L.total_xy_tiles = b.off_xy[b.n];
+    L.total_line = b.off_line[b.n];
     L.total_zt_tiles = b.off_zt[b.n];
     L.ncfg = b.n;
 }
@@ -775,6 +786,9 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
         Cfg &C = c->cfg[k];
         C.xyQ = xy_feasible(C.dims) ? plan_xyQ(C.dims, tl.xy_target) : 1;
         C.xy_reg = ((sched == kSchedXYZT || sched == kSchedXY1D) && tl.xy_reg && xy_reg_fits(C)) ? 1 : 0;
+        // every 1D z and t pass (those of schedules 1 and 2, and the plain
+        // transform calls)
+        C.line_reg = (tl.line_reg && line_reg_fits(C)) ? 1 : 0;
         if (C.xy_reg) C.xyQ = 2;  // the register passes' tile: 2 planes
         C.nxy = xy_feasible(C.dims) ? (C.dims[2] * C.dims[3]) / C.xyQ : 0;
         C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims, tl.zt_target) : 1;
@@ -930,9 +944,9 @@ std::vector<TuneEntry> &tune_cache()
             if (f) {
                 char key[4096];
                 TuneEntry e;
-                while (fscanf(f, "%4095s %d %d %d %d %d %d %d %d", key, &e.sched, &e.tiles.xy_target,
+                while (fscanf(f, "%4095s %d %d %d %d %d %d %d %d %d", key, &e.sched, &e.tiles.xy_target,
                               &e.tiles.xy_ept, &e.tiles.zt_target, &e.tiles.zt_ept, &e.tiles.zt_reg, &e.tiles.zt_reg_p,
-                              &e.tiles.xy_reg) == 9) {
+                              &e.tiles.xy_reg, &e.tiles.line_reg) == 10) {
                     e.key = key;
                     cache.push_back(e);
                 }
@@ -948,7 +962,8 @@ bool valid_tiles(const Tiles &t)
     auto ok_target = [](int v) { return v == 1024 || v == 2048 || v == 4096; };
     return ok_target(t.xy_target) && ok_target(t.zt_target) && (t.xy_ept == 4 || t.xy_ept == 8) &&
            (t.zt_ept == 4 || t.zt_ept == 8) && (t.zt_reg == 0 || t.zt_reg == 1 || t.zt_reg == 2 || t.zt_reg == 4) &&
-           (t.xy_reg == 0 || t.xy_reg == 1 || t.xy_reg == 2 || t.xy_reg == 4) && (t.zt_reg_p == 2 || t.zt_reg_p == 4 || t.zt_reg_p == 8);
+           (t.xy_reg == 0 || t.xy_reg == 1 || t.xy_reg == 2 || t.xy_reg == 4) && (t.zt_reg_p == 2 || t.zt_reg_p == 4 || t.zt_reg_p == 8) &&
+           (t.line_reg == 0 || t.line_reg == 1);
 }
 
 // Tile choices of a fixed schedule: defaults, overridden by GF_XY_TARGET,
@@ -967,6 +982,7 @@ Tiles env_tiles()
     rd("GF_ZT_REG", t.zt_reg);
     rd("GF_XY_REG", t.xy_reg);
     rd("GF_ZT_REG_P", t.zt_reg_p);
+    rd("GF_LINE_REG", t.line_reg);
     return valid_tiles(t) ? t : Tiles();
 }
 
@@ -988,10 +1004,18 @@ gf_status choose_schedule(gf_ctx c, int requested)
         Tiles tiles;
     };
     std::vector<Cand> cands = {{kSched1D, Tiles()}};
-    bool any_zreg = false, any_xreg = false;
+    bool any_zreg = false, any_xreg = false, any_line = false;
     for (int k = 0; k < c->ncfg; ++k) {
         any_zreg = any_zreg || zt_reg_fits(c->cfg[k], 2);
         any_xreg = any_xreg || xy_reg_fits(c->cfg[k]);
+        any_line = any_line || line_reg_fits(c->cfg[k]);
+    }
+    // the 1D z and t passes of schedules 1 and 2: in k_fft_line64 (the
+    // default tiles) or LDS-staged
+    if (any_line) {
+        Tiles t;
+        t.line_reg = 0;
+        cands.push_back({kSched1D, t});
     }
     // (x, y) choices: LDS tiles (target, elements per work-item), or the
     // register passes with 1 or 2 work-groups per tile; (z, t) choices: LDS
@@ -1031,7 +1055,14 @@ gf_status choose_schedule(gf_ctx c, int requested)
     for (const Tiles &x : xs) {
         Tiles t = x;
         t.zt_reg = 0;
-        if (sched_feasible(c, kSchedXY1D)) cands.push_back({kSchedXY1D, t});
+        if (sched_feasible(c, kSchedXY1D)) {
+            cands.push_back({kSchedXY1D, t});
+            if (any_line) {
+                Tiles u = t;
+                u.line_reg = 0;
+                cands.push_back({kSchedXY1D, u});
+            }
+        }
         if (!sched_feasible(c, kSchedXYZT)) continue;
         for (const Tiles &z : zs) {
             t.zt_target = z.zt_target;
@@ -1103,9 +1134,9 @@ gf_status choose_schedule(gf_ctx c, int requested)
     if (path) {
         FILE *f = fopen(path, "a");
         if (f) {
-            fprintf(f, "%s %d %d %d %d %d %d %d %d\n", key.c_str(), pick.sched, pick.tiles.xy_target,
+            fprintf(f, "%s %d %d %d %d %d %d %d %d %d\n", key.c_str(), pick.sched, pick.tiles.xy_target,
                     pick.tiles.xy_ept, pick.tiles.zt_target, pick.tiles.zt_ept, pick.tiles.zt_reg, pick.tiles.zt_reg_p,
-                    pick.tiles.xy_reg);
+                    pick.tiles.xy_reg, pick.tiles.line_reg);
             fclose(f);
         }
     }

@@ -34,10 +34,12 @@ EPS = 1e-15
 # with 1, 2 or 3 stages) and 8 (last radix 8: separate scaling step); 48 x 48
 # planes (a general-extent tile filling 56 % of its 4096-element capacity) in
 # the xy and in the zt pass; 64 x 64 planes (the 64^4 workload's, filling
-# the 4096-element tile exactly)
+# the 4096-element tile exactly); Lz = Lt = 64 with Lx Ly a multiple of 16
+# (the z and t lines of schedules 1 and 2 in registers, k_fft_line64; 4 x 4
+# and 6 x 8 xy-planes, the latter with general extents in the xy pass)
 SHAPES = [(8, 8, 8, 8), (12, 8, 6, 4), (6, 6, 6, 2), (2, 2, 2, 2), (24, 4, 2, 6), (4, 12, 4, 8),
           (27, 2, 4, 6), (3, 9, 2, 4), (256, 4, 2, 2), (2, 2, 2, 256), (4, 4, 4, 4), (4, 2, 4, 16),
-          (48, 48, 2, 2), (2, 2, 48, 48), (64, 64, 2, 2), (2, 2, 64, 64)]
+          (48, 48, 2, 2), (2, 2, 48, 48), (64, 64, 2, 2), (2, 2, 64, 64), (4, 4, 64, 64), (6, 8, 64, 64)]
 
 
 def dev(a):
@@ -220,7 +222,8 @@ def compare_trajectory(F, T, Fr, Tr, spread, dims, label=""):
 
 
 @pytest.mark.parametrize("dims,eps,seed", [((8, 8, 8, 8), 0.3, 1), ((12, 8, 6, 4), 0.3, 3), ((6, 6, 6, 2), 0.35, 4),
-                                           ((27, 2, 4, 6), 0.3, 5), ((3, 9, 2, 4), 0.3, 6)])
+                                           ((27, 2, 4, 6), 0.3, 5), ((3, 9, 2, 4), 0.3, 6),
+                                           ((4, 4, 64, 64), 0.3, 7)])
 @pytest.mark.parametrize("sched", [0] + SCHEDULES)
 def test_trajectory_matches_oracle(dims, eps, seed, sched):
     U = random_links(dims, eps, seed)
@@ -565,6 +568,59 @@ def test_single_precision_storage_batch_equals_single(monkeypatch):
     for k in range(len(cases)):
         (it, F, th), Uf = single[k]
         assert its[k] == it and Fs[k] == F and ths[k] == th
+        assert np.array_equal(host(Ubs[k]), Uf)
+
+
+# ---------------------------------------------------------------- 64-point z and t lines
+
+LINE64_SHAPES = [(4, 4, 64, 64), (16, 2, 64, 64), (6, 8, 64, 64)]
+
+
+@pytest.mark.parametrize("dims", LINE64_SHAPES)
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("sched,line", [(1, "1"), (2, "1"), (2, "0")])
+def test_line64_register_passes_match_oracle(monkeypatch, dims, prec, sched, line):
+    """The 1D z and t passes of 64-point lines in registers (GF_LINE_REG=1,
+    k_fft_line64: forward z, forward t + K(p) + backward t, backward z) and
+    LDS-staged (0), in schedules 1 and 2: the plain transform of three fields
+    (an odd field count) both ways and the gauge vector against the oracle."""
+    monkeypatch.setenv("GF_LINE_REG", line)
+    U = random_links(dims, 0.4, 61)
+    fx = GaugeFixer(dev(U), fft_prec=prec, fft_schedule=sched)
+    g = host(fx.gauge())
+    gref = oracle.gauge_from_delta(dims, oracle.delta(dims, U), ALPHA)
+    assert np.max(np.abs(g - gref)) < (fp32_gauge_tolerance(dims) if prec else 1e-13)
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(62)
+    f = rng.standard_normal((3, V)) + 1j * rng.standard_normal((3, V))
+    ct = torch.complex64 if prec else torch.complex128
+    tol = 3e-6 if prec else 1e-13
+    for sign in (-1, +1):
+        got = host(fx.fft(torch.from_numpy(f).to(ct).to("cuda").contiguous(), sign)).astype(np.complex128)
+        for k in range(3):
+            ref = oracle.fft4d(dims, f[k], sign)
+            assert np.max(np.abs(got[k] - ref)) < tol * np.max(np.abs(ref)), (sign, k)
+
+
+def test_line64_batch_equals_single_runs(monkeypatch):
+    """A batch mixing a configuration whose z and t lines run in registers with
+    one that takes the LDS-staged 1D passes (schedule 2, both in one launch
+    per pass): every member bitwise equal to its own context's run."""
+    monkeypatch.setenv("GF_TCHUNK", "2")
+    monkeypatch.setenv("GF_TCHUNK_BATCH", "2")
+    cases = [((4, 4, 64, 64), 0.3, 63), ((8, 8, 8, 8), 0.3, 64), ((16, 2, 64, 64), 0.35, 65)]
+    Us = [random_links(d, e, s) for d, e, s in cases]
+    single = []
+    for U in Us:
+        Ud = dev(U)
+        fx = GaugeFixer(Ud, fft_prec=1, fft_schedule=2)
+        single.append((fx.fix_until(EPS, 5000), host(Ud)))
+    Ubs = [dev(U) for U in Us]
+    bx = BatchGaugeFixer(Ubs, fft_prec=1, fft_schedule=2)
+    its, Fs, ths = bx.fix_until(EPS, 5000)
+    for k in range(len(cases)):
+        (it, F, th), Uf = single[k]
+        assert its[k] == it and Fs[k] == F and ths[k] == th, (k, its[k], it)
         assert np.array_equal(host(Ubs[k]), Uf)
 
 
