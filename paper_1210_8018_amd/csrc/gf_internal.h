@@ -99,7 +99,7 @@ struct Cfg {
     int ztPad;            // LDS elements added to every t-plane of a zt tile
     int zt_reg;           // the scaled (z, t) pass runs in k_fft_zt_reg (Lz = Lt = 32, ztP = 2 or 4)
     int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 32, xyQ = 2)
-    int line_reg;         // the 1D z and t passes run in k_fft_line64 (Lz = Lt = 64, Lx Ly a multiple of 16)
+    int line[2];          // the 1D z (line[0]) / t (line[1]) passes run in k_fft_line (that extent 32, 48 or 64)
 };
 
 // Block-to-configuration maps for every launch shape of a batch: entry e
@@ -112,7 +112,7 @@ struct Batch {
     int off_fft[4][kMaxCfg + 1];
     int off_xy[kMaxCfg + 1];
     int off_zt[kMaxCfg + 1];
-    int off_line[kMaxCfg + 1];  // k_fft_line64 work-groups (configurations with line_reg)
+    int off_line[2][kMaxCfg + 1];  // k_fft_line units (16 xy-sites x 4 lines) of the z and t passes
 };
 
 struct Launch {
@@ -136,7 +136,8 @@ struct Launch {
     int zt_reg_p;                  // xy-sites per tile of k_fft_zt_reg (2 or 4)
     int xy_reg_any, xy_lds_any;    // iteration's xy passes: some configuration in the register / LDS-staged ones
     int xy_reg_groups;             // work-groups per tile of the register xy passes
-    int total_line;                // work-groups of k_fft_line64 (0: no configuration with line_reg)
+    int total_line[2];             // k_fft_line units of the z and t passes (0: no configuration has them)
+    int line_m[2];                 // line lengths among them: bit 0 32, bit 1 48, bit 2 64
     int max_lds_elems;    // 1D passes: largest P * L
     int fp32;             // transform precision
     int fused;            // iterations use the fused update + divergence kernel

@@ -685,7 +685,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(const Cfg *__restrict__ cfg
     if (respect_done && C.ctrl->done) return;
     const FftAxis &A = C.ax[axis];
     if (P2 != is_p2(A.L)) return;  // the other instance takes it
-    if (axis >= 2 && C.line_reg) return;  // k_fft_line64 takes it
+    if (axis >= 2 && C.line[axis - 2]) return;  // k_fft_line takes it
     const int t = tile - B->off_fft[axis][c];
     const int L = A.L, P = A.P, n = P * L;
     T2 *buf0 = (T2 *)smem;
@@ -1557,124 +1557,150 @@ __global__ __launch_bounds__(256) void k_fft_xy_inv_reg(const Cfg *__restrict__ 
     }
 }
 
-// ============================================================ 1D z and t passes, 64-point lines, radix stages in registers
-// For Lz = Lt = 64 (C.line_reg) the 1D passes along z and t (the plain
-// transform passes and the scaled t pass: forward, K(p), backward) keep each
-// 64-point line in four lanes of one wave (lane offsets 0, 16, 32, 48; 16
-// elements each): a 16-point DFT per lane, the twiddles
-// exp(-2 pi i j k1 / 64), the exchange among the four lanes by the gfx950
-// lane-swap instructions, and 4-point DFTs. The 16 lanes of a row are 16
-// consecutive xy-sites, so every global access of a wave is four runs of 16
-// consecutive elements (256 bytes FP64, 128 bytes FP32); nothing goes
+// ============================================================ 1D z and t passes, lines of 32, 48 or 64 points in registers
+// For Lz or Lt of 32, 48 or 64 (C.line[]) the 1D passes along that axis (the
+// plain transform passes and the scaled t pass: forward, K(p), backward)
+// keep each line of L = 4 M points in four lanes of one wave (lane offsets
+// 0, 16, 32, 48; M = 8, 12 or 16 elements each): an M-point DFT per lane,
+// the twiddles exp(-2 pi i j k1 / L), the exchange among the four lanes by
+// the gfx950 lane-swap instructions, and 4-point DFTs. The 16 lanes of a row
+// are 16 consecutive xy-sites, so every global access of a wave is four runs
+// of 16 consecutive elements (256 bytes FP64, 128 bytes FP32); nothing goes
 // through LDS but the twiddle table. Elements are read and written at their
 // natural positions; only the registers hold the exchange order.
 
-// 16-point DFT of a[0..15] in place, natural order in and out, sign -1
-// (forward) or +1; tw[e] = exp(-2 pi i e / 64). n = n0 + 4 n1, k = k1 + 4 k2:
-//   X[k1 + 4 k2] = sum_n0 exp(s 2 pi i n0 k2 / 4) exp(s 2 pi i n0 k1 / 16)
-//                  sum_n1 a[n0 + 4 n1] exp(s 2 pi i n1 k1 / 4).
-template <typename T2>
-__device__ __forceinline__ void dft16(T2 (&a)[16], const T2 *tw, int sign)
+// R-point DFT (R = 2, 3, 4) of t[0..R-1] in place.
+template <int R, typename T2>
+__device__ __forceinline__ void dft_small(T2 (&t)[R], int sign)
 {
+    if constexpr (R == 2)
+        dft2(t);
+    else if constexpr (R == 3)
+        dft3(t, sign);
+    else
+        dft4r(t[0], t[1], t[2], t[3], sign);
+}
+
+// M-point DFT (M = 4 R) of a[0..M-1] in place, natural order in and out,
+// sign -1 (forward) or +1; tw[e] = exp(-2 pi i e / 4M), so that
+// exp(-2 pi i m / M) = tw[4 m]. n = n0 + 4 n1, k = k1 + R k2:
+//   X[k1 + R k2] = sum_n0 exp(s 2 pi i n0 k2 / 4) exp(s 2 pi i n0 k1 / M)
+//                  sum_n1 a[n0 + 4 n1] exp(s 2 pi i n1 k1 / R).
+template <int M, typename T2>
+__device__ __forceinline__ void dft_lane(T2 (&a)[M], const T2 *tw, int sign)
+{
+    constexpr int R = M / 4;
 #pragma unroll
-    for (int n0 = 0; n0 < 4; ++n0) dft4r(a[n0], a[n0 + 4], a[n0 + 8], a[n0 + 12], sign);
+    for (int n0 = 0; n0 < 4; ++n0) {
+        T2 t[R];
+#pragma unroll
+        for (int n1 = 0; n1 < R; ++n1) t[n1] = a[n0 + 4 * n1];
+        dft_small<R>(t, sign);
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) a[n0 + 4 * k1] = t[k1];
+    }
 #pragma unroll
     for (int n0 = 1; n0 < 4; ++n0)
 #pragma unroll
-        for (int k1 = 1; k1 < 4; ++k1) {
+        for (int k1 = 1; k1 < R; ++k1) {
             T2 w = tw[4 * n0 * k1];
             if (sign > 0) w.y = -w.y;
             a[n0 + 4 * k1] = t_mul(a[n0 + 4 * k1], w);
         }
 #pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) dft4r(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3], sign);
-    // X[k] is at a[4 (k mod 4) + k / 4]: rename into natural order
-    T2 b[16];
+    for (int k1 = 0; k1 < R; ++k1) dft4r(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3], sign);
+    // X[k] is at a[4 (k mod R) + k / R]: rename into natural order
+    T2 b[M];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) b[k] = a[4 * (k & 3) + (k >> 2)];
+    for (int k = 0; k < M; ++k) b[k] = a[4 * (k % R) + k / R];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) a[k] = b[k];
+    for (int k = 0; k < M; ++k) a[k] = b[k];
 }
 
 // The exchange among the four lanes j = 2 a + c (lane offset 32 a + 16 c) of
-// a 64-point line: before, lane j holds Y_j[k1] at R[k1] (k1 = 0..15); after,
-// lane j holds Y_jj[4 j + e] at R[4 jj + e] (jj, e = 0..3). The lanes 32 apart
-// trade halves (R[m + 8 a'] = Y_{2 a' + c}[8 a + m] after), then the lanes 16
-// apart trade quarters of each half. Each step is its own inverse.
-template <typename T2>
-__device__ __forceinline__ void line_exchange(T2 (&R)[16])
+// a line: before, lane j holds Y_j[k1] at R[k1] (k1 = 0..M-1); after, lane j
+// holds Y_jj[(M/4) j + e] at R[(M/4) jj + e] (jj = 0..3, e < M/4). The lanes
+// 32 apart trade halves (R[m + (M/2) a'] = Y_{2 a' + c}[(M/2) a + m] after),
+// then the lanes 16 apart trade quarters of each half. Each step is its own
+// inverse.
+template <int M, typename T2>
+__device__ __forceinline__ void line_exchange(T2 (&R)[M])
 {
 #pragma unroll
-    for (int m = 0; m < 8; ++m) lane_swap<true>(R[m], R[m + 8]);
+    for (int m = 0; m < M / 2; ++m) lane_swap<true>(R[m], R[m + M / 2]);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) lane_swap<false>(R[8 * a + e], R[8 * a + 4 + e]);
+        for (int e = 0; e < M / 4; ++e) lane_swap<false>(R[(M / 2) * a + e], R[(M / 2) * a + M / 4 + e]);
 }
-template <typename T2>
-__device__ __forceinline__ void line_exchange_back(T2 (&R)[16])
+template <int M, typename T2>
+__device__ __forceinline__ void line_exchange_back(T2 (&R)[M])
 {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) lane_swap<false>(R[8 * a + e], R[8 * a + 4 + e]);
+        for (int e = 0; e < M / 4; ++e) lane_swap<false>(R[(M / 2) * a + e], R[(M / 2) * a + M / 4 + e]);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) lane_swap<true>(R[m], R[m + 8]);
+    for (int m = 0; m < M / 2; ++m) lane_swap<true>(R[m], R[m + M / 2]);
 }
 
-// Forward 64-point DFT of a line spread over four lanes, n = 4 n2 + j:
-//   X[k1 + 16 k2] = sum_j exp(-2 pi i j k2 / 4) exp(-2 pi i j k1 / 64) Y_j[k1],
-//   Y_j[k1] = sum_n2 x[4 n2 + j] exp(-2 pi i n2 k1 / 16).
-// On entry R[n2] = x[4 n2 + j]; on return R[4 k2 + e] = X[4 j + e + 16 k2].
-template <typename T2>
-__device__ __forceinline__ void line64_forward(T2 (&R)[16], const T2 *tw, int j)
+// Forward L-point DFT (L = 4 M) of a line spread over four lanes, n = 4 n2 + j:
+//   X[k1 + M k2] = sum_j exp(-2 pi i j k2 / 4) exp(-2 pi i j k1 / L) Y_j[k1],
+//   Y_j[k1] = sum_n2 x[4 n2 + j] exp(-2 pi i n2 k1 / M).
+// On entry R[n2] = x[4 n2 + j]; on return R[(M/4) k2 + e] = X[(M/4) j + e + M k2].
+template <int M, typename T2>
+__device__ __forceinline__ void line_forward(T2 (&R)[M], const T2 *tw, int j)
 {
-    dft16(R, tw, -1);
+    dft_lane<M>(R, tw, -1);
 #pragma unroll
-    for (int k1 = 1; k1 < 16; ++k1) R[k1] = t_mul(R[k1], tw[(j * k1) & 63]);
-    line_exchange(R);
+    for (int k1 = 1; k1 < M; ++k1) R[k1] = t_mul(R[k1], tw[j * k1]);
+    line_exchange<M>(R);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) dft4r(R[e], R[4 + e], R[8 + e], R[12 + e], -1);
+    for (int e = 0; e < M / 4; ++e) dft4r(R[e], R[M / 4 + e], R[M / 2 + e], R[3 * M / 4 + e], -1);
 }
 
-// Backward 64-point DFT (unnormalised) from the layout line64_forward
-// leaves, back to R[n2] = x[4 n2 + j]:
-//   x[4 n2 + j] = sum_k1 exp(2 pi i n2 k1 / 16) exp(2 pi i j k1 / 64) Z_k1[j],
-//   Z_k1[j] = sum_k2 X[k1 + 16 k2] exp(2 pi i j k2 / 4).
-template <typename T2>
-__device__ __forceinline__ void line64_backward(T2 (&R)[16], const T2 *tw, int j)
+// Backward L-point DFT (unnormalised) from the layout line_forward leaves,
+// back to R[n2] = x[4 n2 + j]:
+//   x[4 n2 + j] = sum_k1 exp(2 pi i n2 k1 / M) exp(2 pi i j k1 / L) Z_k1[j],
+//   Z_k1[j] = sum_k2 X[k1 + M k2] exp(2 pi i j k2 / 4).
+template <int M, typename T2>
+__device__ __forceinline__ void line_backward(T2 (&R)[M], const T2 *tw, int j)
 {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) dft4r(R[e], R[4 + e], R[8 + e], R[12 + e], +1);
-    line_exchange_back(R);
+    for (int e = 0; e < M / 4; ++e) dft4r(R[e], R[M / 4 + e], R[M / 2 + e], R[3 * M / 4 + e], +1);
+    line_exchange_back<M>(R);
 #pragma unroll
-    for (int k1 = 1; k1 < 16; ++k1) {
-        T2 w = tw[(j * k1) & 63];
+    for (int k1 = 1; k1 < M; ++k1) {
+        T2 w = tw[j * k1];
         w.y = -w.y;
         R[k1] = t_mul(R[k1], w);
     }
-    dft16(R, tw, +1);
+    dft_lane<M>(R, tw, +1);
 }
 
-// One 1D pass along z (axis 2) or t (axis 3) over configurations with
-// Lz = Lt = 64 (C.line_reg). KIND 0: forward; 1: backward; 2 (t only):
-// forward, K(p) (natural order), backward. Work-group u of a configuration
-// takes field u mod nfields of the lines of unit v = u / nfields: xy-sites
-// 16 (v mod V2/16) + q, and per wave w the line at other coordinate
-// 4 (v div V2/16) + w (t for a z pass, z for a t pass). The fields of a unit
-// are consecutive work-groups (one XCD), so the t pass's K(p) lines come
-// from L2 after the first.
-template <typename T2, int KIND>
-__global__ __launch_bounds__(256) void k_fft_line64(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
-                                                    int axis, void *fields_override, int nfields, int respect_done)
+// One 1D pass along z (axis 2) or t (axis 3) over the configurations whose
+// lines along that axis run in registers (C.line[axis - 2]) and are 4 M long
+// (the instances for the other lengths take the rest). KIND 0: forward; 1:
+// backward; 2 (t only): forward, K(p) (natural order), backward. Work-group
+// u of a configuration takes field u mod nfields of the lines of unit
+// v = u / nfields: xy-sites 16 (v mod V2/16) + q, and per wave w the line at
+// other coordinate 4 (v div V2/16) + w (t for a z pass, z for a t pass). The
+// fields of a unit are consecutive work-groups (one XCD), so the t pass's
+// K(p) lines come from L2 after the first.
+template <typename T2, int M, int KIND>
+__global__ __launch_bounds__(256) void k_fft_line(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                  int axis, void *fields_override, int nfields, int respect_done)
 {
     using T = typename Cx<T2>::T;
-    __shared__ T2 tw[64];
+    constexpr int L = 4 * M;
+    __shared__ T2 tw[L];
     const int u = xcd_remap(blockIdx.x, gridDim.x);
-    const int c = find_cfg(B->off_line, B->n, u / nfields);
+    const int *off = B->off_line[axis - 2];
+    const int c = find_cfg(off, B->n, u / nfields);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
-    const int lu = u - B->off_line[c] * nfields;
+    if (C.dims[axis] != L) return;  // another length's instance takes it
+    const int lu = u - off[c] * nfields;
     const int field = lu % nfields, v = lu / nfields;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int q = lane & 15, j = lane >> 4;
@@ -1686,41 +1712,43 @@ __global__ __launch_bounds__(256) void k_fft_line64(const Cfg *__restrict__ cfgs
     const unsigned S = axis == 2 ? (unsigned)C.V2 : (unsigned)C.V3;
     const size_t wbase = (size_t)16 * xyb + (size_t)other * (axis == 2 ? (size_t)C.V3 : (size_t)C.V2);
     const unsigned o = (unsigned)q;
-    if (threadIdx.x < 64) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[axis])[threadIdx.x];
+    if (threadIdx.x < L) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[axis])[threadIdx.x];
     __syncthreads();
     T2 *__restrict__ g = (T2 *)(fields_override ? fields_override : C.fields) + (size_t)field * C.V + wbase;
-    T2 R[16];
+    T2 R[M];
     if constexpr (KIND == 1) {
 #pragma unroll
         for (int k2 = 0; k2 < 4; ++k2)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) R[4 * k2 + e] = g[o + (unsigned)(4 * j + e + 16 * k2) * S];
-        line64_backward(R, tw, j);
+            for (int e = 0; e < M / 4; ++e)
+                R[(M / 4) * k2 + e] = g[o + (unsigned)((M / 4) * j + e + M * k2) * S];
+        line_backward<M>(R, tw, j);
 #pragma unroll
-        for (int n2 = 0; n2 < 16; ++n2) g[o + (unsigned)(4 * n2 + j) * S] = R[n2];
+        for (int n2 = 0; n2 < M; ++n2) g[o + (unsigned)(4 * n2 + j) * S] = R[n2];
     } else {
 #pragma unroll
-        for (int n2 = 0; n2 < 16; ++n2) R[n2] = g[o + (unsigned)(4 * n2 + j) * S];
-        line64_forward(R, tw, j);
+        for (int n2 = 0; n2 < M; ++n2) R[n2] = g[o + (unsigned)(4 * n2 + j) * S];
+        line_forward<M>(R, tw, j);
         if constexpr (KIND == 2) {
-            // K(p) of momentum (xy-site, kz, kt = 4 j + e + 16 k2)
+            // K(p) of momentum (xy-site, kz, kt = (M/4) j + e + M k2)
             const T *__restrict__ Km = (const T *)C.kmom + wbase;
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const T k = Km[o + (unsigned)(4 * j + e + 16 * k2) * S];
-                    R[4 * k2 + e].x *= k;
-                    R[4 * k2 + e].y *= k;
+                for (int e = 0; e < M / 4; ++e) {
+                    const T k = Km[o + (unsigned)((M / 4) * j + e + M * k2) * S];
+                    R[(M / 4) * k2 + e].x *= k;
+                    R[(M / 4) * k2 + e].y *= k;
                 }
-            line64_backward(R, tw, j);
+            line_backward<M>(R, tw, j);
 #pragma unroll
-            for (int n2 = 0; n2 < 16; ++n2) g[o + (unsigned)(4 * n2 + j) * S] = R[n2];
+            for (int n2 = 0; n2 < M; ++n2) g[o + (unsigned)(4 * n2 + j) * S] = R[n2];
         } else {
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) g[o + (unsigned)(4 * j + e + 16 * k2) * S] = R[4 * k2 + e];
+                for (int e = 0; e < M / 4; ++e)
+                    g[o + (unsigned)((M / 4) * j + e + M * k2) * S] = R[(M / 4) * k2 + e];
         }
     }
 }
@@ -2554,27 +2582,36 @@ hipError_t launch_reduce(const Launch &L, int ncfg, int count_iter, int respect_
 hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *fields_override, int nfields,
                            int respect_done)
 {
-    if (axis >= 2 && L.total_line > 0) {
-        const dim3 lg(L.total_line * nfields), lb(256);
-#define GF_LINE(T2_)                                                                                              \
-    do {                                                                                                          \
-        if (mode == 1)                                                                                            \
-            hipLaunchKernelGGL((k_fft_line64<T2_, 2>), lg, lb, 0, L.stream, L.cfgs, L.batch, axis, fields_override, \
-                               nfields, respect_done);                                                            \
-        else if (sign < 0)                                                                                        \
-            hipLaunchKernelGGL((k_fft_line64<T2_, 0>), lg, lb, 0, L.stream, L.cfgs, L.batch, axis, fields_override, \
-                               nfields, respect_done);                                                            \
-        else                                                                                                      \
-            hipLaunchKernelGGL((k_fft_line64<T2_, 1>), lg, lb, 0, L.stream, L.cfgs, L.batch, axis, fields_override, \
-                               nfields, respect_done);                                                            \
+    if (axis >= 2 && L.total_line[axis - 2] > 0) {
+        const dim3 lg(L.total_line[axis - 2] * nfields), lb(256);
+        const int lm = L.line_m[axis - 2];  // line lengths present: bit 0 32, bit 1 48, bit 2 64
+#define GF_LINE_K(T2_, M_, K_)                                                                                \
+    hipLaunchKernelGGL((k_fft_line<T2_, M_, K_>), lg, lb, 0, L.stream, L.cfgs, L.batch, axis, fields_override, \
+                       nfields, respect_done)
+#define GF_LINE_M(T2_, M_)                \
+    do {                                  \
+        if (mode == 1)                    \
+            GF_LINE_K(T2_, M_, 2);        \
+        else if (sign < 0)                \
+            GF_LINE_K(T2_, M_, 0);        \
+        else                              \
+            GF_LINE_K(T2_, M_, 1);        \
+    } while (0)
+#define GF_LINE(T2_)                           \
+    do {                                       \
+        if (lm & 1) GF_LINE_M(T2_, 8);         \
+        if (lm & 2) GF_LINE_M(T2_, 12);        \
+        if (lm & 4) GF_LINE_M(T2_, 16);        \
     } while (0)
         if (L.fp32)
             GF_LINE(float2);
         else
             GF_LINE(double2);
 #undef GF_LINE
+#undef GF_LINE_M
+#undef GF_LINE_K
     }
-    if (L.total_fft_tiles[axis] == 0) return hipGetLastError();  // every configuration in k_fft_line64
+    if (L.total_fft_tiles[axis] == 0) return hipGetLastError();  // every configuration in k_fft_line
     const dim3 grid(L.total_fft_tiles[axis], nfields);
     // power-of-two and general instances, as for the 2D passes
     const size_t sh32 = (size_t)(2 * L.max_lds_elems + 256) * sizeof(float2);

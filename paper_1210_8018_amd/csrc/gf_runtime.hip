@@ -273,7 +273,7 @@ struct Tiles {
     int zt_reg = 2;
     int zt_reg_p = 4;  // xy-sites per tile of the register (z, t) pass (2, 4 or 8)
     int xy_reg = 1;
-    int line_reg = 1;  // 1D z and t passes of 64-point lines in k_fft_line64
+    int line_reg = 1;  // 1D z and t passes of 32-, 48- and 64-point lines in k_fft_line
     bool operator==(const Tiles &o) const
     {
         return xy_target == o.xy_target && xy_ept == o.xy_ept && zt_target == o.zt_target && zt_ept == o.zt_ept &&
@@ -285,8 +285,13 @@ struct Tiles {
 // its (x, y) passes in k_fft_xy_reg / k_fft_xy_inv_reg (tiles of two planes).
 bool zt_reg_fits(const Cfg &C, int P) { return C.dims[2] == 32 && C.dims[3] == 32 && C.V2 % P == 0; }
 bool xy_reg_fits(const Cfg &C) { return C.dims[0] == 32 && C.dims[1] == 32 && (C.dims[2] * C.dims[3]) % 2 == 0; }
-// and its 1D z and t passes in k_fft_line64 (16 xy-sites per row of a wave)
-bool line_reg_fits(const Cfg &C) { return C.dims[2] == 64 && C.dims[3] == 64 && C.V2 % 16 == 0; }
+// and its 1D pass along axis 2 + a in k_fft_line (a line of 32, 48 or 64
+// points; 16 xy-sites per row of a wave, 4 lines of the other axis per unit)
+bool line_fits(const Cfg &C, int a)
+{
+    const int L = C.dims[2 + a], other = C.dims[3 - a];
+    return (L == 32 || L == 48 || L == 64) && C.V2 % 16 == 0 && other % 4 == 0;
+}
 
 struct gf_ctx_s {
     int ncfg = 0;
@@ -749,11 +754,12 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
         b.idx[e] = list[e];
         b.off_site[e + 1] = b.off_site[e] + C.nblk_site;
         b.off_march[e + 1] = b.off_march[e] + C.nblk_march;
-        // the z and t passes of a configuration with line_reg run in k_fft_line64:
-        // 16 xy-sites times 4 lines per work-group
+        // the z and t passes of a configuration's lines in registers run in
+        // k_fft_line: 16 xy-sites times 4 lines per unit
         for (int mu = 0; mu < 4; ++mu)
-            b.off_fft[mu][e + 1] = b.off_fft[mu][e] + ((mu >= 2 && C.line_reg) ? 0 : C.ax[mu].ntile);
-        b.off_line[e + 1] = b.off_line[e] + (C.line_reg ? (C.V2 / 16) * (C.dims[3] / 4) : 0);
+            b.off_fft[mu][e + 1] = b.off_fft[mu][e] + ((mu >= 2 && C.line[mu - 2]) ? 0 : C.ax[mu].ntile);
+        b.off_line[0][e + 1] = b.off_line[0][e] + (C.line[0] ? (C.V2 / 16) * (C.dims[3] / 4) : 0);
+        b.off_line[1][e + 1] = b.off_line[1][e] + (C.line[1] ? (C.V2 / 16) * (C.dims[2] / 4) : 0);
         b.off_xy[e + 1] = b.off_xy[e] + C.nxy;
         b.off_zt[e + 1] = b.off_zt[e] + C.nzt;
     }
@@ -761,7 +767,12 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
     L.total_march_blocks = b.off_march[b.n];
     for (int mu = 0; mu < 4; ++mu) L.total_fft_tiles[mu] = b.off_fft[mu][b.n];
     L.total_xy_tiles = b.off_xy[b.n];
-    L.total_line = b.off_line[b.n];
+    for (int a = 0; a < 2; ++a) {
+        L.total_line[a] = b.off_line[a][b.n];
+        L.line_m[a] = 0;
+        for (int e = 0; e < b.n; ++e)
+            if (c->cfg[list[e]].line[a]) L.line_m[a] |= 1 << (c->cfg[list[e]].dims[2 + a] / 16 - 2);
+    }
     L.total_zt_tiles = b.off_zt[b.n];
     L.ncfg = b.n;
 }
@@ -788,7 +799,7 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
         C.xy_reg = ((sched == kSchedXYZT || sched == kSchedXY1D) && tl.xy_reg && xy_reg_fits(C)) ? 1 : 0;
         // every 1D z and t pass (those of schedules 1 and 2, and the plain
         // transform calls)
-        C.line_reg = (tl.line_reg && line_reg_fits(C)) ? 1 : 0;
+        for (int a = 0; a < 2; ++a) C.line[a] = (tl.line_reg && line_fits(C, a)) ? 1 : 0;
         if (C.xy_reg) C.xyQ = 2;  // the register passes' tile: 2 planes
         C.nxy = xy_feasible(C.dims) ? (C.dims[2] * C.dims[3]) / C.xyQ : 0;
         C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims, tl.zt_target) : 1;
@@ -1008,9 +1019,9 @@ gf_status choose_schedule(gf_ctx c, int requested)
     for (int k = 0; k < c->ncfg; ++k) {
         any_zreg = any_zreg || zt_reg_fits(c->cfg[k], 2);
         any_xreg = any_xreg || xy_reg_fits(c->cfg[k]);
-        any_line = any_line || line_reg_fits(c->cfg[k]);
+        any_line = any_line || line_fits(c->cfg[k], 0) || line_fits(c->cfg[k], 1);
     }
-    // the 1D z and t passes of schedules 1 and 2: in k_fft_line64 (the
+    // the 1D z and t passes of schedules 1 and 2: in k_fft_line (the
     // default tiles) or LDS-staged
     if (any_line) {
         Tiles t;

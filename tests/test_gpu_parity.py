@@ -35,7 +35,7 @@ EPS = 1e-15
 # planes (a general-extent tile filling 56 % of its 4096-element capacity) in
 # the xy and in the zt pass; 64 x 64 planes (the 64^4 workload's, filling
 # the 4096-element tile exactly); Lz = Lt = 64 with Lx Ly a multiple of 16
-# (the z and t lines of schedules 1 and 2 in registers, k_fft_line64; 4 x 4
+# (the z and t lines of schedules 1 and 2 in registers, k_fft_line; 4 x 4
 # and 6 x 8 xy-planes, the latter with general extents in the xy pass)
 SHAPES = [(8, 8, 8, 8), (12, 8, 6, 4), (6, 6, 6, 2), (2, 2, 2, 2), (24, 4, 2, 6), (4, 12, 4, 8),
           (27, 2, 4, 6), (3, 9, 2, 4), (256, 4, 2, 2), (2, 2, 2, 256), (4, 4, 4, 4), (4, 2, 4, 16),
@@ -223,7 +223,7 @@ def compare_trajectory(F, T, Fr, Tr, spread, dims, label=""):
 
 @pytest.mark.parametrize("dims,eps,seed", [((8, 8, 8, 8), 0.3, 1), ((12, 8, 6, 4), 0.3, 3), ((6, 6, 6, 2), 0.35, 4),
                                            ((27, 2, 4, 6), 0.3, 5), ((3, 9, 2, 4), 0.3, 6),
-                                           ((4, 4, 64, 64), 0.3, 7)])
+                                           ((4, 4, 64, 64), 0.3, 7), ((4, 4, 48, 48), 0.3, 8)])
 @pytest.mark.parametrize("sched", [0] + SCHEDULES)
 def test_trajectory_matches_oracle(dims, eps, seed, sched):
     U = random_links(dims, eps, seed)
@@ -571,17 +571,21 @@ def test_single_precision_storage_batch_equals_single(monkeypatch):
         assert np.array_equal(host(Ubs[k]), Uf)
 
 
-# ---------------------------------------------------------------- 64-point z and t lines
+# ---------------------------------------------------------------- z and t lines of 32, 48, 64 points
 
-LINE64_SHAPES = [(4, 4, 64, 64), (16, 2, 64, 64), (6, 8, 64, 64)]
+# both axes in registers (64, 48 and 32 points, 4 x 4, 16 x 2, 6 x 8, 8 x 2
+# xy-planes); lines of different lengths in one configuration; only the t
+# lines (z = 12) or only the z lines (t = 8)
+LINE_SHAPES = [(4, 4, 64, 64), (16, 2, 64, 64), (6, 8, 64, 64), (4, 4, 48, 48), (8, 2, 32, 32),
+               (4, 4, 32, 64), (8, 2, 12, 48), (4, 4, 64, 8)]
 
 
-@pytest.mark.parametrize("dims", LINE64_SHAPES)
+@pytest.mark.parametrize("dims", LINE_SHAPES)
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("sched,line", [(1, "1"), (2, "1"), (2, "0")])
-def test_line64_register_passes_match_oracle(monkeypatch, dims, prec, sched, line):
-    """The 1D z and t passes of 64-point lines in registers (GF_LINE_REG=1,
-    k_fft_line64: forward z, forward t + K(p) + backward t, backward z) and
+def test_line_register_passes_match_oracle(monkeypatch, dims, prec, sched, line):
+    """The 1D z and t passes with their lines in registers (GF_LINE_REG=1,
+    k_fft_line: forward z, forward t + K(p) + backward t, backward z) and
     LDS-staged (0), in schedules 1 and 2: the plain transform of three fields
     (an odd field count) both ways and the gauge vector against the oracle."""
     monkeypatch.setenv("GF_LINE_REG", line)
@@ -602,13 +606,15 @@ def test_line64_register_passes_match_oracle(monkeypatch, dims, prec, sched, lin
             assert np.max(np.abs(got[k] - ref)) < tol * np.max(np.abs(ref)), (sign, k)
 
 
-def test_line64_batch_equals_single_runs(monkeypatch):
-    """A batch mixing a configuration whose z and t lines run in registers with
-    one that takes the LDS-staged 1D passes (schedule 2, both in one launch
-    per pass): every member bitwise equal to its own context's run."""
+def test_line_batch_equals_single_runs(monkeypatch):
+    """A batch mixing configurations whose z and t lines run in registers
+    (64 and 48 points, so two instances per pass) with one that takes the
+    LDS-staged 1D passes (schedule 2, all in one launch per pass): every
+    member bitwise equal to its own context's run."""
     monkeypatch.setenv("GF_TCHUNK", "2")
     monkeypatch.setenv("GF_TCHUNK_BATCH", "2")
-    cases = [((4, 4, 64, 64), 0.3, 63), ((8, 8, 8, 8), 0.3, 64), ((16, 2, 64, 64), 0.35, 65)]
+    cases = [((4, 4, 64, 64), 0.3, 63), ((8, 8, 8, 8), 0.3, 64), ((16, 2, 64, 64), 0.35, 65),
+             ((4, 4, 48, 48), 0.3, 66)]
     Us = [random_links(d, e, s) for d, e, s in cases]
     single = []
     for U in Us:
