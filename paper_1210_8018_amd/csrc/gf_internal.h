@@ -98,7 +98,7 @@ struct Cfg {
     int xyPad;            // LDS elements added to every x-row of an xy tile (bank spreading)
     int ztPad;            // LDS elements added to every t-plane of a zt tile
     int zt_reg;           // the scaled (z, t) pass runs in k_fft_zt_reg (Lz = Lt = 32, ztP = 2 or 4)
-    int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 32, xyQ = 2)
+    int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 32, 48, 64)
     int line[2];          // the 1D z (line[0]) / t (line[1]) passes run in k_fft_line (that extent 32, 48 or 64)
 };
 
@@ -136,6 +136,7 @@ struct Launch {
     int zt_reg_p;                  // xy-sites per tile of k_fft_zt_reg (2 or 4)
     int xy_reg_any, xy_lds_any;    // iteration's xy passes: some configuration in the register / LDS-staged ones
     int xy_reg_groups;             // work-groups per tile of the register xy passes
+    int xy_m;                      // their plane sizes present: bit 0 32, bit 1 48, bit 2 64
     int total_line[2];             // k_fft_line units of the z and t passes (0: no configuration has them)
     int line_m[2];                 // line lengths among them: bit 0 32, bit 1 48, bit 2 64
     int max_lds_elems;    // 1D passes: largest P * L

@@ -1431,132 +1431,6 @@ __global__ __launch_bounds__(128 * P) __attribute__((amdgpu_waves_per_eu(P >= 4 
     }
 }
 
-// ============================================================ (x, y) passes, 32 x 32 planes, radix stages in registers
-// The same scheme as k_fft_zt_reg for the (x, y) passes of configurations
-// with Lx = Ly = 32 (C.xy_reg): a tile is two consecutive xy-planes of one
-// field; x-pencils (rows) and y-pencils (columns) are held by four lanes
-// each, 8 elements per lane; LDS only moves the tile between the two.
-// Global memory stays in natural order, so the (z, t) pass and K(p) see the
-// layout the LDS-staged passes produce.
-constexpr int kXyRegYs = 33;  // LDS row stride of a plane: the 16 lanes of an access hit distinct banks
-
-// Forward (x, y) transform of the four fields. Work-item (w, q, j) holds
-// plane w / 2 of the tile and row (then column) r = 16 (w mod 2) + q: x-pencil
-// elements x = 4 n2 + j of row y = r, then y-pencil elements y = 4 n2 + j of
-// column kx = r. fold != 0: the work-groups past the tiles do the final
-// reduction of the previous update, as k_fft_xy's.
-template <typename T2>
-__global__ __launch_bounds__(256) void k_fft_xy_reg(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
-                                                    int respect_done, int ngroups, int fold)
-{
-    __shared__ T2 buf[2 * 32 * kXyRegYs + 32];
-    const int ntiles = B->off_xy[B->n] * ngroups;
-    if ((int)blockIdx.x >= ntiles) {
-        const Cfg &R = cfgs[B->idx[blockIdx.x - ntiles]];
-        if (R.ctrl->done) return;
-        finalize_config(R, R.nblk_march, 1, fold == 2, (dd *)buf);
-        return;
-    }
-    const int rb = xcd_remap(blockIdx.x, ntiles);
-    const int tile = rb / ngroups, grp = rb - tile * ngroups;
-    const int nfg = kFields / ngroups, f0 = grp * nfg;
-    const int c = find_cfg(B->off_xy, B->n, tile);
-    const Cfg &C = cfgs[B->idx[c]];
-    if (respect_done && C.ctrl->done) return;
-    if (!C.xy_reg) return;  // the LDS-staged pass takes it
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = lane & 15, j = lane >> 4;
-    const int pl = w >> 1, r = 16 * (w & 1) + q;
-    T2 *tw = buf + 2 * 32 * kXyRegYs;  // exp(-2 pi i e / 32), the same table for x and y
-    if (threadIdx.x < 32) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[0])[threadIdx.x];
-    __syncthreads();
-    T2 *__restrict__ plane = (T2 *)C.fields + (size_t)f0 * C.V + (size_t)((tile - B->off_xy[c]) * 2 + pl) * 1024;
-    T2 *__restrict__ sb = buf + pl * 32 * kXyRegYs;
-    T2 Rn[8];
-#pragma unroll
-    for (int n2 = 0; n2 < 8; ++n2) Rn[n2] = plane[r * 32 + 4 * n2 + j];
-    for (int f = 0; f < nfg; ++f, plane += C.V) {
-        T2 R[8];
-#pragma unroll
-        for (int n2 = 0; n2 < 8; ++n2) R[n2] = Rn[n2];
-        if (f + 1 < nfg) {
-#pragma unroll
-            for (int n2 = 0; n2 < 8; ++n2) Rn[n2] = plane[C.V + r * 32 + 4 * n2 + j];
-        }
-        pencil32_forward(R, tw, j);  // R[2 k2 + e] = (y = r, kx = 2 j + e + 8 k2)
-        if (f) __syncthreads();   // the previous field's reads of the tile are done
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2)
-#pragma unroll
-            for (int e = 0; e < 2; ++e) sb[r * kXyRegYs + 2 * j + e + 8 * k2] = R[2 * k2 + e];
-        __syncthreads();
-#pragma unroll
-        for (int n2 = 0; n2 < 8; ++n2) R[n2] = sb[(4 * n2 + j) * kXyRegYs + r];
-        pencil32_forward(R, tw, j);  // R[2 k2 + e] = (ky = 2 j + e + 8 k2, kx = r)
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2)
-#pragma unroll
-            for (int e = 0; e < 2; ++e) plane[(2 * j + e + 8 * k2) * 32 + r] = R[2 * k2 + e];
-    }
-}
-
-// Inverse (x, y) transform of the four fields of a tile, written to fields2
-// (the filtered fields the fused pass forms g from; FP64 link storage).
-// Columns first (the layout pencil32_backward takes, read from natural
-// order), then rows.
-template <typename T2>
-__global__ __launch_bounds__(256) void k_fft_xy_inv_reg(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
-                                                        int respect_done, int ngroups)
-{
-    __shared__ T2 buf[2 * 32 * kXyRegYs + 32];
-    const int ntiles = B->off_xy[B->n] * ngroups;
-    const int rb = xcd_remap(blockIdx.x, ntiles);
-    const int tile = rb / ngroups, grp = rb - tile * ngroups;
-    const int nfg = kFields / ngroups, f0 = grp * nfg;
-    const int c = find_cfg(B->off_xy, B->n, tile);
-    const Cfg &C = cfgs[B->idx[c]];
-    if (respect_done && C.ctrl->done) return;
-    if (!C.xy_reg) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = lane & 15, j = lane >> 4;
-    const int pl = w >> 1, r = 16 * (w & 1) + q;
-    T2 *tw = buf + 2 * 32 * kXyRegYs;  // exp(-2 pi i e / 32), the same table for x and y
-    if (threadIdx.x < 32) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[0])[threadIdx.x];
-    __syncthreads();
-    const size_t po = (size_t)f0 * C.V + (size_t)((tile - B->off_xy[c]) * 2 + pl) * 1024;
-    const T2 *__restrict__ src = (const T2 *)C.fields + po;
-    T2 *__restrict__ dst = (T2 *)C.fields2 + po;
-    T2 *__restrict__ sb = buf + pl * 32 * kXyRegYs;
-    T2 Rn[8];
-#pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2)
-#pragma unroll
-        for (int e = 0; e < 2; ++e) Rn[2 * k2 + e] = ld_stream(src + (2 * j + e + 8 * k2) * 32 + r);
-    for (int f = 0; f < nfg; ++f, src += C.V, dst += C.V) {
-        T2 R[8];
-#pragma unroll
-        for (int n2 = 0; n2 < 8; ++n2) R[n2] = Rn[n2];
-        if (f + 1 < nfg) {
-#pragma unroll
-            for (int k2 = 0; k2 < 4; ++k2)
-#pragma unroll
-                for (int e = 0; e < 2; ++e) Rn[2 * k2 + e] = ld_stream(src + C.V + (2 * j + e + 8 * k2) * 32 + r);
-        }
-        pencil32_backward(R, tw, j);  // R[n2] = (y = 4 n2 + j, kx = r)
-        if (f) __syncthreads();
-#pragma unroll
-        for (int n2 = 0; n2 < 8; ++n2) sb[(4 * n2 + j) * kXyRegYs + r] = R[n2];
-        __syncthreads();
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2)
-#pragma unroll
-            for (int e = 0; e < 2; ++e) R[2 * k2 + e] = sb[r * kXyRegYs + 2 * j + e + 8 * k2];
-        pencil32_backward(R, tw, j);  // R[n2] = (y = r, x = 4 n2 + j)
-#pragma unroll
-        for (int n2 = 0; n2 < 8; ++n2) dst[r * 32 + 4 * n2 + j] = R[n2];
-    }
-}
-
 // ============================================================ 1D z and t passes, lines of 32, 48 or 64 points in registers
 // For Lz or Lt of 32, 48 or 64 (C.line[]) the 1D passes along that axis (the
 // plain transform passes and the scaled t pass: forward, K(p), backward)
@@ -1750,6 +1624,149 @@ __global__ __launch_bounds__(256) void k_fft_line(const Cfg *__restrict__ cfgs, 
                 for (int e = 0; e < M / 4; ++e)
                     g[o + (unsigned)((M / 4) * j + e + M * k2) * S] = R[(M / 4) * k2 + e];
         }
+    }
+}
+
+// ============================================================ (x, y) passes, 32, 48 and 64 point planes, radix stages in registers
+// For Lx = Ly = L = 4 M (32, 48 or 64) the iteration's (x, y) passes keep
+// each x-line (row) and then each y-line (column) of a plane in four lanes
+// of one wave, M elements per lane, with the line transforms above; LDS only
+// moves the plane from rows to columns. A tile is PL consecutive planes of
+// one field (PL = 2 for 32 points, 1 for 48 and 64: a tile stays within the
+// 4096 elements of the LDS-staged inverse pass, which serves the same tiles
+// for the stage calls and single-precision storage), M/4 waves per plane;
+// work-item (w, q, j) holds row, then column, r = 16 (w mod M/4) + q of plane
+// w / (M/4). Global memory stays in natural order, so the (z, t) and 1D
+// passes and K(p) see the layout the LDS-staged passes produce. The LDS
+// row stride L + 1 puts the 16 lanes of an access on distinct banks.
+template <int M>
+__host__ __device__ constexpr int xy_reg_planes() { return M == 8 ? 2 : 1; }
+template <int M>
+__host__ __device__ constexpr int xy_reg_threads() { return xy_reg_planes<M>() * (M / 4) * 64; }
+// dynamic LDS: the tile (rows of L + 1 elements) and the L twiddles
+template <int M>
+__host__ __device__ constexpr int xy_reg_lds_elems() { return xy_reg_planes<M>() * 4 * M * (4 * M + 1) + 4 * M; }
+
+// Forward (x, y) transform of the four fields (kFields / ngroups of them per
+// work-group, the next one prefetched): rows x = 4 n2 + j of row y = r, then
+// columns y = 4 n2 + j of column kx = r. fold != 0: the work-groups past the
+// tiles do the final reduction of the previous update, as k_fft_xy's.
+template <typename T2, int M>
+__global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_reg(const Cfg *__restrict__ cfgs,
+                                                                   const Batch *__restrict__ B, int respect_done,
+                                                                   int ngroups, int fold)
+{
+    constexpr int L = 4 * M, PL = xy_reg_planes<M>(), WPP = M / 4, YS = L + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T2 *buf = (T2 *)smem;
+    const int ntiles = B->off_xy[B->n] * ngroups;
+    if ((int)blockIdx.x >= ntiles) {
+        const Cfg &R = cfgs[B->idx[blockIdx.x - ntiles]];
+        if (R.ctrl->done) return;
+        finalize_config(R, R.nblk_march, 1, fold == 2, (dd *)buf);
+        return;
+    }
+    const int rb = xcd_remap(blockIdx.x, ntiles);
+    const int tile = rb / ngroups, grp = rb - tile * ngroups;
+    const int nfg = kFields / ngroups, f0 = grp * nfg;
+    const int c = find_cfg(B->off_xy, B->n, tile);
+    const Cfg &C = cfgs[B->idx[c]];
+    if (respect_done && C.ctrl->done) return;
+    if (!C.xy_reg || C.dims[0] != L) return;  // the LDS-staged pass or another length's instance takes it
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane & 15, j = lane >> 4;
+    const int pl = w / WPP, r = 16 * (w % WPP) + q;
+    T2 *tw = buf + PL * L * YS;  // exp(-2 pi i e / L), the same table for x and y
+    if (threadIdx.x < L) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[0])[threadIdx.x];
+    __syncthreads();
+    T2 *__restrict__ plane = (T2 *)C.fields + (size_t)f0 * C.V + (size_t)((tile - B->off_xy[c]) * PL + pl) * (L * L);
+    T2 *__restrict__ sb = buf + pl * L * YS;
+    T2 Rn[M];
+#pragma unroll
+    for (int n2 = 0; n2 < M; ++n2) Rn[n2] = plane[r * L + 4 * n2 + j];
+    for (int f = 0; f < nfg; ++f, plane += C.V) {
+        T2 R[M];
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) R[n2] = Rn[n2];
+        if (f + 1 < nfg) {
+#pragma unroll
+            for (int n2 = 0; n2 < M; ++n2) Rn[n2] = plane[C.V + r * L + 4 * n2 + j];
+        }
+        line_forward<M>(R, tw, j);  // R[(M/4) k2 + e] = (y = r, kx = (M/4) j + e + M k2)
+        if (f) __syncthreads();     // the previous field's reads of the tile are done
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+            for (int e = 0; e < M / 4; ++e) sb[r * YS + (M / 4) * j + e + M * k2] = R[(M / 4) * k2 + e];
+        __syncthreads();
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) R[n2] = sb[(4 * n2 + j) * YS + r];
+        line_forward<M>(R, tw, j);  // R[(M/4) k2 + e] = (ky = (M/4) j + e + M k2, kx = r)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+            for (int e = 0; e < M / 4; ++e) plane[((M / 4) * j + e + M * k2) * L + r] = R[(M / 4) * k2 + e];
+    }
+}
+
+// Inverse (x, y) transform of the four fields of a tile, written to fields2
+// (the filtered fields the fused pass forms g from; FP64 link storage).
+// Columns first (the layout line_backward takes, read from natural order),
+// then rows.
+template <typename T2, int M>
+__global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_inv_reg(const Cfg *__restrict__ cfgs,
+                                                                       const Batch *__restrict__ B,
+                                                                       int respect_done, int ngroups)
+{
+    constexpr int L = 4 * M, PL = xy_reg_planes<M>(), WPP = M / 4, YS = L + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T2 *buf = (T2 *)smem;
+    const int ntiles = B->off_xy[B->n] * ngroups;
+    const int rb = xcd_remap(blockIdx.x, ntiles);
+    const int tile = rb / ngroups, grp = rb - tile * ngroups;
+    const int nfg = kFields / ngroups, f0 = grp * nfg;
+    const int c = find_cfg(B->off_xy, B->n, tile);
+    const Cfg &C = cfgs[B->idx[c]];
+    if (respect_done && C.ctrl->done) return;
+    if (!C.xy_reg || C.dims[0] != L) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane & 15, j = lane >> 4;
+    const int pl = w / WPP, r = 16 * (w % WPP) + q;
+    T2 *tw = buf + PL * L * YS;
+    if (threadIdx.x < L) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[0])[threadIdx.x];
+    __syncthreads();
+    const size_t po = (size_t)f0 * C.V + (size_t)((tile - B->off_xy[c]) * PL + pl) * (L * L);
+    const T2 *__restrict__ src = (const T2 *)C.fields + po;
+    T2 *__restrict__ dst = (T2 *)C.fields2 + po;
+    T2 *__restrict__ sb = buf + pl * L * YS;
+    T2 Rn[M];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+        for (int e = 0; e < M / 4; ++e) Rn[(M / 4) * k2 + e] = ld_stream(src + ((M / 4) * j + e + M * k2) * L + r);
+    for (int f = 0; f < nfg; ++f, src += C.V, dst += C.V) {
+        T2 R[M];
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) R[n2] = Rn[n2];
+        if (f + 1 < nfg) {
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+                for (int e = 0; e < M / 4; ++e)
+                    Rn[(M / 4) * k2 + e] = ld_stream(src + C.V + ((M / 4) * j + e + M * k2) * L + r);
+        }
+        line_backward<M>(R, tw, j);  // R[n2] = (y = 4 n2 + j, kx = r)
+        if (f) __syncthreads();
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) sb[(4 * n2 + j) * YS + r] = R[n2];
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+            for (int e = 0; e < M / 4; ++e) R[(M / 4) * k2 + e] = sb[r * YS + (M / 4) * j + e + M * k2];
+        line_backward<M>(R, tw, j);  // R[n2] = (y = r, x = 4 n2 + j)
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) dst[r * L + 4 * n2 + j] = R[n2];
     }
 }
 
@@ -2665,16 +2682,27 @@ static hipError_t run_xy(const Launch &L, int nf, int sign, void *fo, int rd, in
     if (!fo && L.xy_reg_any) {  // the iteration's forward pass
         if (sign != -1 || nf != kFields) return hipErrorInvalidValue;
         const int ng = L.xy_reg_groups;
-        hipLaunchKernelGGL(k_fft_xy_reg<T2>, dim3(L.total_xy_tiles * ng + (fold ? L.ncfg : 0)), dim3(256), 0,
-                           L.stream, L.cfgs, L.batch, rd, ng, fold);
-        ++launched;
+        // one instance per plane size present; the first with at least
+        // kReduceLanes work-items carries the fold
+#define GF_XYR(M_)                                                                                               \
+    if (L.xy_m & (1 << ((M_) / 4 - 2))) {                                                                        \
+        const int f = xy_reg_threads<M_>() >= kReduceLanes ? fold : 0;                                           \
+        if (f) fold = 0;                                                                                         \
+        hipLaunchKernelGGL((k_fft_xy_reg<T2, M_>), dim3(L.total_xy_tiles * ng + (f ? L.ncfg : 0)),               \
+                           dim3(xy_reg_threads<M_>()), xy_reg_lds_elems<M_>() * sizeof(T2), L.stream, L.cfgs,     \
+                           L.batch, rd, ng, f);                                                                  \
+        ++launched;                                                                                              \
+    }
+        GF_XYR(8) GF_XYR(12) GF_XYR(16)
+#undef GF_XYR
         if (!L.xy_lds_any) return hipGetLastError();
     }
     // a batch mixing power-of-two and general extents launches both
     // instances; only the first carries the folded reduction
 #define X(C_, T_, P2_)                                                                                            \
     if (L.xy_cap == C_ && L.xy_th == T_ && (P2_ ? L.xy_p2 : L.xy_gen)) {                                          \
-        const int f = launched ? 0 : fold;                                                                        \
+        const int f = fold;                                                                                       \
+        fold = 0;                                                                                                 \
         const dim3 grid(L.total_xy_tiles + (f ? L.ncfg : 0), (nf + fpb - 1) / fpb);                               \
         hipLaunchKernelGGL((k_fft_xy<T2, C_, T_, P2_>), grid, dim3(T_), sh, L.stream, L.cfgs, L.batch, sign, fo, rd, \
                            L.xy_tw2, nf, fpb, f);                                                                 \
@@ -2724,9 +2752,14 @@ static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
     int launched = 0;
     if (!go && gauge_store_mode(L) == 3 && L.xy_reg_any) {
         const int ng = L.xy_reg_groups;
-        hipLaunchKernelGGL(k_fft_xy_inv_reg<T2>, dim3(L.total_xy_tiles * ng), dim3(256), 0, L.stream, L.cfgs, L.batch,
-                           rd, ng);
-        ++launched;
+#define GF_XYR(M_)                                                                                                 \
+    if (L.xy_m & (1 << ((M_) / 4 - 2))) {                                                                          \
+        hipLaunchKernelGGL((k_fft_xy_inv_reg<T2, M_>), dim3(L.total_xy_tiles * ng), dim3(xy_reg_threads<M_>()),    \
+                           xy_reg_lds_elems<M_>() * sizeof(T2), L.stream, L.cfgs, L.batch, rd, ng);                \
+        ++launched;                                                                                                \
+    }
+        GF_XYR(8) GF_XYR(12) GF_XYR(16)
+#undef GF_XYR
         if (!L.xy_lds_any) return hipGetLastError();
     }
 #define X(C_, T_, P2_)                                                                                            \
@@ -2740,9 +2773,15 @@ static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
     return launched ? hipGetLastError() : hipErrorInvalidValue;
 }
 
-// The register xy pass (256 work-items) carries the fold whenever it runs
-// (it is launched first); the LDS-staged one needs kReduceLanes work-items.
-bool can_fold_reduce(const Launch &L) { return L.xy_reg_any || L.xy_th >= kReduceLanes; }
+// The fold needs a work-group of kReduceLanes work-items: a register xy
+// instance of 32- or 64-point planes (256), or the LDS-staged pass with
+// work-groups that large.
+bool can_fold_reduce(const Launch &L)
+{
+    const bool reg = L.xy_reg_any && (L.xy_m & 5);
+    const bool lds = L.xy_lds_any && L.xy_th >= kReduceLanes;
+    return reg || lds;
+}
 
 hipError_t launch_fft_xy(const Launch &L, int sign, void *fields_override, int nfields, int respect_done,
                          int fold_reduce)
@@ -2793,6 +2832,16 @@ static hipError_t set_lds_t()
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_fft_zt_reg<T2, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(zt_reg_lds_total<8>() * sizeof(T2)));
+#define GF_XYR(M_)                                                                                              \
+    if (e == hipSuccess)                                                                                        \
+        e = hipFuncSetAttribute((const void *)k_fft_xy_reg<T2, M_>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                (int)(xy_reg_lds_elems<M_>() * sizeof(T2)));                                    \
+    if (e == hipSuccess)                                                                                        \
+        e = hipFuncSetAttribute((const void *)k_fft_xy_inv_reg<T2, M_>,                                        \
+                                hipFuncAttributeMaxDynamicSharedMemorySize,                                     \
+                                (int)(xy_reg_lds_elems<M_>() * sizeof(T2)));
+    GF_XYR(8) GF_XYR(12) GF_XYR(16)
+#undef GF_XYR
     return e;
 }
 

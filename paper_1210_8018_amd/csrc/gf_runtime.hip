@@ -284,7 +284,13 @@ struct Tiles {
 // Whether a configuration's scaled (z, t) pass can run in k_fft_zt_reg, and
 // its (x, y) passes in k_fft_xy_reg / k_fft_xy_inv_reg (tiles of two planes).
 bool zt_reg_fits(const Cfg &C, int P) { return C.dims[2] == 32 && C.dims[3] == 32 && C.V2 % P == 0; }
-bool xy_reg_fits(const Cfg &C) { return C.dims[0] == 32 && C.dims[1] == 32 && (C.dims[2] * C.dims[3]) % 2 == 0; }
+// planes per tile of the register (x, y) passes: 2 for 32 points, 1 for 48 and 64
+int xy_reg_planes_of(int L) { return L == 32 ? 2 : 1; }
+bool xy_reg_fits(const Cfg &C)
+{
+    const int L = C.dims[0];
+    return L == C.dims[1] && (L == 32 || L == 48 || L == 64) && (C.dims[2] * C.dims[3]) % xy_reg_planes_of(L) == 0;
+}
 // and its 1D pass along axis 2 + a in k_fft_line (a line of 32, 48 or 64
 // points; 16 xy-sites per row of a wave, 4 lines of the other axis per unit)
 bool line_fits(const Cfg &C, int a)
@@ -800,7 +806,7 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
         // every 1D z and t pass (those of schedules 1 and 2, and the plain
         // transform calls)
         for (int a = 0; a < 2; ++a) C.line[a] = (tl.line_reg && line_fits(C, a)) ? 1 : 0;
-        if (C.xy_reg) C.xyQ = 2;  // the register passes' tile: 2 planes
+        if (C.xy_reg) C.xyQ = xy_reg_planes_of(C.dims[0]);  // the register passes' tile
         C.nxy = xy_feasible(C.dims) ? (C.dims[2] * C.dims[3]) / C.xyQ : 0;
         C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims, tl.zt_target) : 1;
         // the register pass's tile: zt_reg_p xy-sites (one width per
@@ -846,6 +852,9 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
     c->L.zt_reg_p = tl.zt_reg_p;
     c->L.xy_reg_any = c->L.xy_lds_any = 0;
     c->L.xy_reg_groups = tl.xy_reg > 0 ? tl.xy_reg : 1;
+    c->L.xy_m = 0;
+    for (int k = 0; k < c->ncfg; ++k)
+        if (c->cfg[k].xy_reg) c->L.xy_m |= 1 << (c->cfg[k].dims[0] / 16 - 2);
     for (int k = 0; k < c->ncfg; ++k) {
         const Cfg &C = c->cfg[k];
         if (C.nzt) (C.zt_reg ? c->L.zt_reg_any : c->L.zt_lds_any) = 1;

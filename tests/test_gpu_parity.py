@@ -669,15 +669,19 @@ def test_zt_register_pass_trajectory(monkeypatch, dims, seed, P):
     compare_trajectory(Fh, Th, Fr, Tr, spread, dims, f"{dims} register zt pass")
 
 
-XY32_SHAPES = [(32, 32, 2, 2), (32, 32, 4, 2), (32, 32, 6, 4), (32, 32, 3, 2)]
+# 32 x 32 planes (two per tile; 32 x 32 x 3 x 3 has an odd plane count and
+# takes the LDS-staged passes), 48 x 48 and 64 x 64 planes (one per tile)
+XY32_SHAPES = [(32, 32, 2, 2), (32, 32, 4, 2), (32, 32, 6, 4), (32, 32, 3, 2), (32, 32, 3, 3), (48, 48, 2, 2),
+               (48, 48, 3, 3), (64, 64, 2, 2), (64, 64, 3, 3)]
 
 
 @pytest.mark.parametrize("dims", XY32_SHAPES)
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("sched,reg", [(3, "1"), (3, "2"), (2, "1"), (3, "0")])
 def test_xy_register_pass_matches_oracle(monkeypatch, dims, prec, sched, reg):
-    """The forward (x, y) pass of 32 x 32 planes with its radix stages in
-    registers (GF_XY_REG = work-groups per tile) or LDS-staged (0), beside
+    """The forward (x, y) pass of 32 x 32, 48 x 48 and 64 x 64 planes with its
+    radix stages in registers (GF_XY_REG = work-groups per tile) or
+    LDS-staged (0), beside
     the (z, t) passes of schedule 3 or the 1D z and t passes of schedule 2:
     the gauge vector against the oracle (the inverse pass then forms g in the
     LDS-staged kernel)."""
@@ -690,7 +694,8 @@ def test_xy_register_pass_matches_oracle(monkeypatch, dims, prec, sched, reg):
 
 
 @pytest.mark.parametrize("dims,seed,reg", [((32, 32, 4, 2), 58, "1"), ((32, 32, 3, 2), 59, "2"),
-                                           ((32, 32, 6, 4), 60, "1")])
+                                           ((32, 32, 6, 4), 60, "1"), ((48, 48, 2, 2), 67, "1"),
+                                           ((64, 64, 3, 2), 68, "2")])
 def test_xy_register_pass_trajectory(monkeypatch, dims, seed, reg):
     """Both register (x, y) passes in the iteration (the inverse one writes the
     filtered fields the fused pass forms g from) against the oracle."""
