@@ -630,6 +630,34 @@ def test_line_batch_equals_single_runs(monkeypatch):
         assert np.array_equal(host(Ubs[k]), Uf)
 
 
+@pytest.mark.parametrize("sched", [2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_register_plane_sizes_batch_equals_single_runs(monkeypatch, sched, prec):
+    """A batch of 32 x 32, 48 x 48 and 64 x 64 xy-planes (three instances of
+    each register (x, y) pass in one iteration; the final reduction folded
+    into the 32- or 64-point instance, which the 48-point one, with 192
+    work-items, cannot carry) beside an LDS-staged member: every member
+    bitwise equal to its own context's run (where a lone 48-point member
+    launches its own reduction)."""
+    monkeypatch.setenv("GF_TCHUNK", "2")
+    monkeypatch.setenv("GF_TCHUNK_BATCH", "2")
+    cases = [((32, 32, 2, 4), 0.3, 71), ((48, 48, 2, 2), 0.3, 72), ((64, 64, 2, 2), 0.35, 73),
+             ((8, 8, 8, 8), 0.3, 74)]
+    Us = [random_links(d, e, s) for d, e, s in cases]
+    single = []
+    for U in Us:
+        Ud = dev(U)
+        fx = GaugeFixer(Ud, fft_prec=prec, fft_schedule=sched)
+        single.append((fx.fix_until(EPS, 5000), host(Ud)))
+    Ubs = [dev(U) for U in Us]
+    bx = BatchGaugeFixer(Ubs, fft_prec=prec, fft_schedule=sched)
+    its, Fs, ths = bx.fix_until(EPS, 5000)
+    for k in range(len(cases)):
+        (it, F, th), Uf = single[k]
+        assert its[k] == it and Fs[k] == F and ths[k] == th, (k, its[k], it)
+        assert np.array_equal(host(Ubs[k]), Uf)
+
+
 # ---------------------------------------------------------------- 32 x 32 (z, t) planes
 
 ZT32_SHAPES = [(2, 2, 32, 32), (4, 2, 32, 32), (6, 4, 32, 32), (8, 8, 32, 32), (16, 2, 32, 32)]
