@@ -1639,6 +1639,11 @@ __global__ __launch_bounds__(256) void k_fft_line(const Cfg *__restrict__ cfgs, 
 // w / (M/4). Global memory stays in natural order, so the (z, t) and 1D
 // passes and K(p) see the layout the LDS-staged passes produce. The LDS
 // row stride L + 1 puts the 16 lanes of an access on distinct banks.
+// g = 1 + Delta~ from the four packed filtered fields, projected (defined
+// with the gauge step below)
+template <typename T2>
+__device__ __forceinline__ M3 gauge_from_fields(T2 a, T2 b, T2 d, T2 e);
+
 template <int M>
 __host__ __device__ constexpr int xy_reg_planes() { return M == 8 ? 2 : 1; }
 template <int M>
@@ -1709,18 +1714,24 @@ __global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_reg(const Cfg *_
     }
 }
 
-// Inverse (x, y) transform of the four fields of a tile, written to fields2
-// (the filtered fields the fused pass forms g from; FP64 link storage).
-// Columns first (the layout line_backward takes, read from natural order),
-// then rows.
-template <typename T2, int M>
+// Inverse (x, y) transform of the four fields of a tile. STORE 3: written to
+// fields2 (the filtered fields the fused pass forms g from; FP64 link
+// storage). STORE 2 (FP32 transform, single-precision storage): one
+// work-group takes all four fields, keeps the first three in registers and
+// forms g = 1 + Delta~, projected, at each of its sites with the fourth,
+// stored in binary32 two-row form (what the LDS-staged pass's gauge store
+// mode 2 writes). Columns first (the layout line_backward takes, read from
+// natural order), then rows.
+template <typename T2, int M, int STORE>
 __global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_inv_reg(const Cfg *__restrict__ cfgs,
                                                                        const Batch *__restrict__ B,
                                                                        int respect_done, int ngroups)
 {
+    static_assert(STORE == 3 || std::is_same<T2, float2>::value, "binary32 g from the FP32 transform only");
     constexpr int L = 4 * M, PL = xy_reg_planes<M>(), WPP = M / 4, YS = L + 1;
     extern __shared__ __align__(16) unsigned char smem[];
     T2 *buf = (T2 *)smem;
+    if (STORE == 2) ngroups = 1;
     const int ntiles = B->off_xy[B->n] * ngroups;
     const int rb = xcd_remap(blockIdx.x, ntiles);
     const int tile = rb / ngroups, grp = rb - tile * ngroups;
@@ -1744,16 +1755,17 @@ __global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_inv_reg(const Cf
     for (int k2 = 0; k2 < 4; ++k2)
 #pragma unroll
         for (int e = 0; e < M / 4; ++e) Rn[(M / 4) * k2 + e] = ld_stream(src + ((M / 4) * j + e + M * k2) * L + r);
-    for (int f = 0; f < nfg; ++f, src += C.V, dst += C.V) {
-        T2 R[M];
+    // field f: the prefetched columns in, the next field's prefetched, the
+    // rows of this work-item out in R (y = r, x = 4 n2 + j)
+    auto field = [&](int f, int nf, T2 (&R)[M]) {
 #pragma unroll
         for (int n2 = 0; n2 < M; ++n2) R[n2] = Rn[n2];
-        if (f + 1 < nfg) {
+        if (f + 1 < nf) {
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2)
 #pragma unroll
                 for (int e = 0; e < M / 4; ++e)
-                    Rn[(M / 4) * k2 + e] = ld_stream(src + C.V + ((M / 4) * j + e + M * k2) * L + r);
+                    Rn[(M / 4) * k2 + e] = ld_stream(src + (size_t)(f + 1) * C.V + ((M / 4) * j + e + M * k2) * L + r);
         }
         line_backward<M>(R, tw, j);  // R[n2] = (y = 4 n2 + j, kx = r)
         if (f) __syncthreads();
@@ -1765,8 +1777,24 @@ __global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_inv_reg(const Cf
 #pragma unroll
             for (int e = 0; e < M / 4; ++e) R[(M / 4) * k2 + e] = sb[r * YS + (M / 4) * j + e + M * k2];
         line_backward<M>(R, tw, j);  // R[n2] = (y = r, x = 4 n2 + j)
+    };
+    if constexpr (STORE == 3) {
+        for (int f = 0; f < nfg; ++f) {
+            T2 R[M];
+            field(f, nfg, R);
 #pragma unroll
-        for (int n2 = 0; n2 < M; ++n2) dst[r * L + 4 * n2 + j] = R[n2];
+            for (int n2 = 0; n2 < M; ++n2) dst[(size_t)f * C.V + r * L + 4 * n2 + j] = R[n2];
+        }
+    } else {
+        T2 keep[3][M];  // fields 0..2 at this work-item's sites
+#pragma unroll
+        for (int f = 0; f < 3; ++f) field(f, kFields, keep[f]);
+        T2 R[M];
+        field(3, kFields, R);
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2)
+            m3_store12s(C.g12f, C.V, (int)(po + r * L + 4 * n2 + j),
+                        gauge_from_fields(keep[0][n2], keep[1][n2], keep[2][n2], R[n2]));
     }
 }
 
@@ -1851,7 +1879,8 @@ __global__ __launch_bounds__(TH) void k_fft_xy_inv_gauge(const Cfg *__restrict__
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
     if (P2 != xy_is_p2(C)) return;  // the other instance takes it
-    if (C.xy_reg && two_row == 3 && !g_override) return;  // k_fft_xy_inv_reg takes it
+    // k_fft_xy_inv_reg takes it
+    if (C.xy_reg && !g_override && (two_row == 3 || (two_row == 2 && std::is_same<T2, float2>::value))) return;
     const int t = tile - B->off_xy[c];
     const int n = C.xyQ * C.V2;
     const size_t site0 = (size_t)t * n;
@@ -2750,15 +2779,23 @@ static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
 {
     const size_t sh = lds2d<T2>(L.xy_cap, L.xy_tw2, L.xy_tw_total);
     int launched = 0;
-    if (!go && gauge_store_mode(L) == 3 && L.xy_reg_any) {
-        const int ng = L.xy_reg_groups;
-#define GF_XYR(M_)                                                                                                 \
+    // the register pass writes the filtered fields (FP64 link storage) or,
+    // from the FP32 transform, binary32 g (single-precision storage)
+    const int gm = gauge_store_mode(L);
+    if (!go && L.xy_reg_any && (gm == 3 || (gm == 2 && std::is_same<T2, float2>::value))) {
+#define GF_XYR(M_, S_, NG_)                                                                                        \
     if (L.xy_m & (1 << ((M_) / 4 - 2))) {                                                                          \
-        hipLaunchKernelGGL((k_fft_xy_inv_reg<T2, M_>), dim3(L.total_xy_tiles * ng), dim3(xy_reg_threads<M_>()),    \
-                           xy_reg_lds_elems<M_>() * sizeof(T2), L.stream, L.cfgs, L.batch, rd, ng);                \
+        hipLaunchKernelGGL((k_fft_xy_inv_reg<T2, M_, S_>), dim3(L.total_xy_tiles * (NG_)),                         \
+                           dim3(xy_reg_threads<M_>()), xy_reg_lds_elems<M_>() * sizeof(T2), L.stream, L.cfgs,       \
+                           L.batch, rd, NG_);                                                                      \
         ++launched;                                                                                                \
     }
-        GF_XYR(8) GF_XYR(12) GF_XYR(16)
+        if (gm == 3) {
+            const int ng = L.xy_reg_groups;
+            GF_XYR(8, 3, ng) GF_XYR(12, 3, ng) GF_XYR(16, 3, ng)
+        } else if constexpr (std::is_same<T2, float2>::value) {
+            GF_XYR(8, 2, 1) GF_XYR(12, 2, 1) GF_XYR(16, 2, 1)
+        }
 #undef GF_XYR
         if (!L.xy_lds_any) return hipGetLastError();
     }
@@ -2837,9 +2874,14 @@ static hipError_t set_lds_t()
         e = hipFuncSetAttribute((const void *)k_fft_xy_reg<T2, M_>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                 (int)(xy_reg_lds_elems<M_>() * sizeof(T2)));                                    \
     if (e == hipSuccess)                                                                                        \
-        e = hipFuncSetAttribute((const void *)k_fft_xy_inv_reg<T2, M_>,                                        \
+        e = hipFuncSetAttribute((const void *)k_fft_xy_inv_reg<T2, M_, 3>,                                     \
                                 hipFuncAttributeMaxDynamicSharedMemorySize,                                     \
-                                (int)(xy_reg_lds_elems<M_>() * sizeof(T2)));
+                                (int)(xy_reg_lds_elems<M_>() * sizeof(T2)));                                    \
+    if constexpr (std::is_same<T2, float2>::value)                                                              \
+        if (e == hipSuccess)                                                                                    \
+            e = hipFuncSetAttribute((const void *)k_fft_xy_inv_reg<T2, M_, 2>,                                 \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,                                 \
+                                    (int)(xy_reg_lds_elems<M_>() * sizeof(T2)));
     GF_XYR(8) GF_XYR(12) GF_XYR(16)
 #undef GF_XYR
     return e;

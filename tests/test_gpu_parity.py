@@ -571,6 +571,52 @@ def test_single_precision_storage_batch_equals_single(monkeypatch):
         assert np.array_equal(host(Ubs[k]), Uf)
 
 
+@pytest.mark.parametrize("dims", [(32, 32, 2, 4), (48, 48, 2, 2), (64, 64, 2, 2)])
+@pytest.mark.parametrize("reg", ["1", "0"])
+def test_single_precision_storage_register_xy_passes(monkeypatch, dims, reg):
+    """Single-precision storage with the FP32 transform on 32 x 32, 48 x 48
+    and 64 x 64 xy-planes, whose inverse (x, y) pass (GF_XY_REG=1) forms the
+    binary32 two-row g from the four fields in registers (0: the LDS-staged
+    pass): per-iteration F and theta against the oracle's run with the same
+    storage (FP64 transform), then the refinement down to 1e-15."""
+    monkeypatch.setenv("GF_XY_REG", reg)
+    U = random_links(dims, 0.3, 75)
+    n = 20
+    _, _, Fr, Tr = oracle.fix(dims, U, alpha=ALPHA, eps=-1.0, max_iter=n, f32_storage=True)
+    fx = GaugeFixer(dev(U), link_prec=1, fft_prec=1, fft_schedule=3)
+    fx.step(n)
+    Fh, Th = map(np.asarray, fx.history())
+    assert np.max(np.abs(Fh - Fr)) < 1e-6
+    assert np.max(np.abs(Th - Tr) / Tr) < 1e-3
+    Ud = dev(U)
+    fx = GaugeFixer(Ud, link_prec=1, fft_prec=1, refine_theta=1e-10, fft_schedule=3)
+    it, F, th = fx.fix_until(EPS, 5000)
+    assert th <= EPS
+    _, _, F64, _ = oracle.fix(dims, U, alpha=ALPHA, eps=EPS, max_iter=5000)
+    assert abs(F - F64[-1]) < 1e-6
+    Uf = host(Ud)
+    assert abs(oracle.plaquette(dims, Uf) - oracle.plaquette(dims, U)) < 1e-6
+
+
+def test_single_precision_storage_register_xy_batch_equals_single(monkeypatch):
+    monkeypatch.setenv("GF_TCHUNK", "2")
+    monkeypatch.setenv("GF_TCHUNK_BATCH", "2")
+    cases = [((32, 32, 2, 4), 0.3, 76), ((48, 48, 2, 2), 0.3, 77), ((8, 8, 8, 8), 0.3, 78)]
+    Us = [random_links(d, e, s) for d, e, s in cases]
+    single = []
+    for U in Us:
+        Ud = dev(U)
+        fx = GaugeFixer(Ud, link_prec=1, fft_prec=1, fft_schedule=3)
+        single.append((fx.fix_until(EPS, 5000), host(Ud)))
+    Ubs = [dev(U) for U in Us]
+    bx = BatchGaugeFixer(Ubs, link_prec=1, fft_prec=1, fft_schedule=3)
+    its, Fs, ths = bx.fix_until(EPS, 5000)
+    for k in range(len(cases)):
+        (it, F, th), Uf = single[k]
+        assert its[k] == it and Fs[k] == F and ths[k] == th, (k, its[k], it)
+        assert np.array_equal(host(Ubs[k]), Uf)
+
+
 # ---------------------------------------------------------------- z and t lines of 32, 48, 64 points
 
 # both axes in registers (64, 48 and 32 points, 4 x 4, 16 x 2, 6 x 8, 8 x 2
