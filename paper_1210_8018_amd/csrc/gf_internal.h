@@ -29,6 +29,16 @@ constexpr int kTileElems2D = 4096; // largest LDS tile (elements) of the 2D pass
 
 enum : int { kRunning = 0, kConverged = 1, kMaxIter = 2, kNonFinite = 3 };
 
+// Transform lines held in registers (k_fft_line, k_fft_xy_reg,
+// k_fft_xy_inv_reg): lengths 16 and 24 over two lanes of a wave, 32, 48 and
+// 64 over four; each length is its own kernel instance, marked by a bit.
+__host__ __device__ constexpr bool line_len_ok(int L) { return L == 16 || L == 24 || L == 32 || L == 48 || L == 64; }
+__host__ __device__ constexpr int line_lanes(int L) { return L >= 32 ? 4 : 2; }
+__host__ __device__ constexpr int line_len_bit(int L) { return L == 16 ? 0 : L == 24 ? 1 : L == 32 ? 2 : L == 48 ? 3 : 4; }
+// planes per tile of the register (x, y) passes: a tile stays within 4096
+// elements (the LDS-staged inverse pass serves the same tiles)
+__host__ __device__ constexpr int xy_reg_planes_for(int L) { return L == 16 ? 8 : L == 24 ? 4 : L == 32 ? 2 : 1; }
+
 // Transform schedules: which passes make up the 4D transform, scaling and
 // inverse (the scaling is always fused into the pass that completes the
 // forward transform).
@@ -98,8 +108,8 @@ struct Cfg {
     int xyPad;            // LDS elements added to every x-row of an xy tile (bank spreading)
     int ztPad;            // LDS elements added to every t-plane of a zt tile
     int zt_reg;           // the scaled (z, t) pass runs in k_fft_zt_reg (Lz = Lt = 32, ztP = 2 or 4)
-    int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 32, 48, 64)
-    int line[2];          // the 1D z (line[0]) / t (line[1]) passes run in k_fft_line (that extent 32, 48 or 64)
+    int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 16 to 64)
+    int line[2];          // the 1D z (line[0]) / t (line[1]) passes run in k_fft_line (that extent 16 to 64)
 };
 
 // Block-to-configuration maps for every launch shape of a batch: entry e
@@ -112,7 +122,7 @@ struct Batch {
     int off_fft[4][kMaxCfg + 1];
     int off_xy[kMaxCfg + 1];
     int off_zt[kMaxCfg + 1];
-    int off_line[2][kMaxCfg + 1];  // k_fft_line units (16 xy-sites x 4 lines) of the z and t passes
+    int off_line[2][kMaxCfg + 1];  // k_fft_line units (64 / line_lanes xy-sites x 4 lines) of the z and t passes
 };
 
 struct Launch {
@@ -136,9 +146,9 @@ struct Launch {
     int zt_reg_p;                  // xy-sites per tile of k_fft_zt_reg (2 or 4)
     int xy_reg_any, xy_lds_any;    // iteration's xy passes: some configuration in the register / LDS-staged ones
     int xy_reg_groups;             // work-groups per tile of the register xy passes
-    int xy_m;                      // their plane sizes present: bit 0 32, bit 1 48, bit 2 64
+    int xy_m;                      // their plane sizes present (bits line_len_bit)
     int total_line[2];             // k_fft_line units of the z and t passes (0: no configuration has them)
-    int line_m[2];                 // line lengths among them: bit 0 32, bit 1 48, bit 2 64
+    int line_m[2];                 // line lengths among them (bits line_len_bit)
     int max_lds_elems;    // 1D passes: largest P * L
     int fp32;             // transform precision
     int fused;            // iterations use the fused update + divergence kernel

@@ -1431,19 +1431,21 @@ __global__ __launch_bounds__(128 * P) __attribute__((amdgpu_waves_per_eu(P >= 4 
     }
 }
 
-// ============================================================ 1D z and t passes, lines of 32, 48 or 64 points in registers
-// For Lz or Lt of 32, 48 or 64 (C.line[]) the 1D passes along that axis (the
-// plain transform passes and the scaled t pass: forward, K(p), backward)
-// keep each line of L = 4 M points in four lanes of one wave (lane offsets
-// 0, 16, 32, 48; M = 8, 12 or 16 elements each): an M-point DFT per lane,
-// the twiddles exp(-2 pi i j k1 / L), the exchange among the four lanes by
-// the gfx950 lane-swap instructions, and 4-point DFTs. The 16 lanes of a row
-// are 16 consecutive xy-sites, so every global access of a wave is four runs
-// of 16 consecutive elements (256 bytes FP64, 128 bytes FP32); nothing goes
-// through LDS but the twiddle table. Elements are read and written at their
-// natural positions; only the registers hold the exchange order.
+// ============================================================ 1D z and t passes, lines of 16 to 64 points in registers
+// Where Lz or Lt is 16, 24, 32, 48 or 64 (C.line[]) the 1D passes along that
+// axis (the plain transform passes and the scaled t pass: forward, K(p),
+// backward) keep each line of L = LPL M points in LPL lanes of one wave
+// (LPL = 4 lanes at offsets 0, 16, 32, 48 for 32, 48 and 64 points; LPL = 2
+// at offsets 0 and 32 for 16 and 24 points), M elements each: an M-point DFT
+// per lane, the twiddles exp(-2 pi i j k1 / L), the exchange among the LPL
+// lanes by the gfx950 lane-swap instructions, and LPL-point DFTs. The 64/LPL
+// lanes of a row are consecutive xy-sites, so every global access of a wave
+// is LPL runs of 64/LPL consecutive elements (256 bytes FP64 for LPL = 4,
+// 512 for LPL = 2); nothing goes through LDS but the twiddle table. Elements
+// are read and written at their natural positions; only the registers hold
+// the exchange order.
 
-// R-point DFT (R = 2, 3, 4) of t[0..R-1] in place.
+// R-point DFT (R = 1, 2, 3, 4) of t[0..R-1] in place.
 template <int R, typename T2>
 __device__ __forceinline__ void dft_small(T2 (&t)[R], int sign)
 {
@@ -1451,122 +1453,151 @@ __device__ __forceinline__ void dft_small(T2 (&t)[R], int sign)
         dft2(t);
     else if constexpr (R == 3)
         dft3(t, sign);
-    else
+    else if constexpr (R == 4)
         dft4r(t[0], t[1], t[2], t[3], sign);
 }
 
-// M-point DFT (M = 4 R) of a[0..M-1] in place, natural order in and out,
-// sign -1 (forward) or +1; tw[e] = exp(-2 pi i e / 4M), so that
-// exp(-2 pi i m / M) = tw[4 m]. n = n0 + 4 n1, k = k1 + R k2:
-//   X[k1 + R k2] = sum_n0 exp(s 2 pi i n0 k2 / 4) exp(s 2 pi i n0 k1 / M)
-//                  sum_n1 a[n0 + 4 n1] exp(s 2 pi i n1 k1 / R).
-template <int M, typename T2>
+// M-point DFT (M = R1 R2 with R1 = 4, or 2 where 4 does not divide M) of
+// a[0..M-1] in place, natural order in and out, sign -1 (forward) or +1;
+// tw[e] = exp(-2 pi i e / (S M)), so that exp(-2 pi i m / M) = tw[S m].
+// n = n0 + R1 n1, k = k1 + R2 k2:
+//   X[k1 + R2 k2] = sum_n0 exp(s 2 pi i n0 k2 / R1) exp(s 2 pi i n0 k1 / M)
+//                   sum_n1 a[n0 + R1 n1] exp(s 2 pi i n1 k1 / R2).
+template <int M, int S, typename T2>
 __device__ __forceinline__ void dft_lane(T2 (&a)[M], const T2 *tw, int sign)
 {
-    constexpr int R = M / 4;
+    constexpr int R1 = (M % 4 == 0) ? 4 : 2, R2 = M / R1;
 #pragma unroll
-    for (int n0 = 0; n0 < 4; ++n0) {
-        T2 t[R];
+    for (int n0 = 0; n0 < R1; ++n0) {
+        T2 t[R2];
 #pragma unroll
-        for (int n1 = 0; n1 < R; ++n1) t[n1] = a[n0 + 4 * n1];
-        dft_small<R>(t, sign);
+        for (int n1 = 0; n1 < R2; ++n1) t[n1] = a[n0 + R1 * n1];
+        dft_small<R2>(t, sign);
 #pragma unroll
-        for (int k1 = 0; k1 < R; ++k1) a[n0 + 4 * k1] = t[k1];
+        for (int k1 = 0; k1 < R2; ++k1) a[n0 + R1 * k1] = t[k1];
     }
 #pragma unroll
-    for (int n0 = 1; n0 < 4; ++n0)
+    for (int n0 = 1; n0 < R1; ++n0)
 #pragma unroll
-        for (int k1 = 1; k1 < R; ++k1) {
-            T2 w = tw[4 * n0 * k1];
+        for (int k1 = 1; k1 < R2; ++k1) {
+            T2 w = tw[S * n0 * k1];
             if (sign > 0) w.y = -w.y;
-            a[n0 + 4 * k1] = t_mul(a[n0 + 4 * k1], w);
+            a[n0 + R1 * k1] = t_mul(a[n0 + R1 * k1], w);
         }
 #pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) dft4r(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3], sign);
-    // X[k] is at a[4 (k mod R) + k / R]: rename into natural order
+    for (int k1 = 0; k1 < R2; ++k1) {
+        T2 t[R1];
+#pragma unroll
+        for (int n0 = 0; n0 < R1; ++n0) t[n0] = a[R1 * k1 + n0];
+        dft_small<R1>(t, sign);
+#pragma unroll
+        for (int k2 = 0; k2 < R1; ++k2) a[R1 * k1 + k2] = t[k2];
+    }
+    // X[k] is at a[R1 (k mod R2) + k / R2]: rename into natural order
     T2 b[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) b[k] = a[4 * (k % R) + k / R];
+    for (int k = 0; k < M; ++k) b[k] = a[R1 * (k % R2) + k / R2];
 #pragma unroll
     for (int k = 0; k < M; ++k) a[k] = b[k];
 }
 
-// The exchange among the four lanes j = 2 a + c (lane offset 32 a + 16 c) of
-// a line: before, lane j holds Y_j[k1] at R[k1] (k1 = 0..M-1); after, lane j
-// holds Y_jj[(M/4) j + e] at R[(M/4) jj + e] (jj = 0..3, e < M/4). The lanes
-// 32 apart trade halves (R[m + (M/2) a'] = Y_{2 a' + c}[(M/2) a + m] after),
-// then the lanes 16 apart trade quarters of each half. Each step is its own
-// inverse.
-template <int M, typename T2>
+// The exchange among the LPL lanes j of a line: before, lane j holds Y_j[k1]
+// at R[k1] (k1 = 0..M-1); after, lane j holds Y_jj[(M/LPL) j + e] at
+// R[(M/LPL) jj + e] (jj < LPL, e < M/LPL). The lanes 32 apart trade halves
+// (R[m + (M/2) a'] = Y_{a' ...}[(M/2) a + m] after, a the lane's half); with
+// four lanes (j = 2 a + c, offset 32 a + 16 c) the lanes 16 apart then trade
+// quarters of each half. Each step is its own inverse.
+template <int LPL, int M, typename T2>
 __device__ __forceinline__ void line_exchange(T2 (&R)[M])
 {
 #pragma unroll
     for (int m = 0; m < M / 2; ++m) lane_swap<true>(R[m], R[m + M / 2]);
+    if constexpr (LPL == 4) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int e = 0; e < M / 4; ++e) lane_swap<false>(R[(M / 2) * a + e], R[(M / 2) * a + M / 4 + e]);
+            for (int e = 0; e < M / 4; ++e) lane_swap<false>(R[(M / 2) * a + e], R[(M / 2) * a + M / 4 + e]);
+    }
 }
-template <int M, typename T2>
+template <int LPL, int M, typename T2>
 __device__ __forceinline__ void line_exchange_back(T2 (&R)[M])
 {
+    if constexpr (LPL == 4) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int e = 0; e < M / 4; ++e) lane_swap<false>(R[(M / 2) * a + e], R[(M / 2) * a + M / 4 + e]);
+            for (int e = 0; e < M / 4; ++e) lane_swap<false>(R[(M / 2) * a + e], R[(M / 2) * a + M / 4 + e]);
+    }
 #pragma unroll
     for (int m = 0; m < M / 2; ++m) lane_swap<true>(R[m], R[m + M / 2]);
 }
 
-// Forward L-point DFT (L = 4 M) of a line spread over four lanes, n = 4 n2 + j:
-//   X[k1 + M k2] = sum_j exp(-2 pi i j k2 / 4) exp(-2 pi i j k1 / L) Y_j[k1],
-//   Y_j[k1] = sum_n2 x[4 n2 + j] exp(-2 pi i n2 k1 / M).
-// On entry R[n2] = x[4 n2 + j]; on return R[(M/4) k2 + e] = X[(M/4) j + e + M k2].
-template <int M, typename T2>
+// The LPL-point DFTs over jj of the exchanged layout, R[(M/LPL) jj + e].
+template <int LPL, int M, typename T2>
+__device__ __forceinline__ void line_dft_across(T2 (&R)[M], int sign)
+{
+    constexpr int Q = M / LPL;
+#pragma unroll
+    for (int e = 0; e < Q; ++e) {
+        T2 t[LPL];
+#pragma unroll
+        for (int jj = 0; jj < LPL; ++jj) t[jj] = R[Q * jj + e];
+        dft_small<LPL>(t, sign);
+#pragma unroll
+        for (int jj = 0; jj < LPL; ++jj) R[Q * jj + e] = t[jj];
+    }
+}
+
+// Forward L-point DFT (L = LPL M) of a line spread over LPL lanes,
+// n = LPL n2 + j:
+//   X[k1 + M k2] = sum_j exp(-2 pi i j k2 / LPL) exp(-2 pi i j k1 / L) Y_j[k1],
+//   Y_j[k1] = sum_n2 x[LPL n2 + j] exp(-2 pi i n2 k1 / M).
+// On entry R[n2] = x[LPL n2 + j]; on return R[(M/LPL) k2 + e] =
+// X[(M/LPL) j + e + M k2].
+template <int LPL, int M, typename T2>
 __device__ __forceinline__ void line_forward(T2 (&R)[M], const T2 *tw, int j)
 {
-    dft_lane<M>(R, tw, -1);
+    dft_lane<M, LPL>(R, tw, -1);
 #pragma unroll
     for (int k1 = 1; k1 < M; ++k1) R[k1] = t_mul(R[k1], tw[j * k1]);
-    line_exchange<M>(R);
-#pragma unroll
-    for (int e = 0; e < M / 4; ++e) dft4r(R[e], R[M / 4 + e], R[M / 2 + e], R[3 * M / 4 + e], -1);
+    line_exchange<LPL, M>(R);
+    line_dft_across<LPL, M>(R, -1);
 }
 
 // Backward L-point DFT (unnormalised) from the layout line_forward leaves,
-// back to R[n2] = x[4 n2 + j]:
-//   x[4 n2 + j] = sum_k1 exp(2 pi i n2 k1 / M) exp(2 pi i j k1 / L) Z_k1[j],
-//   Z_k1[j] = sum_k2 X[k1 + M k2] exp(2 pi i j k2 / 4).
-template <int M, typename T2>
+// back to R[n2] = x[LPL n2 + j]:
+//   x[LPL n2 + j] = sum_k1 exp(2 pi i n2 k1 / M) exp(2 pi i j k1 / L) Z_k1[j],
+//   Z_k1[j] = sum_k2 X[k1 + M k2] exp(2 pi i j k2 / LPL).
+template <int LPL, int M, typename T2>
 __device__ __forceinline__ void line_backward(T2 (&R)[M], const T2 *tw, int j)
 {
-#pragma unroll
-    for (int e = 0; e < M / 4; ++e) dft4r(R[e], R[M / 4 + e], R[M / 2 + e], R[3 * M / 4 + e], +1);
-    line_exchange_back<M>(R);
+    line_dft_across<LPL, M>(R, +1);
+    line_exchange_back<LPL, M>(R);
 #pragma unroll
     for (int k1 = 1; k1 < M; ++k1) {
         T2 w = tw[j * k1];
         w.y = -w.y;
         R[k1] = t_mul(R[k1], w);
     }
-    dft_lane<M>(R, tw, +1);
+    dft_lane<M, LPL>(R, tw, +1);
 }
 
 // One 1D pass along z (axis 2) or t (axis 3) over the configurations whose
-// lines along that axis run in registers (C.line[axis - 2]) and are 4 M long
-// (the instances for the other lengths take the rest). KIND 0: forward; 1:
-// backward; 2 (t only): forward, K(p) (natural order), backward. Work-group
-// u of a configuration takes field u mod nfields of the lines of unit
-// v = u / nfields: xy-sites 16 (v mod V2/16) + q, and per wave w the line at
-// other coordinate 4 (v div V2/16) + w (t for a z pass, z for a t pass). The
-// fields of a unit are consecutive work-groups (one XCD), so the t pass's
-// K(p) lines come from L2 after the first.
-template <typename T2, int M, int KIND>
+// lines along that axis run in registers (C.line[axis - 2]) and are LPL M
+// long (the instances for the other lengths take the rest). KIND 0:
+// forward; 1: backward; 2 (t only): forward, K(p) (natural order), backward.
+// With NQ = 64 / LPL lanes per row, work-group u of a configuration takes
+// field u mod nfields of the lines of unit v = u / nfields: xy-sites
+// NQ (v mod V2/NQ) + q, and per wave w the line at other coordinate
+// 4 (v div V2/NQ) + w (t for a z pass, z for a t pass). The fields of a unit
+// are consecutive work-groups (one XCD), so the t pass's K(p) lines come
+// from L2 after the first.
+template <typename T2, int LPL, int M, int KIND>
 __global__ __launch_bounds__(256) void k_fft_line(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
                                                   int axis, void *fields_override, int nfields, int respect_done)
 {
     using T = typename Cx<T2>::T;
-    constexpr int L = 4 * M;
+    constexpr int L = LPL * M, NQ = 64 / LPL, Q = M / LPL;
     __shared__ T2 tw[L];
     const int u = xcd_remap(blockIdx.x, gridDim.x);
     const int *off = B->off_line[axis - 2];
@@ -1577,14 +1608,14 @@ __global__ __launch_bounds__(256) void k_fft_line(const Cfg *__restrict__ cfgs, 
     const int lu = u - off[c] * nfields;
     const int field = lu % nfields, v = lu / nfields;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = lane & 15, j = lane >> 4;
-    const int nxyb = C.V2 >> 4;
+    const int q = lane % NQ, j = lane / NQ;
+    const int nxyb = C.V2 / NQ;
     const int xyb = v % nxyb, other = 4 * (v / nxyb) + w;
     // element l of this work-item's line at g[q + l S]: a base common to the
     // wave and a 32-bit offset per work-item (below 2^31 elements for every
     // lattice that fits the device)
     const unsigned S = axis == 2 ? (unsigned)C.V2 : (unsigned)C.V3;
-    const size_t wbase = (size_t)16 * xyb + (size_t)other * (axis == 2 ? (size_t)C.V3 : (size_t)C.V2);
+    const size_t wbase = (size_t)NQ * xyb + (size_t)other * (axis == 2 ? (size_t)C.V3 : (size_t)C.V2);
     const unsigned o = (unsigned)q;
     if (threadIdx.x < L) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[axis])[threadIdx.x];
     __syncthreads();
@@ -1592,76 +1623,75 @@ __global__ __launch_bounds__(256) void k_fft_line(const Cfg *__restrict__ cfgs, 
     T2 R[M];
     if constexpr (KIND == 1) {
 #pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2)
+        for (int k2 = 0; k2 < LPL; ++k2)
 #pragma unroll
-            for (int e = 0; e < M / 4; ++e)
-                R[(M / 4) * k2 + e] = g[o + (unsigned)((M / 4) * j + e + M * k2) * S];
-        line_backward<M>(R, tw, j);
+            for (int e = 0; e < Q; ++e) R[Q * k2 + e] = g[o + (unsigned)(Q * j + e + M * k2) * S];
+        line_backward<LPL, M>(R, tw, j);
 #pragma unroll
-        for (int n2 = 0; n2 < M; ++n2) g[o + (unsigned)(4 * n2 + j) * S] = R[n2];
+        for (int n2 = 0; n2 < M; ++n2) g[o + (unsigned)(LPL * n2 + j) * S] = R[n2];
     } else {
 #pragma unroll
-        for (int n2 = 0; n2 < M; ++n2) R[n2] = g[o + (unsigned)(4 * n2 + j) * S];
-        line_forward<M>(R, tw, j);
+        for (int n2 = 0; n2 < M; ++n2) R[n2] = g[o + (unsigned)(LPL * n2 + j) * S];
+        line_forward<LPL, M>(R, tw, j);
         if constexpr (KIND == 2) {
-            // K(p) of momentum (xy-site, kz, kt = (M/4) j + e + M k2)
+            // K(p) of momentum (xy-site, kz, kt = Q j + e + M k2)
             const T *__restrict__ Km = (const T *)C.kmom + wbase;
 #pragma unroll
-            for (int k2 = 0; k2 < 4; ++k2)
+            for (int k2 = 0; k2 < LPL; ++k2)
 #pragma unroll
-                for (int e = 0; e < M / 4; ++e) {
-                    const T k = Km[o + (unsigned)((M / 4) * j + e + M * k2) * S];
-                    R[(M / 4) * k2 + e].x *= k;
-                    R[(M / 4) * k2 + e].y *= k;
+                for (int e = 0; e < Q; ++e) {
+                    const T k = Km[o + (unsigned)(Q * j + e + M * k2) * S];
+                    R[Q * k2 + e].x *= k;
+                    R[Q * k2 + e].y *= k;
                 }
-            line_backward<M>(R, tw, j);
+            line_backward<LPL, M>(R, tw, j);
 #pragma unroll
-            for (int n2 = 0; n2 < M; ++n2) g[o + (unsigned)(4 * n2 + j) * S] = R[n2];
+            for (int n2 = 0; n2 < M; ++n2) g[o + (unsigned)(LPL * n2 + j) * S] = R[n2];
         } else {
 #pragma unroll
-            for (int k2 = 0; k2 < 4; ++k2)
+            for (int k2 = 0; k2 < LPL; ++k2)
 #pragma unroll
-                for (int e = 0; e < M / 4; ++e)
-                    g[o + (unsigned)((M / 4) * j + e + M * k2) * S] = R[(M / 4) * k2 + e];
+                for (int e = 0; e < Q; ++e) g[o + (unsigned)(Q * j + e + M * k2) * S] = R[Q * k2 + e];
         }
     }
 }
 
-// ============================================================ (x, y) passes, 32, 48 and 64 point planes, radix stages in registers
-// For Lx = Ly = L = 4 M (32, 48 or 64) the iteration's (x, y) passes keep
-// each x-line (row) and then each y-line (column) of a plane in four lanes
-// of one wave, M elements per lane, with the line transforms above; LDS only
-// moves the plane from rows to columns. A tile is PL consecutive planes of
-// one field (PL = 2 for 32 points, 1 for 48 and 64: a tile stays within the
-// 4096 elements of the LDS-staged inverse pass, which serves the same tiles
-// for the stage calls and single-precision storage), M/4 waves per plane;
-// work-item (w, q, j) holds row, then column, r = 16 (w mod M/4) + q of plane
-// w / (M/4). Global memory stays in natural order, so the (z, t) and 1D
-// passes and K(p) see the layout the LDS-staged passes produce. The LDS
-// row stride L + 1 puts the 16 lanes of an access on distinct banks.
+// ============================================================ (x, y) passes, 16 to 64 point planes, radix stages in registers
+// For Lx = Ly = L of 16, 24, 32, 48 or 64 the iteration's (x, y) passes keep
+// each x-line (row) and then each y-line (column) of a plane in LPL lanes of
+// one wave, M = L / LPL elements per lane, with the line transforms above;
+// LDS only moves the planes from rows to columns. A tile is PL consecutive
+// planes of one field (8 of 16 points, 4 of 24, 2 of 32, 1 of 48 and 64:
+// a tile stays within the 4096 elements of the LDS-staged inverse pass,
+// which serves the same tiles for the stage calls and for single-precision
+// storage with the FP64 transform), PL L / NQ waves (NQ = 64 / LPL lines
+// per wave); work-item (w, q, j) holds line rr = NQ w + q of the tile: row,
+// then column, r = rr mod L of plane rr / L. Global memory stays in natural
+// order, so the (z, t) and 1D passes and K(p) see the layout the LDS-staged
+// passes produce. The LDS row stride L + 1 spreads the lanes of an access
+// over the banks.
+template <int L>
+__host__ __device__ constexpr int xy_reg_threads() { return xy_reg_planes_for(L) * L * line_lanes(L); }
+// dynamic LDS: the tile (rows of L + 1 elements) and the L twiddles
+template <int L>
+__host__ __device__ constexpr int xy_reg_lds_elems() { return xy_reg_planes_for(L) * L * (L + 1) + L; }
+
 // g = 1 + Delta~ from the four packed filtered fields, projected (defined
 // with the gauge step below)
 template <typename T2>
 __device__ __forceinline__ M3 gauge_from_fields(T2 a, T2 b, T2 d, T2 e);
 
-template <int M>
-__host__ __device__ constexpr int xy_reg_planes() { return M == 8 ? 2 : 1; }
-template <int M>
-__host__ __device__ constexpr int xy_reg_threads() { return xy_reg_planes<M>() * (M / 4) * 64; }
-// dynamic LDS: the tile (rows of L + 1 elements) and the L twiddles
-template <int M>
-__host__ __device__ constexpr int xy_reg_lds_elems() { return xy_reg_planes<M>() * 4 * M * (4 * M + 1) + 4 * M; }
-
 // Forward (x, y) transform of the four fields (kFields / ngroups of them per
-// work-group, the next one prefetched): rows x = 4 n2 + j of row y = r, then
-// columns y = 4 n2 + j of column kx = r. fold != 0: the work-groups past the
+// work-group, the next one prefetched): rows x = LPL n2 + j of row y = r, then
+// columns y = LPL n2 + j of column kx = r. fold != 0: the work-groups past the
 // tiles do the final reduction of the previous update, as k_fft_xy's.
-template <typename T2, int M>
-__global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_reg(const Cfg *__restrict__ cfgs,
+template <typename T2, int L>
+__global__ __launch_bounds__(xy_reg_threads<L>()) void k_fft_xy_reg(const Cfg *__restrict__ cfgs,
                                                                    const Batch *__restrict__ B, int respect_done,
                                                                    int ngroups, int fold)
 {
-    constexpr int L = 4 * M, PL = xy_reg_planes<M>(), WPP = M / 4, YS = L + 1;
+    constexpr int LPL = line_lanes(L), M = L / LPL, Q = M / LPL, NQ = 64 / LPL, PL = xy_reg_planes_for(L);
+    constexpr int YS = L + 1;
     extern __shared__ __align__(16) unsigned char smem[];
     T2 *buf = (T2 *)smem;
     const int ntiles = B->off_xy[B->n] * ngroups;
@@ -1679,8 +1709,8 @@ __global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_reg(const Cfg *_
     if (respect_done && C.ctrl->done) return;
     if (!C.xy_reg || C.dims[0] != L) return;  // the LDS-staged pass or another length's instance takes it
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = lane & 15, j = lane >> 4;
-    const int pl = w / WPP, r = 16 * (w % WPP) + q;
+    const int q = lane % NQ, j = lane / NQ;
+    const int rr = NQ * w + q, pl = rr / L, r = rr - pl * L;
     T2 *tw = buf + PL * L * YS;  // exp(-2 pi i e / L), the same table for x and y
     if (threadIdx.x < L) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[0])[threadIdx.x];
     __syncthreads();
@@ -1688,29 +1718,29 @@ __global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_reg(const Cfg *_
     T2 *__restrict__ sb = buf + pl * L * YS;
     T2 Rn[M];
 #pragma unroll
-    for (int n2 = 0; n2 < M; ++n2) Rn[n2] = plane[r * L + 4 * n2 + j];
+    for (int n2 = 0; n2 < M; ++n2) Rn[n2] = plane[r * L + LPL * n2 + j];
     for (int f = 0; f < nfg; ++f, plane += C.V) {
         T2 R[M];
 #pragma unroll
         for (int n2 = 0; n2 < M; ++n2) R[n2] = Rn[n2];
         if (f + 1 < nfg) {
 #pragma unroll
-            for (int n2 = 0; n2 < M; ++n2) Rn[n2] = plane[C.V + r * L + 4 * n2 + j];
+            for (int n2 = 0; n2 < M; ++n2) Rn[n2] = plane[C.V + r * L + LPL * n2 + j];
         }
-        line_forward<M>(R, tw, j);  // R[(M/4) k2 + e] = (y = r, kx = (M/4) j + e + M k2)
-        if (f) __syncthreads();     // the previous field's reads of the tile are done
+        line_forward<LPL, M>(R, tw, j);  // R[Q k2 + e] = (y = r, kx = Q j + e + M k2)
+        if (f) __syncthreads();          // the previous field's reads of the tile are done
 #pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2)
+        for (int k2 = 0; k2 < LPL; ++k2)
 #pragma unroll
-            for (int e = 0; e < M / 4; ++e) sb[r * YS + (M / 4) * j + e + M * k2] = R[(M / 4) * k2 + e];
+            for (int e = 0; e < Q; ++e) sb[r * YS + Q * j + e + M * k2] = R[Q * k2 + e];
         __syncthreads();
 #pragma unroll
-        for (int n2 = 0; n2 < M; ++n2) R[n2] = sb[(4 * n2 + j) * YS + r];
-        line_forward<M>(R, tw, j);  // R[(M/4) k2 + e] = (ky = (M/4) j + e + M k2, kx = r)
+        for (int n2 = 0; n2 < M; ++n2) R[n2] = sb[(LPL * n2 + j) * YS + r];
+        line_forward<LPL, M>(R, tw, j);  // R[Q k2 + e] = (ky = Q j + e + M k2, kx = r)
 #pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2)
+        for (int k2 = 0; k2 < LPL; ++k2)
 #pragma unroll
-            for (int e = 0; e < M / 4; ++e) plane[((M / 4) * j + e + M * k2) * L + r] = R[(M / 4) * k2 + e];
+            for (int e = 0; e < Q; ++e) plane[(Q * j + e + M * k2) * L + r] = R[Q * k2 + e];
     }
 }
 
@@ -1722,13 +1752,14 @@ __global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_reg(const Cfg *_
 // stored in binary32 two-row form (what the LDS-staged pass's gauge store
 // mode 2 writes). Columns first (the layout line_backward takes, read from
 // natural order), then rows.
-template <typename T2, int M, int STORE>
-__global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_inv_reg(const Cfg *__restrict__ cfgs,
+template <typename T2, int L, int STORE>
+__global__ __launch_bounds__(xy_reg_threads<L>()) void k_fft_xy_inv_reg(const Cfg *__restrict__ cfgs,
                                                                        const Batch *__restrict__ B,
                                                                        int respect_done, int ngroups)
 {
     static_assert(STORE == 3 || std::is_same<T2, float2>::value, "binary32 g from the FP32 transform only");
-    constexpr int L = 4 * M, PL = xy_reg_planes<M>(), WPP = M / 4, YS = L + 1;
+    constexpr int LPL = line_lanes(L), M = L / LPL, Q = M / LPL, NQ = 64 / LPL, PL = xy_reg_planes_for(L);
+    constexpr int YS = L + 1;
     extern __shared__ __align__(16) unsigned char smem[];
     T2 *buf = (T2 *)smem;
     if (STORE == 2) ngroups = 1;
@@ -1741,8 +1772,8 @@ __global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_inv_reg(const Cf
     if (respect_done && C.ctrl->done) return;
     if (!C.xy_reg || C.dims[0] != L) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = lane & 15, j = lane >> 4;
-    const int pl = w / WPP, r = 16 * (w % WPP) + q;
+    const int q = lane % NQ, j = lane / NQ;
+    const int rr = NQ * w + q, pl = rr / L, r = rr - pl * L;
     T2 *tw = buf + PL * L * YS;
     if (threadIdx.x < L) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[0])[threadIdx.x];
     __syncthreads();
@@ -1752,38 +1783,38 @@ __global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_inv_reg(const Cf
     T2 *__restrict__ sb = buf + pl * L * YS;
     T2 Rn[M];
 #pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2)
+    for (int k2 = 0; k2 < LPL; ++k2)
 #pragma unroll
-        for (int e = 0; e < M / 4; ++e) Rn[(M / 4) * k2 + e] = ld_stream(src + ((M / 4) * j + e + M * k2) * L + r);
+        for (int e = 0; e < Q; ++e) Rn[Q * k2 + e] = ld_stream(src + (Q * j + e + M * k2) * L + r);
     // field f: the prefetched columns in, the next field's prefetched, the
-    // rows of this work-item out in R (y = r, x = 4 n2 + j)
+    // rows of this work-item out in R (y = r, x = LPL n2 + j)
     auto field = [&](int f, int nf, T2 (&R)[M]) {
 #pragma unroll
         for (int n2 = 0; n2 < M; ++n2) R[n2] = Rn[n2];
         if (f + 1 < nf) {
 #pragma unroll
-            for (int k2 = 0; k2 < 4; ++k2)
+            for (int k2 = 0; k2 < LPL; ++k2)
 #pragma unroll
-                for (int e = 0; e < M / 4; ++e)
-                    Rn[(M / 4) * k2 + e] = ld_stream(src + (size_t)(f + 1) * C.V + ((M / 4) * j + e + M * k2) * L + r);
+                for (int e = 0; e < Q; ++e)
+                    Rn[Q * k2 + e] = ld_stream(src + (size_t)(f + 1) * C.V + (Q * j + e + M * k2) * L + r);
         }
-        line_backward<M>(R, tw, j);  // R[n2] = (y = 4 n2 + j, kx = r)
+        line_backward<LPL, M>(R, tw, j);  // R[n2] = (y = LPL n2 + j, kx = r)
         if (f) __syncthreads();
 #pragma unroll
-        for (int n2 = 0; n2 < M; ++n2) sb[(4 * n2 + j) * YS + r] = R[n2];
+        for (int n2 = 0; n2 < M; ++n2) sb[(LPL * n2 + j) * YS + r] = R[n2];
         __syncthreads();
 #pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2)
+        for (int k2 = 0; k2 < LPL; ++k2)
 #pragma unroll
-            for (int e = 0; e < M / 4; ++e) R[(M / 4) * k2 + e] = sb[r * YS + (M / 4) * j + e + M * k2];
-        line_backward<M>(R, tw, j);  // R[n2] = (y = r, x = 4 n2 + j)
+            for (int e = 0; e < Q; ++e) R[Q * k2 + e] = sb[r * YS + Q * j + e + M * k2];
+        line_backward<LPL, M>(R, tw, j);  // R[n2] = (y = r, x = LPL n2 + j)
     };
     if constexpr (STORE == 3) {
         for (int f = 0; f < nfg; ++f) {
             T2 R[M];
             field(f, nfg, R);
 #pragma unroll
-            for (int n2 = 0; n2 < M; ++n2) dst[(size_t)f * C.V + r * L + 4 * n2 + j] = R[n2];
+            for (int n2 = 0; n2 < M; ++n2) dst[(size_t)f * C.V + r * L + LPL * n2 + j] = R[n2];
         }
     } else {
         T2 keep[3][M];  // fields 0..2 at this work-item's sites
@@ -1793,7 +1824,7 @@ __global__ __launch_bounds__(xy_reg_threads<M>()) void k_fft_xy_inv_reg(const Cf
         field(3, kFields, R);
 #pragma unroll
         for (int n2 = 0; n2 < M; ++n2)
-            m3_store12s(C.g12f, C.V, (int)(po + r * L + 4 * n2 + j),
+            m3_store12s(C.g12f, C.V, (int)(po + r * L + LPL * n2 + j),
                         gauge_from_fields(keep[0][n2], keep[1][n2], keep[2][n2], R[n2]));
     }
 }
@@ -2630,31 +2661,27 @@ hipError_t launch_fft_axis(const Launch &L, int axis, int sign, int mode, void *
 {
     if (axis >= 2 && L.total_line[axis - 2] > 0) {
         const dim3 lg(L.total_line[axis - 2] * nfields), lb(256);
-        const int lm = L.line_m[axis - 2];  // line lengths present: bit 0 32, bit 1 48, bit 2 64
-#define GF_LINE_K(T2_, M_, K_)                                                                                \
-    hipLaunchKernelGGL((k_fft_line<T2_, M_, K_>), lg, lb, 0, L.stream, L.cfgs, L.batch, axis, fields_override, \
-                       nfields, respect_done)
-#define GF_LINE_M(T2_, M_)                \
-    do {                                  \
-        if (mode == 1)                    \
-            GF_LINE_K(T2_, M_, 2);        \
-        else if (sign < 0)                \
-            GF_LINE_K(T2_, M_, 0);        \
-        else                              \
-            GF_LINE_K(T2_, M_, 1);        \
-    } while (0)
-#define GF_LINE(T2_)                           \
-    do {                                       \
-        if (lm & 1) GF_LINE_M(T2_, 8);         \
-        if (lm & 2) GF_LINE_M(T2_, 12);        \
-        if (lm & 4) GF_LINE_M(T2_, 16);        \
-    } while (0)
-        if (L.fp32)
-            GF_LINE(float2);
-        else
-            GF_LINE(double2);
+        const int lm = L.line_m[axis - 2];  // line lengths present (line_len_bit)
+#define GF_LINE_K(T2_, L_, K_)                                                                                    \
+    hipLaunchKernelGGL((k_fft_line<T2_, line_lanes(L_), (L_) / line_lanes(L_), K_>), lg, lb, 0, L.stream, L.cfgs, \
+                       L.batch, axis, fields_override, nfields, respect_done)
+#define GF_LINE_L(T2_, L_)                    \
+    if (lm & (1 << line_len_bit(L_))) {       \
+        if (mode == 1)                        \
+            GF_LINE_K(T2_, L_, 2);            \
+        else if (sign < 0)                    \
+            GF_LINE_K(T2_, L_, 0);            \
+        else                                  \
+            GF_LINE_K(T2_, L_, 1);            \
+    }
+#define GF_LINE(T2_) GF_LINE_L(T2_, 16) GF_LINE_L(T2_, 24) GF_LINE_L(T2_, 32) GF_LINE_L(T2_, 48) GF_LINE_L(T2_, 64)
+        if (L.fp32) {
+            GF_LINE(float2)
+        } else {
+            GF_LINE(double2)
+        }
 #undef GF_LINE
-#undef GF_LINE_M
+#undef GF_LINE_L
 #undef GF_LINE_K
     }
     if (L.total_fft_tiles[axis] == 0) return hipGetLastError();  // every configuration in k_fft_line
@@ -2713,16 +2740,16 @@ static hipError_t run_xy(const Launch &L, int nf, int sign, void *fo, int rd, in
         const int ng = L.xy_reg_groups;
         // one instance per plane size present; the first with at least
         // kReduceLanes work-items carries the fold
-#define GF_XYR(M_)                                                                                               \
-    if (L.xy_m & (1 << ((M_) / 4 - 2))) {                                                                        \
-        const int f = xy_reg_threads<M_>() >= kReduceLanes ? fold : 0;                                           \
+#define GF_XYR(L_)                                                                                               \
+    if (L.xy_m & (1 << line_len_bit(L_))) {                                                                      \
+        const int f = xy_reg_threads<L_>() >= kReduceLanes ? fold : 0;                                           \
         if (f) fold = 0;                                                                                         \
-        hipLaunchKernelGGL((k_fft_xy_reg<T2, M_>), dim3(L.total_xy_tiles * ng + (f ? L.ncfg : 0)),               \
-                           dim3(xy_reg_threads<M_>()), xy_reg_lds_elems<M_>() * sizeof(T2), L.stream, L.cfgs,     \
+        hipLaunchKernelGGL((k_fft_xy_reg<T2, L_>), dim3(L.total_xy_tiles * ng + (f ? L.ncfg : 0)),               \
+                           dim3(xy_reg_threads<L_>()), xy_reg_lds_elems<L_>() * sizeof(T2), L.stream, L.cfgs,     \
                            L.batch, rd, ng, f);                                                                  \
         ++launched;                                                                                              \
     }
-        GF_XYR(8) GF_XYR(12) GF_XYR(16)
+        GF_XYR(16) GF_XYR(24) GF_XYR(32) GF_XYR(48) GF_XYR(64)
 #undef GF_XYR
         if (!L.xy_lds_any) return hipGetLastError();
     }
@@ -2783,18 +2810,18 @@ static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
     // from the FP32 transform, binary32 g (single-precision storage)
     const int gm = gauge_store_mode(L);
     if (!go && L.xy_reg_any && (gm == 3 || (gm == 2 && std::is_same<T2, float2>::value))) {
-#define GF_XYR(M_, S_, NG_)                                                                                        \
-    if (L.xy_m & (1 << ((M_) / 4 - 2))) {                                                                          \
-        hipLaunchKernelGGL((k_fft_xy_inv_reg<T2, M_, S_>), dim3(L.total_xy_tiles * (NG_)),                         \
-                           dim3(xy_reg_threads<M_>()), xy_reg_lds_elems<M_>() * sizeof(T2), L.stream, L.cfgs,       \
+#define GF_XYR(L_, S_, NG_)                                                                                        \
+    if (L.xy_m & (1 << line_len_bit(L_))) {                                                                        \
+        hipLaunchKernelGGL((k_fft_xy_inv_reg<T2, L_, S_>), dim3(L.total_xy_tiles * (NG_)),                         \
+                           dim3(xy_reg_threads<L_>()), xy_reg_lds_elems<L_>() * sizeof(T2), L.stream, L.cfgs,       \
                            L.batch, rd, NG_);                                                                      \
         ++launched;                                                                                                \
     }
         if (gm == 3) {
             const int ng = L.xy_reg_groups;
-            GF_XYR(8, 3, ng) GF_XYR(12, 3, ng) GF_XYR(16, 3, ng)
+            GF_XYR(16, 3, ng) GF_XYR(24, 3, ng) GF_XYR(32, 3, ng) GF_XYR(48, 3, ng) GF_XYR(64, 3, ng)
         } else if constexpr (std::is_same<T2, float2>::value) {
-            GF_XYR(8, 2, 1) GF_XYR(12, 2, 1) GF_XYR(16, 2, 1)
+            GF_XYR(16, 2, 1) GF_XYR(24, 2, 1) GF_XYR(32, 2, 1) GF_XYR(48, 2, 1) GF_XYR(64, 2, 1)
         }
 #undef GF_XYR
         if (!L.xy_lds_any) return hipGetLastError();
@@ -2811,11 +2838,17 @@ static hipError_t run_xyg(const Launch &L, int rd, double2 *go)
 }
 
 // The fold needs a work-group of kReduceLanes work-items: a register xy
-// instance of 32- or 64-point planes (256), or the LDS-staged pass with
+// instance of 16-, 32- or 64-point planes (256), or the LDS-staged pass with
 // work-groups that large.
 bool can_fold_reduce(const Launch &L)
 {
-    const bool reg = L.xy_reg_any && (L.xy_m & 5);
+    int big = 0;  // register instances of 256 work-items
+    if (xy_reg_threads<16>() >= kReduceLanes) big |= 1 << line_len_bit(16);
+    if (xy_reg_threads<24>() >= kReduceLanes) big |= 1 << line_len_bit(24);
+    if (xy_reg_threads<32>() >= kReduceLanes) big |= 1 << line_len_bit(32);
+    if (xy_reg_threads<48>() >= kReduceLanes) big |= 1 << line_len_bit(48);
+    if (xy_reg_threads<64>() >= kReduceLanes) big |= 1 << line_len_bit(64);
+    const bool reg = L.xy_reg_any && (L.xy_m & big);
     const bool lds = L.xy_lds_any && L.xy_th >= kReduceLanes;
     return reg || lds;
 }
@@ -2869,20 +2902,20 @@ static hipError_t set_lds_t()
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_fft_zt_reg<T2, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(zt_reg_lds_total<8>() * sizeof(T2)));
-#define GF_XYR(M_)                                                                                              \
+#define GF_XYR(L_)                                                                                              \
     if (e == hipSuccess)                                                                                        \
-        e = hipFuncSetAttribute((const void *)k_fft_xy_reg<T2, M_>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                (int)(xy_reg_lds_elems<M_>() * sizeof(T2)));                                    \
+        e = hipFuncSetAttribute((const void *)k_fft_xy_reg<T2, L_>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                (int)(xy_reg_lds_elems<L_>() * sizeof(T2)));                                    \
     if (e == hipSuccess)                                                                                        \
-        e = hipFuncSetAttribute((const void *)k_fft_xy_inv_reg<T2, M_, 3>,                                     \
+        e = hipFuncSetAttribute((const void *)k_fft_xy_inv_reg<T2, L_, 3>,                                     \
                                 hipFuncAttributeMaxDynamicSharedMemorySize,                                     \
-                                (int)(xy_reg_lds_elems<M_>() * sizeof(T2)));                                    \
+                                (int)(xy_reg_lds_elems<L_>() * sizeof(T2)));                                    \
     if constexpr (std::is_same<T2, float2>::value)                                                              \
         if (e == hipSuccess)                                                                                    \
-            e = hipFuncSetAttribute((const void *)k_fft_xy_inv_reg<T2, M_, 2>,                                 \
+            e = hipFuncSetAttribute((const void *)k_fft_xy_inv_reg<T2, L_, 2>,                                 \
                                     hipFuncAttributeMaxDynamicSharedMemorySize,                                 \
-                                    (int)(xy_reg_lds_elems<M_>() * sizeof(T2)));
-    GF_XYR(8) GF_XYR(12) GF_XYR(16)
+                                    (int)(xy_reg_lds_elems<L_>() * sizeof(T2)));
+    GF_XYR(16) GF_XYR(24) GF_XYR(32) GF_XYR(48) GF_XYR(64)
 #undef GF_XYR
     return e;
 }

@@ -266,14 +266,14 @@ struct KTime {
 // with zt_reg work-groups per tile (1, 2 or 4, the four fields split among
 // them); 0: the LDS-staged pass.
 // xy_reg: the same for the iteration's (x, y) passes of configurations with
-// Lx = Ly = 32 (k_fft_xy_reg, k_fft_xy_inv_reg).
+// Lx = Ly of 16, 24, 32, 48 or 64 (k_fft_xy_reg, k_fft_xy_inv_reg).
 struct Tiles {
     int xy_target = 1024, xy_ept = 4;
     int zt_target = 4096, zt_ept = 8;
     int zt_reg = 2;
     int zt_reg_p = 4;  // xy-sites per tile of the register (z, t) pass (2, 4 or 8)
     int xy_reg = 1;
-    int line_reg = 1;  // 1D z and t passes of 32-, 48- and 64-point lines in k_fft_line
+    int line_reg = 1;  // 1D z and t passes of 16- to 64-point lines in k_fft_line
     bool operator==(const Tiles &o) const
     {
         return xy_target == o.xy_target && xy_ept == o.xy_ept && zt_target == o.zt_target && zt_ept == o.zt_ept &&
@@ -282,21 +282,21 @@ struct Tiles {
 };
 
 // Whether a configuration's scaled (z, t) pass can run in k_fft_zt_reg, and
-// its (x, y) passes in k_fft_xy_reg / k_fft_xy_inv_reg (tiles of two planes).
+// its (x, y) passes in k_fft_xy_reg / k_fft_xy_inv_reg (tiles of
+// xy_reg_planes_for(Lx) planes).
 bool zt_reg_fits(const Cfg &C, int P) { return C.dims[2] == 32 && C.dims[3] == 32 && C.V2 % P == 0; }
-// planes per tile of the register (x, y) passes: 2 for 32 points, 1 for 48 and 64
-int xy_reg_planes_of(int L) { return L == 32 ? 2 : 1; }
 bool xy_reg_fits(const Cfg &C)
 {
     const int L = C.dims[0];
-    return L == C.dims[1] && (L == 32 || L == 48 || L == 64) && (C.dims[2] * C.dims[3]) % xy_reg_planes_of(L) == 0;
+    return L == C.dims[1] && line_len_ok(L) && (C.dims[2] * C.dims[3]) % xy_reg_planes_for(L) == 0;
 }
-// and its 1D pass along axis 2 + a in k_fft_line (a line of 32, 48 or 64
-// points; 16 xy-sites per row of a wave, 4 lines of the other axis per unit)
+// and its 1D pass along axis 2 + a in k_fft_line (a line of 16 to 64
+// points; 64 / line_lanes xy-sites per row of a wave, 4 lines of the other
+// axis per unit)
 bool line_fits(const Cfg &C, int a)
 {
     const int L = C.dims[2 + a], other = C.dims[3 - a];
-    return (L == 32 || L == 48 || L == 64) && C.V2 % 16 == 0 && other % 4 == 0;
+    return line_len_ok(L) && C.V2 % (64 / line_lanes(L)) == 0 && other % 4 == 0;
 }
 
 struct gf_ctx_s {
@@ -764,8 +764,10 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
         // k_fft_line: 16 xy-sites times 4 lines per unit
         for (int mu = 0; mu < 4; ++mu)
             b.off_fft[mu][e + 1] = b.off_fft[mu][e] + ((mu >= 2 && C.line[mu - 2]) ? 0 : C.ax[mu].ntile);
-        b.off_line[0][e + 1] = b.off_line[0][e] + (C.line[0] ? (C.V2 / 16) * (C.dims[3] / 4) : 0);
-        b.off_line[1][e + 1] = b.off_line[1][e] + (C.line[1] ? (C.V2 / 16) * (C.dims[2] / 4) : 0);
+        for (int a = 0; a < 2; ++a) {
+            const int nq = 64 / line_lanes(C.dims[2 + a]);
+            b.off_line[a][e + 1] = b.off_line[a][e] + (C.line[a] ? (C.V2 / nq) * (C.dims[3 - a] / 4) : 0);
+        }
         b.off_xy[e + 1] = b.off_xy[e] + C.nxy;
         b.off_zt[e + 1] = b.off_zt[e] + C.nzt;
     }
@@ -777,7 +779,7 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
         L.total_line[a] = b.off_line[a][b.n];
         L.line_m[a] = 0;
         for (int e = 0; e < b.n; ++e)
-            if (c->cfg[list[e]].line[a]) L.line_m[a] |= 1 << (c->cfg[list[e]].dims[2 + a] / 16 - 2);
+            if (c->cfg[list[e]].line[a]) L.line_m[a] |= 1 << line_len_bit(c->cfg[list[e]].dims[2 + a]);
     }
     L.total_zt_tiles = b.off_zt[b.n];
     L.ncfg = b.n;
@@ -806,7 +808,7 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
         // every 1D z and t pass (those of schedules 1 and 2, and the plain
         // transform calls)
         for (int a = 0; a < 2; ++a) C.line[a] = (tl.line_reg && line_fits(C, a)) ? 1 : 0;
-        if (C.xy_reg) C.xyQ = xy_reg_planes_of(C.dims[0]);  // the register passes' tile
+        if (C.xy_reg) C.xyQ = xy_reg_planes_for(C.dims[0]);  // the register passes' tile
         C.nxy = xy_feasible(C.dims) ? (C.dims[2] * C.dims[3]) / C.xyQ : 0;
         C.ztP = zt_feasible(C.dims) ? plan_ztP(C.dims, tl.zt_target) : 1;
         // the register pass's tile: zt_reg_p xy-sites (one width per
@@ -854,7 +856,7 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
     c->L.xy_reg_groups = tl.xy_reg > 0 ? tl.xy_reg : 1;
     c->L.xy_m = 0;
     for (int k = 0; k < c->ncfg; ++k)
-        if (c->cfg[k].xy_reg) c->L.xy_m |= 1 << (c->cfg[k].dims[0] / 16 - 2);
+        if (c->cfg[k].xy_reg) c->L.xy_m |= 1 << line_len_bit(c->cfg[k].dims[0]);
     for (int k = 0; k < c->ncfg; ++k) {
         const Cfg &C = c->cfg[k];
         if (C.nzt) (C.zt_reg ? c->L.zt_reg_any : c->L.zt_lds_any) = 1;

@@ -571,11 +571,11 @@ def test_single_precision_storage_batch_equals_single(monkeypatch):
         assert np.array_equal(host(Ubs[k]), Uf)
 
 
-@pytest.mark.parametrize("dims", [(32, 32, 2, 4), (48, 48, 2, 2), (64, 64, 2, 2)])
+@pytest.mark.parametrize("dims", [(16, 16, 2, 4), (24, 24, 2, 2), (32, 32, 2, 4), (48, 48, 2, 2), (64, 64, 2, 2)])
 @pytest.mark.parametrize("reg", ["1", "0"])
 def test_single_precision_storage_register_xy_passes(monkeypatch, dims, reg):
-    """Single-precision storage with the FP32 transform on 32 x 32, 48 x 48
-    and 64 x 64 xy-planes, whose inverse (x, y) pass (GF_XY_REG=1) forms the
+    """Single-precision storage with the FP32 transform on 16 x 16 to 64 x 64
+    xy-planes, whose inverse (x, y) pass (GF_XY_REG=1) forms the
     binary32 two-row g from the four fields in registers (0: the LDS-staged
     pass): per-iteration F and theta against the oracle's run with the same
     storage (FP64 transform), then the refinement down to 1e-15."""
@@ -617,13 +617,16 @@ def test_single_precision_storage_register_xy_batch_equals_single(monkeypatch):
         assert np.array_equal(host(Ubs[k]), Uf)
 
 
-# ---------------------------------------------------------------- z and t lines of 32, 48, 64 points
+# ---------------------------------------------------------------- z and t lines of 16 to 64 points
 
-# both axes in registers (64, 48 and 32 points, 4 x 4, 16 x 2, 6 x 8, 8 x 2
-# xy-planes); lines of different lengths in one configuration; only the t
-# lines (z = 12) or only the z lines (t = 8)
+# both axes in registers (64, 48 and 32 points over four lanes: 4 x 4,
+# 16 x 2, 6 x 8, 8 x 2 xy-planes; 24 and 16 points over two lanes: 8 x 4,
+# 16 x 2); lines of different lengths and lane counts in one configuration;
+# only the t lines (z = 12; z = 16 on 4 x 4 xy-planes, fewer than the 32
+# xy-sites a two-lane row needs) or only the z lines (t = 8)
 LINE_SHAPES = [(4, 4, 64, 64), (16, 2, 64, 64), (6, 8, 64, 64), (4, 4, 48, 48), (8, 2, 32, 32),
-               (4, 4, 32, 64), (8, 2, 12, 48), (4, 4, 64, 8)]
+               (4, 4, 32, 64), (8, 2, 12, 48), (4, 4, 64, 8), (8, 4, 24, 24), (16, 2, 16, 16),
+               (4, 8, 16, 32), (4, 4, 16, 32), (8, 4, 24, 8)]
 
 
 @pytest.mark.parametrize("dims", LINE_SHAPES)
@@ -704,6 +707,34 @@ def test_register_plane_sizes_batch_equals_single_runs(monkeypatch, sched, prec)
         assert np.array_equal(host(Ubs[k]), Uf)
 
 
+@pytest.mark.parametrize("sched", [2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_lane_lines_batch_equals_single_runs(monkeypatch, sched, prec):
+    """A batch of members whose register lines span two lanes (16 x 16 and
+    24 x 24 xy-planes; 16- and 24-point z and t lines) beside four-lane ones
+    (32-point t lines, 32 x 32 planes) and an LDS-staged member: the register
+    (x, y) passes run their 16-, 24- and 32-point instances in one iteration,
+    the 16-point one carrying the folded reduction; every member bitwise
+    equal to its own context's run."""
+    monkeypatch.setenv("GF_TCHUNK", "2")
+    monkeypatch.setenv("GF_TCHUNK_BATCH", "2")
+    cases = [((16, 16, 2, 4), 0.3, 81), ((24, 24, 4, 4), 0.3, 82), ((8, 4, 24, 24), 0.3, 83),
+             ((4, 8, 16, 32), 0.35, 84), ((32, 32, 2, 2), 0.3, 85), ((8, 8, 8, 8), 0.3, 86)]
+    Us = [random_links(d, e, s) for d, e, s in cases]
+    single = []
+    for U in Us:
+        Ud = dev(U)
+        fx = GaugeFixer(Ud, fft_prec=prec, fft_schedule=sched)
+        single.append((fx.fix_until(EPS, 5000), host(Ud)))
+    Ubs = [dev(U) for U in Us]
+    bx = BatchGaugeFixer(Ubs, fft_prec=prec, fft_schedule=sched)
+    its, Fs, ths = bx.fix_until(EPS, 5000)
+    for k in range(len(cases)):
+        (it, F, th), Uf = single[k]
+        assert its[k] == it and Fs[k] == F and ths[k] == th, (k, its[k], it)
+        assert np.array_equal(host(Ubs[k]), Uf)
+
+
 # ---------------------------------------------------------------- 32 x 32 (z, t) planes
 
 ZT32_SHAPES = [(2, 2, 32, 32), (4, 2, 32, 32), (6, 4, 32, 32), (8, 8, 32, 32), (16, 2, 32, 32)]
@@ -744,16 +775,19 @@ def test_zt_register_pass_trajectory(monkeypatch, dims, seed, P):
 
 
 # 32 x 32 planes (two per tile; 32 x 32 x 3 x 3 has an odd plane count and
-# takes the LDS-staged passes), 48 x 48 and 64 x 64 planes (one per tile)
+# takes the LDS-staged passes), 48 x 48 and 64 x 64 planes (one per tile),
+# 16 x 16 (eight per tile) and 24 x 24 planes (four per tile; 3 x 3 planes
+# of either take the LDS-staged passes)
 XY32_SHAPES = [(32, 32, 2, 2), (32, 32, 4, 2), (32, 32, 6, 4), (32, 32, 3, 2), (32, 32, 3, 3), (48, 48, 2, 2),
-               (48, 48, 3, 3), (64, 64, 2, 2), (64, 64, 3, 3)]
+               (48, 48, 3, 3), (64, 64, 2, 2), (64, 64, 3, 3), (16, 16, 2, 4), (16, 16, 4, 6), (16, 16, 3, 3),
+               (24, 24, 2, 2), (24, 24, 4, 3), (24, 24, 3, 3)]
 
 
 @pytest.mark.parametrize("dims", XY32_SHAPES)
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("sched,reg", [(3, "1"), (3, "2"), (2, "1"), (3, "0")])
 def test_xy_register_pass_matches_oracle(monkeypatch, dims, prec, sched, reg):
-    """The forward (x, y) pass of 32 x 32, 48 x 48 and 64 x 64 planes with its
+    """The forward (x, y) pass of 16 x 16 to 64 x 64 planes with its
     radix stages in registers (GF_XY_REG = work-groups per tile) or
     LDS-staged (0), beside
     the (z, t) passes of schedule 3 or the 1D z and t passes of schedule 2:
@@ -769,7 +803,8 @@ def test_xy_register_pass_matches_oracle(monkeypatch, dims, prec, sched, reg):
 
 @pytest.mark.parametrize("dims,seed,reg", [((32, 32, 4, 2), 58, "1"), ((32, 32, 3, 2), 59, "2"),
                                            ((32, 32, 6, 4), 60, "1"), ((48, 48, 2, 2), 67, "1"),
-                                           ((64, 64, 3, 2), 68, "2")])
+                                           ((64, 64, 3, 2), 68, "2"), ((16, 16, 2, 4), 79, "1"),
+                                           ((24, 24, 4, 3), 80, "2")])
 def test_xy_register_pass_trajectory(monkeypatch, dims, seed, reg):
     """Both register (x, y) passes in the iteration (the inverse one writes the
     filtered fields the fused pass forms g from) against the oracle."""
