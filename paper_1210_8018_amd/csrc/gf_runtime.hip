@@ -98,40 +98,42 @@ int plan_tile(const int dims[4], int tile[3], int ntile[3])
     return (dims[0] * dims[1] * dims[2] + kSiteBlock - 1) / kSiteBlock;
 }
 
-// Blocks of the t-marching kernels: nb3 site sets times `tch` t-slices. More
-// slices per block save the re-read of the t-neighbour at the first slice;
-// fewer give more blocks. `target` is the number of blocks wanted: 1024 (four
-// per CU, two resident at a time) for FP64 link storage, 512 for binary32
-// storage (at 32^4, 4 slices per block instead of 8 make the FP64-storage
-// pass 2 % faster and the binary32-storage pass 3 % slower). Of the counts
-// at or above the target, the first whose last round of `resident` blocks
-// (those the device holds at once) is at least 90 % full is taken, else the
-// fullest: at 48^4 the 3456 blocks of 6 slices (96 %) run the fused pass 7 %
-// faster than the 1296 of 16 slices (84 %). A walk is at most 8 slices: at
-// 64^4 the 8192 blocks of 8 slices run it 2.7 % faster than the 1024 that
-// walk all 64.
+// Blocks of the t-marching kernels: nb3 site sets times `tch` t-slices, a
+// walk of at most 8 slices. Each walk re-reads its first slice's
+// t-neighbours (about 0.23 of a slice's traffic); the blocks run in rounds
+// of `resident` (two per CU). The walk length taken minimises
+//   rounds * (tch + 0.23) * (1.05 if a single round, FP64 link storage),
+// largest tch on ties: a single round leaves the CUs idle while its slowest
+// blocks finish, and with FP64 links that costs more than the walk-end
+// re-reads a second round adds. Measured picks (FP64 fused pass): 32^4 4
+// slices (1024 blocks; 8 slices, one round, 2 % slower; binary32 storage
+// the other way round, 8 slices 3 % faster); 24^4 3 slices (432 blocks, one
+// round: 72 us against 77 for 1 slice and 82 for 4); 16^3 x 32 1 slice (512
+// blocks; 2 slices 4 % slower); 48^4 6 slices (3456 blocks; 8 and 4 slices
+// 7 % and 5 % slower); 64^4 8 slices (8192 blocks; one walk over all 64
+// slices 2.7 % slower).
 constexpr int kMaxTchunk = 8;
-int plan_tchunk(const int dims[4], int nb3, int target, int resident)
+int plan_tchunk(const int dims[4], int nb3, bool f64_links, int resident)
 {
     const char *env = getenv("GF_TCHUNK");
     if (env) {
         const int t = atoi(env);
         if (t >= 1 && dims[3] % t == 0) return t;
     }
-    int best = 0;
-    double best_fill = -1.0;
-    for (int nT = 1; nT <= dims[3]; ++nT) {
-        const long long nb = (long long)nb3 * nT;
-        if (dims[3] % nT || nb < target || dims[3] / nT > kMaxTchunk) continue;
+    int best = 1;
+    double best_cost = 1e300;
+    for (int t = 1; t <= kMaxTchunk && t <= dims[3]; ++t) {
+        if (dims[3] % t) continue;
+        const long long nb = (long long)nb3 * (dims[3] / t);
         const long long rounds = (nb + resident - 1) / resident;
-        const double fill = (double)nb / (double)(rounds * resident);
-        if (fill >= 0.9) return dims[3] / nT;
-        if (fill > best_fill) {
-            best_fill = fill;
-            best = nT;
+        double cost = (double)rounds * (t + 0.23);
+        if (rounds == 1 && f64_links) cost *= 1.05;
+        if (cost <= best_cost) {
+            best_cost = cost;
+            best = t;
         }
     }
-    return best ? dims[3] / best : 1;
+    return best;
 }
 
 // In a batch every configuration's marching blocks take about the same
@@ -761,7 +763,7 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
         b.off_site[e + 1] = b.off_site[e] + C.nblk_site;
         b.off_march[e + 1] = b.off_march[e] + C.nblk_march;
         // the z and t passes of a configuration's lines in registers run in
-        // k_fft_line: 16 xy-sites times 4 lines per unit
+        // k_fft_line: 64 / line_lanes xy-sites times 4 lines per unit
         for (int mu = 0; mu < 4; ++mu)
             b.off_fft[mu][e + 1] = b.off_fft[mu][e] + ((mu >= 2 && C.line[mu - 2]) ? 0 : C.ax[mu].ntile);
         for (int a = 0; a < 2; ++a) {
@@ -1040,7 +1042,7 @@ gf_status choose_schedule(gf_ctx c, int requested)
         cands.push_back({kSched1D, t});
     }
     // (x, y) choices: LDS tiles (target, elements per work-item), or the
-    // register passes with 1 or 2 work-groups per tile; (z, t) choices: LDS
+    // register passes with 1, 2 or 4 work-groups per tile; (z, t) choices: LDS
     // tiles, or the register pass with 1, 2 or 4 (the LDS tile then serves
     // only the plain transform calls)
     std::vector<Tiles> xs, zs;
@@ -1053,7 +1055,7 @@ gf_status choose_schedule(gf_ctx c, int requested)
             xs.push_back(t);
         }
     if (any_xreg)
-        for (int g : {1, 2}) {
+        for (int g : {1, 2, 4}) {
             Tiles t;
             t.xy_reg = g;
             xs.push_back(t);
@@ -1222,7 +1224,7 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         C.nblk_site = (C.V + kSiteBlock - 1) / kSiteBlock;
         C.nb3 = plan_tile(p.dims, C.tile, C.ntile);
         C.tch = (ncfg > 1) ? plan_tchunk_batch(p.dims)
-                           : plan_tchunk(p.dims, C.nb3, p.link_prec ? 512 : 1024, kMarchResidentPerCU * ncu);
+                           : plan_tchunk(p.dims, C.nb3, p.link_prec == 0, kMarchResidentPerCU * ncu);
         C.nblk_march = C.nb3 * (p.dims[3] / C.tch);
         C.U = (double2 *)links[k];
         C.U12[0] = (double2 *)(c->ws + l.links12a);

@@ -601,7 +601,8 @@ def test_single_precision_storage_register_xy_passes(monkeypatch, dims, reg):
 def test_single_precision_storage_register_xy_batch_equals_single(monkeypatch):
     monkeypatch.setenv("GF_TCHUNK", "2")
     monkeypatch.setenv("GF_TCHUNK_BATCH", "2")
-    cases = [((32, 32, 2, 4), 0.3, 76), ((48, 48, 2, 2), 0.3, 77), ((8, 8, 8, 8), 0.3, 78)]
+    cases = [((32, 32, 2, 4), 0.3, 76), ((48, 48, 2, 2), 0.3, 77), ((8, 8, 8, 8), 0.3, 78),
+             ((16, 16, 2, 4), 0.3, 87), ((24, 24, 2, 2), 0.3, 88)]
     Us = [random_links(d, e, s) for d, e, s in cases]
     single = []
     for U in Us:
@@ -785,7 +786,7 @@ XY32_SHAPES = [(32, 32, 2, 2), (32, 32, 4, 2), (32, 32, 6, 4), (32, 32, 3, 2), (
 
 @pytest.mark.parametrize("dims", XY32_SHAPES)
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("sched,reg", [(3, "1"), (3, "2"), (2, "1"), (3, "0")])
+@pytest.mark.parametrize("sched,reg", [(3, "1"), (3, "2"), (3, "4"), (2, "1"), (3, "0")])
 def test_xy_register_pass_matches_oracle(monkeypatch, dims, prec, sched, reg):
     """The forward (x, y) pass of 16 x 16 to 64 x 64 planes with its
     radix stages in registers (GF_XY_REG = work-groups per tile) or
