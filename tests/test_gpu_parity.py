@@ -306,6 +306,32 @@ def test_site_sets_give_bitwise_equal_links(monkeypatch, dims, tiles, kw):
         assert np.array_equal(run(env), ref), env
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(fft_prec=1, link_prec=1)])
+def test_walk_lengths_give_bitwise_equal_links(monkeypatch, kw):
+    """The walk length of the marching blocks (t-slices per block, chosen by
+    the planner from the lattice shape) changes only the order of the partial
+    sums of F and theta: the links after a fixed number of updates are
+    bitwise equal for every walk length that divides Lt, and F after them
+    agrees to rounding."""
+    dims = (8, 8, 4, 24)
+    U = random_links(dims, 0.3, 5)
+
+    def run(t):
+        monkeypatch.setenv("GF_TCHUNK", str(t))
+        Ud = dev(U)
+        fx = GaugeFixer(Ud, **kw)
+        fx.step(6)
+        F, _ = fx.functional()
+        del fx
+        return host(Ud), F
+
+    ref, Fref = run(1)
+    for t in (2, 3, 4, 6, 8):
+        Ut, Ft = run(t)
+        assert np.array_equal(Ut, ref), t
+        assert abs(Ft - Fref) < 1e-14, t
+
+
 def test_step_equals_fix_prefix():
     """Calls of every length give the trajectory of one uninterrupted run,
     bitwise: the first update of a call reads the caller's links, the last of
