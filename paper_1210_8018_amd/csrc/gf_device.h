@@ -411,6 +411,38 @@ __device__ __forceinline__ void block_sum2(dd &a, dd &b, dd *lds)
     }
 }
 
+// block_sum2 over each of the NB groups of kSiteBlock work-items of a block
+// (waves summed in the same order as a block of kSiteBlock); the result of
+// group h is valid in its first work-item. `lds` must hold 2 * (blockDim.x /
+// 64) dd entries.
+template <int NB>
+__device__ __forceinline__ void block_sum2_sets(dd &a, dd &b, dd *lds)
+{
+    if constexpr (NB == 1) {
+        block_sum2(a, b, lds);
+    } else {
+        constexpr int WPS = kSiteBlock / 64;  // waves per set
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (lane == 0) {
+            lds[2 * w] = a;
+            lds[2 * w + 1] = b;
+        }
+        __syncthreads();
+        if (threadIdx.x % kSiteBlock == 0) {
+            const int w0 = w;  // first wave of this set
+            dd x = lds[2 * w0], y = lds[2 * w0 + 1];
+            for (int k = 1; k < WPS; ++k) {
+                x = dd_add(x, lds[2 * (w0 + k)]);
+                y = dd_add(y, lds[2 * (w0 + k) + 1]);
+            }
+            a = x;
+            b = y;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- integers
 __device__ __forceinline__ bool is_p2(int v) { return (v & (v - 1)) == 0; }
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }

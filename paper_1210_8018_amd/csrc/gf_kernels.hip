@@ -2047,11 +2047,14 @@ __device__ __forceinline__ float2 *links12<float2>(const Cfg &C, int b) { return
 //
 // Slot of the site (xn, yn, zn), flat index s3n, among the work-items of
 // marching block b3 (march_xyz's numbering), or -1 if another block owns it.
+// With NB site sets per block (linear sets only for NB > 1), b3 is the
+// block's first set and the slot counts over all NB kSiteBlock of them.
+template <int NB = 1>
 __device__ __forceinline__ int block_slot(const Cfg &C, int b3, int s3n, int xn, int yn, int zn)
 {
-    if (C.tile[0] == 0) {
+    if (NB > 1 || C.tile[0] == 0) {
         const int o = s3n - b3 * kSiteBlock;
-        return (o >= 0 && o < kSiteBlock) ? o : -1;
+        return (o >= 0 && o < NB * kSiteBlock) ? o : -1;
     }
     const int tx = C.tile[0], ty = C.tile[1], tz = C.tile[2];
     const int bx = b3 % C.ntile[0], rb = b3 / C.ntile[0];
@@ -2108,15 +2111,20 @@ __device__ __forceinline__ void store_new_link(S2 *__restrict__ base, int V, int
 // from the caller's array, the last update of a gf_step call writes the new
 // ones there, so that a call copies no links in or out; the updates in
 // between use the two-row buffers (these instances run inside the graphs).
-template <typename T2, bool RU, typename S2, bool SRC = false, bool DST = false>
-__global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__restrict__ cfgs,
-                                                               const Batch *__restrict__ B)
+// NB: site sets per block (1, or 2 for linear sets: the neighbour exchange
+// spans both, each set keeps its own partial sums).
+template <typename T2, bool RU, typename S2, bool SRC = false, bool DST = false, int NB = 1>
+__global__ __launch_bounds__(kSiteBlock * NB) void k_update_delta_x(const Cfg *__restrict__ cfgs,
+                                                                    const Batch *__restrict__ B)
 {
     static_assert(!(SRC || DST) || std::is_same<S2, double2>::value, "caller layout: FP64 storage only");
-    __shared__ dd red[2 * (kSiteBlock / 64)];
-    __shared__ double2 sg[6][kSiteBlock];    // g(x), rows 0 and 1, of the block's sites at this slice
-    __shared__ double sa[2][9][kSiteBlock];  // U'_mu(x) - U'_mu(x)^dag (AH order), mu = x, y
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    constexpr int NS = kSiteBlock * NB;
+    __shared__ dd red[2 * (NS / 64)];
+    __shared__ double2 sg[6][NS];    // g(x), rows 0 and 1, of the block's sites at this slice
+    __shared__ double sa[2][9][NS];  // U'_mu(x) - U'_mu(x)^dag (AH order), mu = x, y
+    // NB > 1: the block takes NB consecutive site sets of one walk (each
+    // configuration's nb3 a multiple of NB), each with its own partial sums
+    const int blk = xcd_remap(blockIdx.x, gridDim.x) * NB;
     const int c = find_cfg(B->off_march, B->n, blk);
     const Cfg &C = cfgs[B->idx[c]];
     const Ctrl *ct = C.ctrl;
@@ -2131,13 +2139,16 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
     S2 *__restrict__ Un = DST ? (S2 *)C.U : links12<S2>(C, ct->cur ^ 1);
     const bool reunit = C.reunit_every > 0 && ct->ru_now;
     if (reunit != RU) return;
-    const int lb = blk - B->off_march[c];
-    const int b3 = lb % C.nb3, tc = lb / C.nb3;
     const int tid = threadIdx.x;
+    const int half = NB > 1 ? tid / kSiteBlock : 0, ltid = NB > 1 ? tid % kSiteBlock : tid;
+    const int lb0 = blk - B->off_march[c];  // the block's first site set
+    const int lb = lb0 + half;
+    const int b3 = lb % C.nb3, tc = lb / C.nb3;
+    const int b3f = lb0 % C.nb3;
     // where the links are after this update (read by k_unpack_links only)
-    if (lb == 0 && tid == 0) C.ctrl->in_caller = DST ? 1 : 0;
+    if (lb == 0 && ltid == 0) C.ctrl->in_caller = DST ? 1 : 0;
     int x, y, z;
-    const bool inside = march_xyz(C, b3, tid, x, y, z);
+    const bool inside = march_xyz(C, b3, ltid, x, y, z);
     const int Lx = C.dims[0], Ly = C.dims[1], Lz = C.dims[2], Lt = C.dims[3];
     const int s3 = x + Lx * (y + Ly * z);
     int fwd3[3], back3[3], sf[2], sb[2];
@@ -2150,10 +2161,10 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
     back3[0] = s3 + (xb - x);
     back3[1] = s3 + (yb - y) * Lx;
     back3[2] = s3 + (zb - z) * C.V2;
-    sf[0] = inside ? block_slot(C, b3, fwd3[0], xf, y, z) : -1;
-    sf[1] = inside ? block_slot(C, b3, fwd3[1], x, yf, z) : -1;
-    sb[0] = inside ? block_slot(C, b3, back3[0], xb, y, z) : -1;
-    sb[1] = inside ? block_slot(C, b3, back3[1], x, yb, z) : -1;
+    sf[0] = inside ? block_slot<NB>(C, b3f, fwd3[0], xf, y, z) : -1;
+    sf[1] = inside ? block_slot<NB>(C, b3f, fwd3[1], x, yf, z) : -1;
+    sb[0] = inside ? block_slot<NB>(C, b3f, back3[0], xb, y, z) : -1;
+    sb[1] = inside ? block_slot<NB>(C, b3f, back3[1], x, yb, z) : -1;
     const int t0 = tc * C.tch;
     dd fs = {0.0, 0.0}, ts = {0.0, 0.0};
     // Slice t forms g(x, t) and completes the site (x, t - 1): its forward
@@ -2290,8 +2301,8 @@ __global__ __launch_bounds__(kSiteBlock) void k_update_delta_x(const Cfg *__rest
             gp = gx;
         }
     }
-    block_sum2(fs, ts, red);
-    if (threadIdx.x == 0) {
+    block_sum2_sets<NB>(fs, ts, red);
+    if (ltid == 0) {
         double *p = C.partials + (size_t)lb * 4;
         p[0] = fs.hi;
         p[1] = fs.lo;
@@ -2940,14 +2951,23 @@ hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override)
 
 hipError_t launch_update_delta(const Launch &L, int link_io)
 {
-    const dim3 grid(L.total_march_blocks), blk(kSiteBlock);
+    const int nb = L.march_pair ? 2 : 1;
+    const dim3 grid(L.total_march_blocks / nb), blk(kSiteBlock * nb);
     if (L.any_reunit) hipLaunchKernelGGL(k_mark_reunit, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.batch);
-#define GF_UPD(T2_, S2_, SRC_, DST_)                                                                                  \
-    do {                                                                                                              \
-        hipLaunchKernelGGL((k_update_delta_x<T2_, false, S2_, SRC_, DST_>), grid, blk, 0, L.stream, L.cfgs, L.batch); \
-        if (L.any_reunit)                                                                                             \
-            hipLaunchKernelGGL((k_update_delta_x<T2_, true, S2_, SRC_, DST_>), grid, blk, 0, L.stream, L.cfgs,        \
-                               L.batch);                                                                              \
+#define GF_UPD_NB(T2_, S2_, SRC_, DST_, NB_)                                                                       \
+    do {                                                                                                           \
+        hipLaunchKernelGGL((k_update_delta_x<T2_, false, S2_, SRC_, DST_, NB_>), grid, blk, 0, L.stream, L.cfgs,   \
+                           L.batch);                                                                               \
+        if (L.any_reunit)                                                                                          \
+            hipLaunchKernelGGL((k_update_delta_x<T2_, true, S2_, SRC_, DST_, NB_>), grid, blk, 0, L.stream, L.cfgs, \
+                               L.batch);                                                                           \
+    } while (0)
+#define GF_UPD(T2_, S2_, SRC_, DST_)               \
+    do {                                           \
+        if (nb == 2)                               \
+            GF_UPD_NB(T2_, S2_, SRC_, DST_, 2);    \
+        else                                       \
+            GF_UPD_NB(T2_, S2_, SRC_, DST_, 1);    \
     } while (0)
 #define GF_UPD_IO(T2_)                                    \
     do {                                                  \
@@ -2972,6 +2992,7 @@ hipError_t launch_update_delta(const Launch &L, int link_io)
     }
 #undef GF_UPD_IO
 #undef GF_UPD
+#undef GF_UPD_NB
     return hipGetLastError();
 }
 

@@ -775,6 +775,28 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
     }
     L.total_site_blocks = b.off_site[b.n];
     L.total_march_blocks = b.off_march[b.n];
+    // Two site sets per block of the fused pass (512 work-items, one block
+    // per CU instead of two of 256): where a set of kSiteBlock consecutive
+    // sites is fewer than 8 whole x-rows (Lx = 24, 48, 64: 10.7, 5.3 and 4
+    // rows), the doubled set halves the share of sites whose y-neighbour
+    // another block owns, which pays for the barriers of 8 instead of 4 waves
+    // (fused pass 2.3 %, 2.6 % and 4.3 % faster at 24^4, 48^4 and 64^4); at
+    // 32^4 (8 rows) it is 1.7 % slower. Linear sets with an even number per
+    // walk in every configuration of the launch, and every configuration of
+    // that kind; GF_PAIR=0 / 1 turns it off / on wherever it can run. The
+    // links and the partial sums are bitwise those of one set per block.
+    {
+        const char *env = getenv("GF_PAIR");
+        const int force = env ? atoi(env) : -1;
+        bool pair = force != 0 && b.n > 0;
+        for (int e = 0; e < b.n && pair; ++e) {
+            const Cfg &C = c->cfg[list[e]];
+            const bool can = C.tile[0] == 0 && C.nb3 % 2 == 0;
+            const bool want = kSiteBlock % C.dims[0] != 0 || kSiteBlock / C.dims[0] < 8;
+            pair = can && (force == 1 || want);
+        }
+        L.march_pair = pair ? 1 : 0;
+    }
     for (int mu = 0; mu < 4; ++mu) L.total_fft_tiles[mu] = b.off_fft[mu][b.n];
     L.total_xy_tiles = b.off_xy[b.n];
     for (int a = 0; a < 2; ++a) {

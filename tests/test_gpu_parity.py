@@ -332,6 +332,28 @@ def test_walk_lengths_give_bitwise_equal_links(monkeypatch, kw):
         assert abs(Ft - Fref) < 1e-14, t
 
 
+@pytest.mark.parametrize("dims", [(24, 24, 8, 8), (32, 32, 8, 8), (48, 48, 4, 4), (64, 64, 2, 4)])
+@pytest.mark.parametrize("kw", [dict(), dict(fft_prec=1), dict(fft_prec=1, link_prec=1)])
+def test_paired_site_sets_give_bitwise_equal_results(monkeypatch, dims, kw):
+    """The fused pass with two site sets per block (GF_PAIR=1; the default
+    for Lx = 24, 48 and 64) against one set per block (GF_PAIR=0): the links
+    and the per-iteration F and theta after a fixed number of updates are
+    bitwise equal (each set keeps its own partial sums, reduced in the same
+    order)."""
+    U = random_links(dims, 0.3, 9)
+    out = []
+    for p in ("0", "1"):
+        monkeypatch.setenv("GF_PAIR", p)
+        Ud = dev(U)
+        fx = GaugeFixer(Ud, **kw)
+        fx.step(7)
+        F, T = fx.history()
+        out.append((host(Ud), np.asarray(F), np.asarray(T)))
+        del fx
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 def test_step_equals_fix_prefix():
     """Calls of every length give the trajectory of one uninterrupted run,
     bitwise: the first update of a call reads the caller's links, the last of
