@@ -130,7 +130,8 @@ struct Launch {
     const Batch *batch;   // device struct
     int total_site_blocks;
     int total_march_blocks;
-    int march_pair;       // the fused pass takes two site sets per block (512 work-items)
+    int march_pair;       // the fused pass takes two site sets per block (512 work-items): 0 never,
+                          // 1 always, 2 with single-precision link storage only
     int total_fft_tiles[4];
     int total_xy_tiles;
     int total_zt_tiles;

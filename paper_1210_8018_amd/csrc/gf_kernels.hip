@@ -2951,7 +2951,7 @@ hipError_t launch_gauge(const Launch &L, int respect_done, double2 *g_override)
 
 hipError_t launch_update_delta(const Launch &L, int link_io)
 {
-    const int nb = L.march_pair ? 2 : 1;
+    const int nb = (L.march_pair == 1 || (L.march_pair == 2 && L.link_f32)) ? 2 : 1;
     const dim3 grid(L.total_march_blocks / nb), blk(kSiteBlock * nb);
     if (L.any_reunit) hipLaunchKernelGGL(k_mark_reunit, dim3((L.ncfg + 63) / 64), dim3(64), 0, L.stream, L.cfgs, L.batch);
 #define GF_UPD_NB(T2_, S2_, SRC_, DST_, NB_)                                                                       \

@@ -781,21 +781,21 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
     // rows), the doubled set halves the share of sites whose y-neighbour
     // another block owns, which pays for the barriers of 8 instead of 4 waves
     // (fused pass 2.3 %, 2.6 % and 4.3 % faster at 24^4, 48^4 and 64^4); at
-    // 32^4 (8 rows) it is 1.7 % slower. Linear sets with an even number per
-    // walk in every configuration of the launch, and every configuration of
-    // that kind; GF_PAIR=0 / 1 turns it off / on wherever it can run. The
-    // links and the partial sums are bitwise those of one set per block.
+    // 32^4 (8 rows) it is 1.7 % slower with FP64 link storage, 1.1 % faster
+    // with single-precision storage. Linear sets with an even number per
+    // walk in every configuration of the launch; GF_PAIR=0 / 1 turns it off /
+    // on wherever it can run. The links and the partial sums are bitwise
+    // those of one set per block.
     {
         const char *env = getenv("GF_PAIR");
         const int force = env ? atoi(env) : -1;
-        bool pair = force != 0 && b.n > 0;
-        for (int e = 0; e < b.n && pair; ++e) {
+        bool can = force != 0 && b.n > 0, want = true;
+        for (int e = 0; e < b.n && can; ++e) {
             const Cfg &C = c->cfg[list[e]];
-            const bool can = C.tile[0] == 0 && C.nb3 % 2 == 0;
-            const bool want = kSiteBlock % C.dims[0] != 0 || kSiteBlock / C.dims[0] < 8;
-            pair = can && (force == 1 || want);
+            can = C.tile[0] == 0 && C.nb3 % 2 == 0;
+            want = want && (kSiteBlock % C.dims[0] != 0 || kSiteBlock / C.dims[0] < 8);
         }
-        L.march_pair = pair ? 1 : 0;
+        L.march_pair = !can ? 0 : (force == 1 || want) ? 1 : 2;
     }
     for (int mu = 0; mu < 4; ++mu) L.total_fft_tiles[mu] = b.off_fft[mu][b.n];
     L.total_xy_tiles = b.off_xy[b.n];
