@@ -9,7 +9,7 @@ durations measured with HIP events on the library's stream, the roofline of
 the dominant kernel, and the CPU oracle on a bounded sample.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-iters N] [--no-cpu]
-python bench.py --workload batch|large48|large64|diff|thermal   (other measured workloads)
+python bench.py --workload batch|batch_small|large48|large64|diff|thermal   (other measured workloads)
 """
 import argparse
 import json
@@ -72,7 +72,7 @@ def main():
     ap.add_argument("--eps", type=float, default=0.3)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "batch", "large48", "large64", "diff", "thermal"])
+                    choices=["headline", "batch", "batch_small", "large48", "large64", "diff", "thermal"])
     ap.add_argument("--beta", type=float, default=6.0)
     ap.add_argument("--sweeps", type=int, default=300)
     ap.add_argument("--oracle-iters", type=int, default=20,
@@ -92,8 +92,8 @@ def main():
     from paper_1210_8018_amd.inputs import random_links
 
     if args.workload != "headline":
-        {"batch": bench_batch, "large48": bench_large, "large64": bench_large, "diff": bench_diff,
-         "thermal": bench_thermal}[args.workload](args)
+        {"batch": bench_batch, "batch_small": bench_batch, "large48": bench_large, "large64": bench_large,
+         "diff": bench_diff, "thermal": bench_thermal}[args.workload](args)
         return
 
     dims = tuple(int(v) for v in args.dims.split(","))
@@ -279,15 +279,24 @@ def main():
 
 
 def bench_batch(args):
-    """24 configurations of uneven shapes in one batch context (FP64 links, FP32 transform)."""
+    """Configurations of uneven shapes in one batch context (FP64 links, FP32
+    transform) against the same ones one context after another. `batch`: 24
+    configurations (8x12^4, 8x16^3x32, 6x24^4, 2x32^4), eps ~ U[0.2, 0.6);
+    `batch_small`: the 16 small ones (8x12^4, 8x16^3x32), eps ~ U[0.2, 0.45),
+    lattices too small to fill the GPU one at a time."""
     import numpy as np
     import torch
 
     from paper_1210_8018_amd.api import BatchGaugeFixer, GaugeFixer
     from paper_1210_8018_amd.inputs import batch_workload
 
+    small = args.workload == "batch_small"
     log("generating the batch workload")
-    cfgs = list(batch_workload())
+    if small:
+        cfgs = list(batch_workload([(12, 12, 12, 12)] * 8 + [(16, 16, 16, 32)] * 8, first_seed=200,
+                                   eps_range=(0.2, 0.45)))
+    else:
+        cfgs = list(batch_workload())
     U0 = [torch.from_numpy(U).to("cuda") for _, _, _, U in cfgs]
     torch.cuda.synchronize()
     Us = [u.clone() for u in U0]
@@ -327,12 +336,19 @@ def bench_batch(args):
         del fx, U
     sites = [int(np.prod(d)) for d, _, _, _ in cfgs]
     site_its = sum(i * v for i, v in zip(its, sites))
+    if small:
+        metric = "batch makespan to theta<=1e-15, 16 configurations (8x12^4, 8x16^3x32)"
+        workload = ("batch of 16, eps ~ U[0.2,0.45), seeds 200-215, alpha=0.08, theta_eps=1e-15, "
+                    "links reunitarised every 100 updates")
+    else:
+        metric = "batch makespan to theta<=1e-15, 24 configurations (8x12^4, 8x16^3x32, 6x24^4, 2x32^4)"
+        workload = ("batch of 24, eps ~ U[0.2,0.6), seeds 100-123, alpha=0.08, theta_eps=1e-15, "
+                    "links reunitarised every 100 updates")
     out = {
-        "metric": "batch makespan to theta<=1e-15, 24 configurations (8x12^4, 8x16^3x32, 6x24^4, 2x32^4)",
+        "metric": metric,
         "value": round(makespan, 4), "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
         "dtype": "f64 links / c64 transform",
-        "config": {"workload": "batch of 24, eps ~ U[0.2,0.6), seeds 100-123, alpha=0.08, theta_eps=1e-15, "
-                               "links reunitarised every 100 updates"},
+        "config": {"workload": workload},
         "per_config": [{"dims": list(d), "eps": round(e, 4), "seed": sd, "iterations": i, "F_final": F, "theta": th}
                        for (d, e, sd, _), i, F, th in zip(cfgs, its, Fs, ths)],
         "total_iterations": int(sum(its)), "site_iterations_per_s": site_its / makespan,

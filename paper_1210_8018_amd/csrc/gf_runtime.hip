@@ -807,6 +807,32 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
     }
     L.total_zt_tiles = b.off_zt[b.n];
     L.ncfg = b.n;
+    // which kernel instances the listed configurations need: power-of-two
+    // and general extents, register and LDS-staged 2D passes, register
+    // plane sizes, and the LDS-staged 1D passes of the axes whose lines do
+    // not run in registers (an instance no listed configuration needs is
+    // not launched)
+    auto p2 = [](int v) { return (v & (v - 1)) == 0; };
+    L.xy_p2 = L.xy_gen = L.zt_p2 = L.zt_gen = 0;
+    L.xy_reg_any = L.xy_lds_any = L.zt_reg_any = L.zt_lds_any = 0;
+    L.xy_m = 0;
+    for (int mu = 0; mu < 4; ++mu) L.ax_p2[mu] = L.ax_gen[mu] = 0;
+    for (int e = 0; e < b.n; ++e) {
+        const Cfg &C = c->cfg[list[e]];
+        if (C.nxy) {
+            ((p2(C.dims[0]) && p2(C.dims[1]) && p2(C.xyQ)) ? L.xy_p2 : L.xy_gen) = 1;
+            (C.xy_reg ? L.xy_reg_any : L.xy_lds_any) = 1;
+            if (C.xy_reg) L.xy_m |= 1 << line_len_bit(C.dims[0]);
+        }
+        if (C.nzt) {
+            ((p2(C.dims[2]) && p2(C.dims[3])) ? L.zt_p2 : L.zt_gen) = 1;
+            (C.zt_reg ? L.zt_reg_any : L.zt_lds_any) = 1;
+        }
+        for (int mu = 0; mu < 4; ++mu) {
+            if (mu >= 2 && C.line[mu - 2]) continue;
+            (p2(C.dims[mu]) ? L.ax_p2[mu] : L.ax_gen[mu]) = 1;
+        }
+    }
 }
 
 void drop_graph(gf_ctx c)
@@ -858,34 +884,21 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
     std::vector<int> all(c->ncfg);
     for (int k = 0; k < c->ncfg; ++k) all[k] = k;
     fill_map(c, all, c->bmap, c->L);
+    // tile capacities and twiddle layouts over every configuration (the
+    // instance flags are set per launch list by fill_map)
     int xy_max = 0, zt_max = 0, mx = 0, my = 0, mz = 0, mt = 0;
-    bool xy_p2 = false, zt_p2 = false, xy_gen = false, zt_gen = false;
-    auto p2 = [](int v) { return (v & (v - 1)) == 0; };
     for (int k = 0; k < c->ncfg; ++k) {
         const Cfg &C = c->cfg[k];
         if (C.nxy) xy_max = std::max(xy_max, C.xyQ * C.V2);
         if (C.nzt) zt_max = std::max(zt_max, C.ztP * C.dims[2] * C.dims[3]);
-        const bool xp = p2(C.dims[0]) && p2(C.dims[1]) && p2(C.xyQ), zp = p2(C.dims[2]) && p2(C.dims[3]);
-        if (C.nxy) (xp ? xy_p2 : xy_gen) = true;
-        if (C.nzt) (zp ? zt_p2 : zt_gen) = true;
         mx = std::max(mx, C.dims[0]);
         my = std::max(my, C.dims[1]);
         mz = std::max(mz, C.dims[2]);
         mt = std::max(mt, C.dims[3]);
     }
-    c->L.zt_reg_any = c->L.zt_lds_any = 0;
     c->L.zt_reg_groups = tl.zt_reg > 0 ? tl.zt_reg : 1;
     c->L.zt_reg_p = tl.zt_reg_p;
-    c->L.xy_reg_any = c->L.xy_lds_any = 0;
     c->L.xy_reg_groups = tl.xy_reg > 0 ? tl.xy_reg : 1;
-    c->L.xy_m = 0;
-    for (int k = 0; k < c->ncfg; ++k)
-        if (c->cfg[k].xy_reg) c->L.xy_m |= 1 << line_len_bit(c->cfg[k].dims[0]);
-    for (int k = 0; k < c->ncfg; ++k) {
-        const Cfg &C = c->cfg[k];
-        if (C.nzt) (C.zt_reg ? c->L.zt_reg_any : c->L.zt_lds_any) = 1;
-        if (C.nxy) (C.xy_reg ? c->L.xy_reg_any : c->L.xy_lds_any) = 1;
-    }
     auto cap_for = [](int n) { return n <= 1024 ? 1024 : (n <= 2048 ? 2048 : 4096); };
     c->L.xy_cap = cap_for(xy_max);
     c->L.zt_cap = cap_for(zt_max);
@@ -895,10 +908,6 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
     // one after the other (the next one prefetched)
     c->L.xy_fpb = kFields;
     c->L.zt_fpb = kFields;
-    c->L.xy_p2 = xy_p2;
-    c->L.zt_p2 = zt_p2;
-    c->L.xy_gen = xy_gen;
-    c->L.zt_gen = zt_gen;
     c->L.xy_tw2 = mx;
     c->L.xy_tw_total = mx + my;
     c->L.zt_tw2 = mz;
@@ -921,13 +930,22 @@ gf_status apply_schedule(gf_ctx c, int sched, const Tiles &tl)
 }
 
 // Batch contexts: after a chunk, launch only the configurations still
-// iterating (finished ones would only cost empty blocks).
+// iterating (finished ones would only cost empty blocks). A new map means a
+// new graph (0.4 to 1.3 ms to capture and instantiate), so the map is kept
+// until the finished configurations hold a fifth of its marching blocks:
+// their blocks leave at once.
 gf_status compact_active(gf_ctx c)
 {
     std::vector<int> act;
+    long long w_act = 0, w_map = 0;
     for (int k = 0; k < c->ncfg; ++k)
-        if (c->h_ctrl[k].done == kRunning) act.push_back(k);
+        if (c->h_ctrl[k].done == kRunning) {
+            act.push_back(k);
+            w_act += c->cfg[k].nblk_march;
+        }
+    for (int k : c->active) w_map += c->cfg[k].nblk_march;
     if (act.empty() || act == c->active) return GF_OK;
+    if (w_act * 5 > w_map * 4) return GF_OK;
     fill_map(c, act, c->bact, c->Lact);
     c->active = act;
     HIPCHK(c, hipMemcpyAsync(c->d_batch_act, &c->bact, sizeof(Batch), hipMemcpyHostToDevice, c->stream));
@@ -1291,13 +1309,6 @@ gf_status setup(gf_ctx c, int ncfg, const gf_params *params, void *const *links,
         fill_map(c, all, c->bmap, c->L);
     }
     c->L.max_lds_elems = max_lds;
-    for (int mu = 0; mu < 4; ++mu) {
-        c->L.ax_p2[mu] = c->L.ax_gen[mu] = 0;
-        for (int k = 0; k < ncfg; ++k) {
-            const int Lm = params[k].dims[mu];
-            ((Lm & (Lm - 1)) == 0 ? c->L.ax_p2[mu] : c->L.ax_gen[mu]) = 1;
-        }
-    }
     c->L.fp32 = params[0].fft_prec;
     // single-precision storage exists only in the fused exchange pass
     c->L.fused = (getenv("GF_NOFUSE") && params[0].link_prec == 0) ? 0 : 1;
