@@ -332,14 +332,15 @@ def test_walk_lengths_give_bitwise_equal_links(monkeypatch, kw):
         assert abs(Ft - Fref) < 1e-14, t
 
 
-@pytest.mark.parametrize("dims", [(24, 24, 8, 8), (32, 32, 8, 8), (48, 48, 4, 4), (64, 64, 2, 4)])
+@pytest.mark.parametrize("dims", [(24, 24, 8, 8), (32, 32, 8, 8), (48, 48, 4, 4), (64, 64, 2, 4), (24, 24, 6, 4)])
 @pytest.mark.parametrize("kw", [dict(), dict(fft_prec=1), dict(fft_prec=1, link_prec=1)])
 def test_paired_site_sets_give_bitwise_equal_results(monkeypatch, dims, kw):
     """The fused pass with two site sets per block (GF_PAIR=1; the default
     for Lx = 24, 48 and 64) against one set per block (GF_PAIR=0): the links
     and the per-iteration F and theta after a fixed number of updates are
     bitwise equal (each set keeps its own partial sums, reduced in the same
-    order)."""
+    order). 24 x 24 x 6 x 4: 3456 sites per slice, so the last set of each
+    walk is ragged (128 of its 256 work-items hold a site)."""
     U = random_links(dims, 0.3, 9)
     out = []
     for p in ("0", "1"):
