@@ -355,6 +355,31 @@ def test_paired_site_sets_give_bitwise_equal_results(monkeypatch, dims, kw):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_paired_batch_equals_single_runs(monkeypatch, prec):
+    """A batch whose members all take two site sets per fused-pass block
+    (Lx = 24, 48, 64; one with a ragged last set per walk), finishing at
+    different iterations, so the map is compacted while paired: every member
+    bitwise equal to its own context's run."""
+    monkeypatch.setenv("GF_TCHUNK", "2")
+    monkeypatch.setenv("GF_TCHUNK_BATCH", "2")
+    cases = [((24, 24, 8, 8), 0.3, 89), ((48, 48, 4, 4), 0.35, 90), ((64, 64, 2, 4), 0.3, 91),
+             ((24, 24, 6, 4), 0.4, 92)]
+    Us = [random_links(d, e, s) for d, e, s in cases]
+    single = []
+    for U in Us:
+        Ud = dev(U)
+        fx = GaugeFixer(Ud, fft_prec=prec, fft_schedule=2)
+        single.append((fx.fix_until(EPS, 5000), host(Ud)))
+    Ubs = [dev(U) for U in Us]
+    bx = BatchGaugeFixer(Ubs, fft_prec=prec, fft_schedule=2)
+    its, Fs, ths = bx.fix_until(EPS, 5000)
+    for k in range(len(cases)):
+        (it, F, th), Uf = single[k]
+        assert its[k] == it and Fs[k] == F and ths[k] == th, (k, its[k], it)
+        assert np.array_equal(host(Ubs[k]), Uf)
+
+
 def test_step_equals_fix_prefix():
     """Calls of every length give the trajectory of one uninterrupted run,
     bitwise: the first update of a call reads the caller's links, the last of
