@@ -107,7 +107,7 @@ struct Cfg {
     int ztP, nzt;         // zt pass: P consecutive xy-sites per tile, nzt tiles per field
     int xyPad;            // LDS elements added to every x-row of an xy tile (bank spreading)
     int ztPad;            // LDS elements added to every t-plane of a zt tile
-    int zt_reg;           // the scaled (z, t) pass runs in k_fft_zt_reg (Lz = Lt = 32, ztP = 2 or 4)
+    int zt_reg;           // the scaled (z, t) pass runs in registers: k_fft_zt_reg (Lz = Lt = 32), k_fft_zt_line2 (16, 24)
     int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 16 to 64)
     int line[2];          // the 1D z (line[0]) / t (line[1]) passes run in k_fft_line (that extent 16 to 64)
 };
@@ -145,7 +145,8 @@ struct Launch {
     int zt_tw2, zt_tw_total;       // same for the zt pass
     int zt_reg_any, zt_lds_any;    // scaled zt pass: some configuration in k_fft_zt_reg / in k_fft_zt
     int zt_reg_groups;             // work-groups per tile of k_fft_zt_reg (1, 2 or 4: fields split among them)
-    int zt_reg_p;                  // xy-sites per tile of k_fft_zt_reg (2 or 4)
+    int zt_reg_p;                  // xy-sites per tile of k_fft_zt_reg / k_fft_zt_line2 (2, 4 or 8)
+    int zt_m;                      // (z, t) plane sizes of the register pass present (bits line_len_bit)
     int xy_reg_any, xy_lds_any;    // iteration's xy passes: some configuration in the register / LDS-staged ones
     int xy_reg_groups;             // work-groups per tile of the register xy passes
     int xy_m;                      // their plane sizes present (bits line_len_bit)

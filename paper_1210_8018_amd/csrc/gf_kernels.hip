@@ -1339,11 +1339,12 @@ __host__ __device__ constexpr int zt_reg_lds_elems() { return 32 * zt_reg_tp<P>(
 template <int P>
 __host__ __device__ constexpr int zt_reg_lds_total() { return zt_reg_lds_elems<P>() + 32; }
 
-// Index of K(p) for xy-site xy and (z, t) site zt = kz + 32 kt in the
-// register pass's tile order: tile xy / P, then (z, t), then p = xy mod P.
-__host__ __device__ __forceinline__ size_t zt_reg_k_index(int xy, int zt, int P)
+// Index of K(p) for xy-site xy and (z, t) site zt = kz + Lz kt (nzt = Lz Lt
+// sites per plane) in the register pass's tile order: tile xy / P, then
+// (z, t), then p = xy mod P.
+__host__ __device__ __forceinline__ size_t zt_reg_k_index(int xy, int zt, int P, int nzt)
 {
-    return ((size_t)(xy / P) * 1024 + zt) * P + xy % P;
+    return ((size_t)(xy / P) * nzt + zt) * P + xy % P;
 }
 
 // The scaled (z, t) pass over configurations with Lz = Lt = 32 (C.zt_reg):
@@ -1373,7 +1374,7 @@ __global__ __launch_bounds__(128 * P) __attribute__((amdgpu_waves_per_eu(P >= 4 
     const int c = find_cfg(B->off_zt, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
-    if (!C.zt_reg || C.ztP != P) return;  // the LDS-staged pass or the other tile width takes it
+    if (!C.zt_reg || C.ztP != P || C.dims[2] != 32) return;  // the LDS-staged pass, another tile width or length
     const int V2 = C.V2;
     const int i0 = (tile - B->off_zt[c]) * P;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1386,7 +1387,7 @@ __global__ __launch_bounds__(128 * P) __attribute__((amdgpu_waves_per_eu(P >= 4 
     T kreg[8];
     {
         // the table is in this pass's tile order (zt_reg_k_index)
-        const T *__restrict__ Km = (const T *)C.kmom + zt_reg_k_index(i0 + p, 0, P);
+        const T *__restrict__ Km = (const T *)C.kmom + zt_reg_k_index(i0 + p, 0, P, 1024);
 #pragma unroll
         for (int k2 = 0; k2 < 4; ++k2)
 #pragma unroll
@@ -1653,6 +1654,94 @@ __global__ __launch_bounds__(256) void k_fft_line(const Cfg *__restrict__ cfgs, 
 #pragma unroll
                 for (int e = 0; e < Q; ++e) g[o + (unsigned)(Q * j + e + M * k2) * S] = R[Q * k2 + e];
         }
+    }
+}
+
+// ============================================================ (z, t) pass, 16 x 16 and 24 x 24 planes in registers
+// The scaled (z, t) pass of configurations with Lz = Lt = L of 16 or 24
+// (C.zt_reg), the two-lane counterpart of k_fft_zt_reg: each z- and then
+// t-line of L points lives in two lanes of a wave (lanes 32 apart, M = L / 2
+// elements each, the line transforms above), a tile is P consecutive
+// xy-sites times the (z, t) plane (P L lines, 2 P L work-items; P L a
+// multiple of 32), LDS moves the tile from z-lines to t-lines and back
+// (layout p + P z + (L + 1) P t), and K(p) is read in the tile order of
+// zt_reg_k_index. Work-item (w, q, j) holds line id = 32 w + q: (p, r) =
+// (id mod P, id / P), along z (z = 2 n2 + j, t = r), then along t.
+template <int L, int P>
+__host__ __device__ constexpr int zt_line2_threads() { return 2 * P * L; }
+template <int L, int P>
+__host__ __device__ constexpr int zt_line2_lds_elems() { return (L + 1) * P * L + L; }
+
+template <typename T2, int L, int P>
+__global__ __launch_bounds__(2 * P * L) void k_fft_zt_line2(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
+                                                             int respect_done, int ngroups)
+{
+    using T = typename Cx<T2>::T;
+    constexpr int LPL = 2, M = L / 2, Q = M / 2, TP = (L + 1) * P;
+    static_assert((P * L) % 32 == 0, "whole waves of line pairs");
+    extern __shared__ __align__(16) unsigned char smem[];
+    T2 *buf = (T2 *)smem;
+    T2 *tw = buf + TP * L;  // exp(-2 pi i e / L), the same table for z and t
+    const int rb = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = rb / ngroups, grp = rb - tile * ngroups;
+    const int nfg = kFields / ngroups, f0 = grp * nfg;
+    const int c = find_cfg(B->off_zt, B->n, tile);
+    const Cfg &C = cfgs[B->idx[c]];
+    if (respect_done && C.ctrl->done) return;
+    if (!C.zt_reg || C.ztP != P || C.dims[2] != L) return;  // another pass, tile width or length
+    const int V2 = C.V2;
+    const int i0 = (tile - B->off_zt[c]) * P;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane & 31, j = lane >> 5;
+    const int id = 32 * w + q;
+    const int p = id % P, r = id / P;
+    if (threadIdx.x < L) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[2])[threadIdx.x];
+    // K(p) of the elements a work-item holds after the forward t transform:
+    // momentum (xy-site i0 + p, kz = r, kt = Q j + e + M k2) at R[Q k2 + e]
+    T kreg[M];
+    {
+        const T *__restrict__ Km = (const T *)C.kmom + zt_reg_k_index(i0 + p, 0, P, L * L);
+#pragma unroll
+        for (int k2 = 0; k2 < LPL; ++k2)
+#pragma unroll
+            for (int e = 0; e < Q; ++e) kreg[Q * k2 + e] = Km[(size_t)(r + L * (Q * j + e + M * k2)) * P];
+    }
+    // z-line element n2 (z = 2 n2 + j, t = r) of field f0 in global memory
+    T2 *__restrict__ g = (T2 *)C.fields + (size_t)f0 * C.V + i0 + p + (size_t)V2 * (L * r + j);
+    const size_t gz = (size_t)2 * V2;  // z -> z + 2
+    for (int f = 0; f < nfg; ++f, g += C.V) {
+        T2 R[M];
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) R[n2] = g[n2 * gz];
+        if (f == 0) __syncthreads();  // the twiddle table
+        line_forward<LPL, M>(R, tw, j);  // R[Q k2 + e] = (kz = Q j + e + M k2, t = r)
+        if (f) __syncthreads();          // the previous field's t -> z reads are done
+#pragma unroll
+        for (int k2 = 0; k2 < LPL; ++k2)
+#pragma unroll
+            for (int e = 0; e < Q; ++e) buf[p + P * (Q * j + e + M * k2) + TP * r] = R[Q * k2 + e];
+        __syncthreads();
+        // t-line (p, kz = r): elements t = 2 n2 + j
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) R[n2] = buf[p + P * r + TP * (LPL * n2 + j)];
+        line_forward<LPL, M>(R, tw, j);  // R[Q k2 + e] = (kz = r, kt = Q j + e + M k2)
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            R[k].x *= kreg[k];
+            R[k].y *= kreg[k];
+        }
+        line_backward<LPL, M>(R, tw, j);  // R[n2] = (kz = r, t = 2 n2 + j)
+        __syncthreads();                  // every z -> t read is done
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) buf[p + P * r + TP * (LPL * n2 + j)] = R[n2];
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < LPL; ++k2)
+#pragma unroll
+            for (int e = 0; e < Q; ++e) R[Q * k2 + e] = buf[p + P * (Q * j + e + M * k2) + TP * r];
+        line_backward<LPL, M>(R, tw, j);  // R[n2] = (z = 2 n2 + j, t = r)
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) g[n2 * gz] = R[n2];
     }
 }
 
@@ -2332,7 +2421,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_momentum_table(const Cfg *__rest
     const double *s2 = C.sin2;
     const double p2 =
         s2[C.sin2_off[0] + n[0]] + s2[C.sin2_off[1] + n[1]] + s2[C.sin2_off[2] + n[2]] + s2[C.sin2_off[3] + n[3]];
-    const size_t o = C.zt_reg ? zt_reg_k_index(s % C.V2, s / C.V2, C.ztP) : (size_t)s;
+    const size_t o = C.zt_reg ? zt_reg_k_index(s % C.V2, s / C.V2, C.ztP, C.dims[2] * C.dims[3]) : (size_t)s;
     ((T *)C.kmom)[o] = (T)((p2 > 0.0) ? C.kfac / p2 : 0.0);
 }
 
@@ -2789,15 +2878,25 @@ static hipError_t run_zt(const Launch &L, int nf, int mode, int sign, void *fo, 
     int launched = 0;
     if (mode == 1 && L.zt_reg_any) {
         const int ng = L.zt_reg_groups;
-        if (L.zt_reg_p == 8)
-            hipLaunchKernelGGL((k_fft_zt_reg<T2, 8>), dim3(L.total_zt_tiles * ng), dim3(1024),
-                               zt_reg_lds_total<8>() * sizeof(T2), L.stream, L.cfgs, L.batch, rd, ng);
-        else if (L.zt_reg_p == 4)
-            hipLaunchKernelGGL((k_fft_zt_reg<T2, 4>), dim3(L.total_zt_tiles * ng), dim3(512),
-                               zt_reg_lds_total<4>() * sizeof(T2), L.stream, L.cfgs, L.batch, rd, ng);
-        else
-            hipLaunchKernelGGL((k_fft_zt_reg<T2, 2>), dim3(L.total_zt_tiles * ng), dim3(256),
-                               zt_reg_lds_total<2>() * sizeof(T2), L.stream, L.cfgs, L.batch, rd, ng);
+        const dim3 zg(L.total_zt_tiles * ng);
+        // one instance per plane size present (bits line_len_bit)
+        if (L.zt_m & (1 << line_len_bit(32))) {
+            if (L.zt_reg_p == 8)
+                hipLaunchKernelGGL((k_fft_zt_reg<T2, 8>), zg, dim3(1024), zt_reg_lds_total<8>() * sizeof(T2), L.stream,
+                                   L.cfgs, L.batch, rd, ng);
+            else if (L.zt_reg_p == 4)
+                hipLaunchKernelGGL((k_fft_zt_reg<T2, 4>), zg, dim3(512), zt_reg_lds_total<4>() * sizeof(T2), L.stream,
+                                   L.cfgs, L.batch, rd, ng);
+            else
+                hipLaunchKernelGGL((k_fft_zt_reg<T2, 2>), zg, dim3(256), zt_reg_lds_total<2>() * sizeof(T2), L.stream,
+                                   L.cfgs, L.batch, rd, ng);
+        }
+#define GF_ZTL(L_, P_)                                                                                       \
+    if ((L.zt_m & (1 << line_len_bit(L_))) && L.zt_reg_p == (P_))                                            \
+        hipLaunchKernelGGL((k_fft_zt_line2<T2, L_, P_>), zg, dim3((zt_line2_threads<L_, P_>())),             \
+                           (zt_line2_lds_elems<L_, P_>() * sizeof(T2)), L.stream, L.cfgs, L.batch, rd, ng);
+        GF_ZTL(16, 2) GF_ZTL(16, 4) GF_ZTL(16, 8) GF_ZTL(24, 4) GF_ZTL(24, 8)
+#undef GF_ZTL
         ++launched;
         if (!L.zt_lds_any) return hipGetLastError();
     }
@@ -2913,6 +3012,9 @@ static hipError_t set_lds_t()
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_fft_zt_reg<T2, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(zt_reg_lds_total<8>() * sizeof(T2)));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_fft_zt_line2<T2, 24, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)((zt_line2_lds_elems<24, 8>()) * sizeof(T2)));
 #define GF_XYR(L_)                                                                                              \
     if (e == hipSuccess)                                                                                        \
         e = hipFuncSetAttribute((const void *)k_fft_xy_reg<T2, L_>, hipFuncAttributeMaxDynamicSharedMemorySize, \

@@ -264,7 +264,8 @@ struct KTime {
 // Tile choices of the 2D passes: target elements per tile and elements per
 // work-item (the work-group size is the tile capacity divided by it).
 // zt_reg: the scaled (z, t) pass of configurations with Lz = Lt = 32 runs
-// in k_fft_zt_reg (radix stages in registers) instead of the LDS-staged pass,
+// in k_fft_zt_reg (radix stages in registers; 16 and 24 in k_fft_zt_line2)
+// instead of the LDS-staged pass,
 // with zt_reg work-groups per tile (1, 2 or 4, the four fields split among
 // them); 0: the LDS-staged pass.
 // xy_reg: the same for the iteration's (x, y) passes of configurations with
@@ -286,7 +287,14 @@ struct Tiles {
 // Whether a configuration's scaled (z, t) pass can run in k_fft_zt_reg, and
 // its (x, y) passes in k_fft_xy_reg / k_fft_xy_inv_reg (tiles of
 // xy_reg_planes_for(Lx) planes).
-bool zt_reg_fits(const Cfg &C, int P) { return C.dims[2] == 32 && C.dims[3] == 32 && C.V2 % P == 0; }
+// (32 x 32 planes in k_fft_zt_reg; 16 x 16 and 24 x 24 in k_fft_zt_line2,
+// whose tiles hold whole waves of line pairs)
+bool zt_reg_fits(const Cfg &C, int P)
+{
+    const int L = C.dims[2];
+    if (L != C.dims[3] || C.V2 % P) return false;
+    return L == 32 || ((L == 16 || L == 24) && (P * L) % 32 == 0);
+}
 bool xy_reg_fits(const Cfg &C)
 {
     const int L = C.dims[0];
@@ -815,7 +823,7 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
     auto p2 = [](int v) { return (v & (v - 1)) == 0; };
     L.xy_p2 = L.xy_gen = L.zt_p2 = L.zt_gen = 0;
     L.xy_reg_any = L.xy_lds_any = L.zt_reg_any = L.zt_lds_any = 0;
-    L.xy_m = 0;
+    L.xy_m = L.zt_m = 0;
     for (int mu = 0; mu < 4; ++mu) L.ax_p2[mu] = L.ax_gen[mu] = 0;
     for (int e = 0; e < b.n; ++e) {
         const Cfg &C = c->cfg[list[e]];
@@ -827,6 +835,7 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
         if (C.nzt) {
             ((p2(C.dims[2]) && p2(C.dims[3])) ? L.zt_p2 : L.zt_gen) = 1;
             (C.zt_reg ? L.zt_reg_any : L.zt_lds_any) = 1;
+            if (C.zt_reg) L.zt_m |= 1 << line_len_bit(C.dims[2]);
         }
         for (int mu = 0; mu < 4; ++mu) {
             if (mu >= 2 && C.line[mu - 2]) continue;
@@ -1070,7 +1079,7 @@ gf_status choose_schedule(gf_ctx c, int requested)
     std::vector<Cand> cands = {{kSched1D, Tiles()}};
     bool any_zreg = false, any_xreg = false, any_line = false;
     for (int k = 0; k < c->ncfg; ++k) {
-        any_zreg = any_zreg || zt_reg_fits(c->cfg[k], 2);
+        any_zreg = any_zreg || zt_reg_fits(c->cfg[k], 2) || zt_reg_fits(c->cfg[k], 4) || zt_reg_fits(c->cfg[k], 8);
         any_xreg = any_xreg || xy_reg_fits(c->cfg[k]);
         any_line = any_line || line_fits(c->cfg[k], 0) || line_fits(c->cfg[k], 1);
     }
