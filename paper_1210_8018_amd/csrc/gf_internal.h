@@ -38,6 +38,12 @@ __host__ __device__ constexpr int line_len_bit(int L) { return L == 16 ? 0 : L =
 // planes per tile of the register (x, y) passes: a tile stays within 4096
 // elements (the LDS-staged inverse pass serves the same tiles)
 __host__ __device__ constexpr int xy_reg_planes_for(int L) { return L == 16 ? 8 : L == 24 ? 4 : L == 32 ? 2 : 1; }
+// (z, t) plane shapes of the register (z, t) passes, one instance each:
+// 32 x 32 (k_fft_zt_reg), 16 x 16, 24 x 24, 16 x 32 (k_fft_zt_lines); -1 none
+__host__ __device__ constexpr int zt_shape_bit(int Lz, int Lt)
+{
+    return (Lz == 16 && Lt == 16) ? 0 : (Lz == 24 && Lt == 24) ? 1 : (Lz == 32 && Lt == 32) ? 2 : (Lz == 16 && Lt == 32) ? 3 : -1;
+}
 
 // Transform schedules: which passes make up the 4D transform, scaling and
 // inverse (the scaling is always fused into the pass that completes the
@@ -107,7 +113,7 @@ struct Cfg {
     int ztP, nzt;         // zt pass: P consecutive xy-sites per tile, nzt tiles per field
     int xyPad;            // LDS elements added to every x-row of an xy tile (bank spreading)
     int ztPad;            // LDS elements added to every t-plane of a zt tile
-    int zt_reg;           // the scaled (z, t) pass runs in registers: k_fft_zt_reg (Lz = Lt = 32), k_fft_zt_line2 (16, 24)
+    int zt_reg;           // the scaled (z, t) pass runs in registers: k_fft_zt_reg (32 x 32), k_fft_zt_lines (16 x 16, 24 x 24, 16 x 32)
     int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 16 to 64)
     int line[2];          // the 1D z (line[0]) / t (line[1]) passes run in k_fft_line (that extent 16 to 64)
 };
@@ -145,8 +151,8 @@ struct Launch {
     int zt_tw2, zt_tw_total;       // same for the zt pass
     int zt_reg_any, zt_lds_any;    // scaled zt pass: some configuration in k_fft_zt_reg / in k_fft_zt
     int zt_reg_groups;             // work-groups per tile of k_fft_zt_reg (1, 2 or 4: fields split among them)
-    int zt_reg_p;                  // xy-sites per tile of k_fft_zt_reg / k_fft_zt_line2 (2, 4 or 8)
-    int zt_m;                      // (z, t) plane sizes of the register pass present (bits line_len_bit)
+    int zt_reg_p;                  // xy-sites per tile of k_fft_zt_reg / k_fft_zt_lines (2, 4 or 8)
+    int zt_m;                      // (z, t) plane shapes of the register passes present (bits zt_shape_bit)
     int xy_reg_any, xy_lds_any;    // iteration's xy passes: some configuration in the register / LDS-staged ones
     int xy_reg_groups;             // work-groups per tile of the register xy passes
     int xy_m;                      // their plane sizes present (bits line_len_bit)

@@ -1374,7 +1374,7 @@ __global__ __launch_bounds__(128 * P) __attribute__((amdgpu_waves_per_eu(P >= 4 
     const int c = find_cfg(B->off_zt, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
-    if (!C.zt_reg || C.ztP != P || C.dims[2] != 32) return;  // the LDS-staged pass, another tile width or length
+    if (!C.zt_reg || C.ztP != P || C.dims[2] != 32 || C.dims[3] != 32) return;  // another pass, width or shape
     const int V2 = C.V2;
     const int i0 = (tile - B->off_zt[c]) * P;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1657,91 +1657,101 @@ __global__ __launch_bounds__(256) void k_fft_line(const Cfg *__restrict__ cfgs, 
     }
 }
 
-// ============================================================ (z, t) pass, 16 x 16 and 24 x 24 planes in registers
-// The scaled (z, t) pass of configurations with Lz = Lt = L of 16 or 24
-// (C.zt_reg), the two-lane counterpart of k_fft_zt_reg: each z- and then
-// t-line of L points lives in two lanes of a wave (lanes 32 apart, M = L / 2
-// elements each, the line transforms above), a tile is P consecutive
-// xy-sites times the (z, t) plane (P L lines, 2 P L work-items; P L a
-// multiple of 32), LDS moves the tile from z-lines to t-lines and back
-// (layout p + P z + (L + 1) P t), and K(p) is read in the tile order of
-// zt_reg_k_index. Work-item (w, q, j) holds line id = 32 w + q: (p, r) =
-// (id mod P, id / P), along z (z = 2 n2 + j, t = r), then along t.
-template <int L, int P>
-__host__ __device__ constexpr int zt_line2_threads() { return 2 * P * L; }
-template <int L, int P>
-__host__ __device__ constexpr int zt_line2_lds_elems() { return (L + 1) * P * L + L; }
+// ============================================================ (z, t) pass, 16 x 16, 24 x 24 and 16 x 32 planes in registers
+// The scaled (z, t) pass of configurations with (Lz, Lt) = (16, 16),
+// (24, 24) or (16, 32) (C.zt_reg), the counterpart of k_fft_zt_reg built
+// from the line transforms above: each z-line (LZ points) and then each
+// t-line (LT points) lives in line_lanes of them in one wave, a tile is P
+// consecutive xy-sites times the (z, t) plane, and LDS moves the tile from
+// z-lines to t-lines and back (layout p + P z + (LZ + 1) P t). Both phases
+// use every work-item: P LT z-lines of line_lanes(LZ) lanes and P LZ
+// t-lines of line_lanes(LT) lanes are the same count. K(p) is read in the
+// tile order of zt_reg_k_index. Work-item (w, q, j) holds line id = NQ w +
+// q (NQ = 64 / lanes per line): (p, r) = (id mod P, id / P), r = t along z,
+// r = kz along t.
+template <int LZ, int LT, int P>
+__host__ __device__ constexpr int zt_lines_threads() { return P * LT * line_lanes(LZ); }
+template <int LZ, int LT, int P>
+__host__ __device__ constexpr int zt_lines_lds_elems() { return (LZ + 1) * P * LT + LZ + LT; }
 
-template <typename T2, int L, int P>
-__global__ __launch_bounds__(2 * P * L) void k_fft_zt_line2(const Cfg *__restrict__ cfgs, const Batch *__restrict__ B,
-                                                             int respect_done, int ngroups)
+template <typename T2, int LZ, int LT, int P>
+__global__ __launch_bounds__(P * LT * (LZ >= 32 ? 4 : 2)) void k_fft_zt_lines(const Cfg *__restrict__ cfgs,
+                                                                              const Batch *__restrict__ B,
+                                                                              int respect_done, int ngroups)
 {
     using T = typename Cx<T2>::T;
-    constexpr int LPL = 2, M = L / 2, Q = M / 2, TP = (L + 1) * P;
-    static_assert((P * L) % 32 == 0, "whole waves of line pairs");
+    constexpr int LPZ = line_lanes(LZ), MZ = LZ / LPZ, QZ = MZ / LPZ, NQZ = 64 / LPZ;
+    constexpr int LPT = line_lanes(LT), MT = LT / LPT, QT = MT / LPT, NQT = 64 / LPT;
+    constexpr int TP = (LZ + 1) * P;
+    static_assert(P * LT * LPZ == P * LZ * LPT, "both phases use every work-item");
+    static_assert((P * LT * LPZ) % 64 == 0, "whole waves");
     extern __shared__ __align__(16) unsigned char smem[];
     T2 *buf = (T2 *)smem;
-    T2 *tw = buf + TP * L;  // exp(-2 pi i e / L), the same table for z and t
+    T2 *twz = buf + TP * LT;  // exp(-2 pi i e / LZ)
+    T2 *twt = twz + LZ;       // exp(-2 pi i e / LT)
     const int rb = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = rb / ngroups, grp = rb - tile * ngroups;
     const int nfg = kFields / ngroups, f0 = grp * nfg;
     const int c = find_cfg(B->off_zt, B->n, tile);
     const Cfg &C = cfgs[B->idx[c]];
     if (respect_done && C.ctrl->done) return;
-    if (!C.zt_reg || C.ztP != P || C.dims[2] != L) return;  // another pass, tile width or length
+    if (!C.zt_reg || C.ztP != P || C.dims[2] != LZ || C.dims[3] != LT) return;  // another pass, width or shape
     const int V2 = C.V2;
     const int i0 = (tile - B->off_zt[c]) * P;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = lane & 31, j = lane >> 5;
-    const int id = 32 * w + q;
-    const int p = id % P, r = id / P;
-    if (threadIdx.x < L) tw[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[2])[threadIdx.x];
+    const int qz = lane % NQZ, jz = lane / NQZ, idz = NQZ * w + qz;
+    const int pz = idz % P, rz = idz / P;  // z-line (xy-site i0 + pz, t = rz)
+    const int qt = lane % NQT, jt = lane / NQT, idt = NQT * w + qt;
+    const int pt = idt % P, rt = idt / P;  // t-line (xy-site i0 + pt, kz = rt)
+    if (threadIdx.x < LZ) twz[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[2])[threadIdx.x];
+    if (threadIdx.x < LT) twt[threadIdx.x] = ((const T2 *)C.tw + C.tw_off[3])[threadIdx.x];
     // K(p) of the elements a work-item holds after the forward t transform:
-    // momentum (xy-site i0 + p, kz = r, kt = Q j + e + M k2) at R[Q k2 + e]
-    T kreg[M];
+    // momentum (xy-site i0 + pt, kz = rt, kt = QT jt + e + MT k2) at Rt[QT k2 + e]
+    T kreg[MT];
     {
-        const T *__restrict__ Km = (const T *)C.kmom + zt_reg_k_index(i0 + p, 0, P, L * L);
+        const T *__restrict__ Km = (const T *)C.kmom + zt_reg_k_index(i0 + pt, 0, P, LZ * LT);
 #pragma unroll
-        for (int k2 = 0; k2 < LPL; ++k2)
+        for (int k2 = 0; k2 < LPT; ++k2)
 #pragma unroll
-            for (int e = 0; e < Q; ++e) kreg[Q * k2 + e] = Km[(size_t)(r + L * (Q * j + e + M * k2)) * P];
+            for (int e = 0; e < QT; ++e) kreg[QT * k2 + e] = Km[(size_t)(rt + LZ * (QT * jt + e + MT * k2)) * P];
     }
-    // z-line element n2 (z = 2 n2 + j, t = r) of field f0 in global memory
-    T2 *__restrict__ g = (T2 *)C.fields + (size_t)f0 * C.V + i0 + p + (size_t)V2 * (L * r + j);
-    const size_t gz = (size_t)2 * V2;  // z -> z + 2
+    // z-line element n2 (z = LPZ n2 + jz, t = rz) of field f0 in global memory
+    T2 *__restrict__ g = (T2 *)C.fields + (size_t)f0 * C.V + i0 + pz + (size_t)V2 * (LZ * rz + jz);
+    const size_t gz = (size_t)LPZ * V2;  // z -> z + LPZ
     for (int f = 0; f < nfg; ++f, g += C.V) {
-        T2 R[M];
+        T2 R[MZ];
 #pragma unroll
-        for (int n2 = 0; n2 < M; ++n2) R[n2] = g[n2 * gz];
-        if (f == 0) __syncthreads();  // the twiddle table
-        line_forward<LPL, M>(R, tw, j);  // R[Q k2 + e] = (kz = Q j + e + M k2, t = r)
-        if (f) __syncthreads();          // the previous field's t -> z reads are done
+        for (int n2 = 0; n2 < MZ; ++n2) R[n2] = g[n2 * gz];
+        if (f == 0) __syncthreads();     // the twiddle tables
+        line_forward<LPZ, MZ>(R, twz, jz);  // R[QZ k2 + e] = (kz = QZ jz + e + MZ k2, t = rz)
+        if (f) __syncthreads();             // the previous field's t -> z reads are done
 #pragma unroll
-        for (int k2 = 0; k2 < LPL; ++k2)
+        for (int k2 = 0; k2 < LPZ; ++k2)
 #pragma unroll
-            for (int e = 0; e < Q; ++e) buf[p + P * (Q * j + e + M * k2) + TP * r] = R[Q * k2 + e];
+            for (int e = 0; e < QZ; ++e) buf[pz + P * (QZ * jz + e + MZ * k2) + TP * rz] = R[QZ * k2 + e];
         __syncthreads();
-        // t-line (p, kz = r): elements t = 2 n2 + j
+        // t-line (pt, kz = rt): elements t = LPT n2 + jt
+        T2 Rt[MT];
 #pragma unroll
-        for (int n2 = 0; n2 < M; ++n2) R[n2] = buf[p + P * r + TP * (LPL * n2 + j)];
-        line_forward<LPL, M>(R, tw, j);  // R[Q k2 + e] = (kz = r, kt = Q j + e + M k2)
+        for (int n2 = 0; n2 < MT; ++n2) Rt[n2] = buf[pt + P * rt + TP * (LPT * n2 + jt)];
+        line_forward<LPT, MT>(Rt, twt, jt);  // Rt[QT k2 + e] = (kz = rt, kt = QT jt + e + MT k2)
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            R[k].x *= kreg[k];
-            R[k].y *= kreg[k];
+        for (int k = 0; k < MT; ++k) {
+            Rt[k].x *= kreg[k];
+            Rt[k].y *= kreg[k];
         }
-        line_backward<LPL, M>(R, tw, j);  // R[n2] = (kz = r, t = 2 n2 + j)
-        __syncthreads();                  // every z -> t read is done
+        line_backward<LPT, MT>(Rt, twt, jt);  // Rt[n2] = (kz = rt, t = LPT n2 + jt)
+        __syncthreads();                      // every z -> t read is done
 #pragma unroll
-        for (int n2 = 0; n2 < M; ++n2) buf[p + P * r + TP * (LPL * n2 + j)] = R[n2];
+        for (int n2 = 0; n2 < MT; ++n2) buf[pt + P * rt + TP * (LPT * n2 + jt)] = Rt[n2];
         __syncthreads();
 #pragma unroll
-        for (int k2 = 0; k2 < LPL; ++k2)
+        for (int k2 = 0; k2 < LPZ; ++k2)
 #pragma unroll
-            for (int e = 0; e < Q; ++e) R[Q * k2 + e] = buf[p + P * (Q * j + e + M * k2) + TP * r];
-        line_backward<LPL, M>(R, tw, j);  // R[n2] = (z = 2 n2 + j, t = r)
+            for (int e = 0; e < QZ; ++e) R[QZ * k2 + e] = buf[pz + P * (QZ * jz + e + MZ * k2) + TP * rz];
+        line_backward<LPZ, MZ>(R, twz, jz);  // R[n2] = (z = LPZ n2 + jz, t = rz)
 #pragma unroll
-        for (int n2 = 0; n2 < M; ++n2) g[n2 * gz] = R[n2];
+        for (int n2 = 0; n2 < MZ; ++n2) g[n2 * gz] = R[n2];
     }
 }
 
@@ -2880,7 +2890,7 @@ static hipError_t run_zt(const Launch &L, int nf, int mode, int sign, void *fo, 
         const int ng = L.zt_reg_groups;
         const dim3 zg(L.total_zt_tiles * ng);
         // one instance per plane size present (bits line_len_bit)
-        if (L.zt_m & (1 << line_len_bit(32))) {
+        if (L.zt_m & (1 << zt_shape_bit(32, 32))) {
             if (L.zt_reg_p == 8)
                 hipLaunchKernelGGL((k_fft_zt_reg<T2, 8>), zg, dim3(1024), zt_reg_lds_total<8>() * sizeof(T2), L.stream,
                                    L.cfgs, L.batch, rd, ng);
@@ -2891,11 +2901,12 @@ static hipError_t run_zt(const Launch &L, int nf, int mode, int sign, void *fo, 
                 hipLaunchKernelGGL((k_fft_zt_reg<T2, 2>), zg, dim3(256), zt_reg_lds_total<2>() * sizeof(T2), L.stream,
                                    L.cfgs, L.batch, rd, ng);
         }
-#define GF_ZTL(L_, P_)                                                                                       \
-    if ((L.zt_m & (1 << line_len_bit(L_))) && L.zt_reg_p == (P_))                                            \
-        hipLaunchKernelGGL((k_fft_zt_line2<T2, L_, P_>), zg, dim3((zt_line2_threads<L_, P_>())),             \
-                           (zt_line2_lds_elems<L_, P_>() * sizeof(T2)), L.stream, L.cfgs, L.batch, rd, ng);
-        GF_ZTL(16, 2) GF_ZTL(16, 4) GF_ZTL(16, 8) GF_ZTL(24, 4) GF_ZTL(24, 8)
+#define GF_ZTL(LZ_, LT_, P_)                                                                                   \
+    if ((L.zt_m & (1 << zt_shape_bit(LZ_, LT_))) && L.zt_reg_p == (P_))                                         \
+        hipLaunchKernelGGL((k_fft_zt_lines<T2, LZ_, LT_, P_>), zg, dim3((zt_lines_threads<LZ_, LT_, P_>())),    \
+                           (zt_lines_lds_elems<LZ_, LT_, P_>() * sizeof(T2)), L.stream, L.cfgs, L.batch, rd, ng);
+        GF_ZTL(16, 16, 2) GF_ZTL(16, 16, 4) GF_ZTL(16, 16, 8) GF_ZTL(24, 24, 4) GF_ZTL(24, 24, 8)
+        GF_ZTL(16, 32, 2) GF_ZTL(16, 32, 4) GF_ZTL(16, 32, 8)
 #undef GF_ZTL
         ++launched;
         if (!L.zt_lds_any) return hipGetLastError();
@@ -3013,8 +3024,13 @@ static hipError_t set_lds_t()
         e = hipFuncSetAttribute((const void *)k_fft_zt_reg<T2, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(zt_reg_lds_total<8>() * sizeof(T2)));
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_fft_zt_line2<T2, 24, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)((zt_line2_lds_elems<24, 8>()) * sizeof(T2)));
+        e = hipFuncSetAttribute((const void *)k_fft_zt_lines<T2, 24, 24, 8>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)((zt_lines_lds_elems<24, 24, 8>()) * sizeof(T2)));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_fft_zt_lines<T2, 16, 32, 8>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)((zt_lines_lds_elems<16, 32, 8>()) * sizeof(T2)));
 #define GF_XYR(L_)                                                                                              \
     if (e == hipSuccess)                                                                                        \
         e = hipFuncSetAttribute((const void *)k_fft_xy_reg<T2, L_>, hipFuncAttributeMaxDynamicSharedMemorySize, \

@@ -264,7 +264,8 @@ struct KTime {
 // Tile choices of the 2D passes: target elements per tile and elements per
 // work-item (the work-group size is the tile capacity divided by it).
 // zt_reg: the scaled (z, t) pass of configurations with Lz = Lt = 32 runs
-// in k_fft_zt_reg (radix stages in registers; 16 and 24 in k_fft_zt_line2)
+// in k_fft_zt_reg (radix stages in registers; 16 x 16, 24 x 24 and 16 x 32
+// planes in k_fft_zt_lines)
 // instead of the LDS-staged pass,
 // with zt_reg work-groups per tile (1, 2 or 4, the four fields split among
 // them); 0: the LDS-staged pass.
@@ -287,13 +288,14 @@ struct Tiles {
 // Whether a configuration's scaled (z, t) pass can run in k_fft_zt_reg, and
 // its (x, y) passes in k_fft_xy_reg / k_fft_xy_inv_reg (tiles of
 // xy_reg_planes_for(Lx) planes).
-// (32 x 32 planes in k_fft_zt_reg; 16 x 16 and 24 x 24 in k_fft_zt_line2,
-// whose tiles hold whole waves of line pairs)
+// (32 x 32 planes in k_fft_zt_reg; 16 x 16, 24 x 24 and 16 x 32 in
+// k_fft_zt_lines, whose tiles hold whole waves of lines: 2 P Lt a multiple
+// of 64, so 24 x 24 takes 4 or 8 xy-sites per tile)
 bool zt_reg_fits(const Cfg &C, int P)
 {
-    const int L = C.dims[2];
-    if (L != C.dims[3] || C.V2 % P) return false;
-    return L == 32 || ((L == 16 || L == 24) && (P * L) % 32 == 0);
+    const int Lz = C.dims[2], Lt = C.dims[3];
+    if (zt_shape_bit(Lz, Lt) < 0 || C.V2 % P) return false;
+    return Lz == 32 || (P * Lt * line_lanes(Lz)) % 64 == 0;
 }
 bool xy_reg_fits(const Cfg &C)
 {
@@ -835,7 +837,7 @@ void fill_map(gf_ctx c, const std::vector<int> &list, Batch &b, Launch &L)
         if (C.nzt) {
             ((p2(C.dims[2]) && p2(C.dims[3])) ? L.zt_p2 : L.zt_gen) = 1;
             (C.zt_reg ? L.zt_reg_any : L.zt_lds_any) = 1;
-            if (C.zt_reg) L.zt_m |= 1 << line_len_bit(C.dims[2]);
+            if (C.zt_reg) L.zt_m |= 1 << zt_shape_bit(C.dims[2], C.dims[3]);
         }
         for (int mu = 0; mu < 4; ++mu) {
             if (mu >= 2 && C.line[mu - 2]) continue;
