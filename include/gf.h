@@ -80,8 +80,8 @@ typedef struct {
                              (in the iteration with FP64 link storage it
                              writes the filtered fields, from which the link
                              update forms g). Lines of 16, 24, 32, 48 and 64
-                             points, and (z,t) planes of 16x16, 24x24, 32x32
-                             and 16x32, run with their radix stages in
+                             points, and (z,t) planes of 16x16, 24x24, 32x32,
+                             16x32 and 48x48, run with their radix stages in
                              registers.
                              Schedules 2 and 3 need Lx*Ly <= 4096 (and
                              Lz*Lt <= 4096 for 3); GF_ERR_SHAPE otherwise.   */

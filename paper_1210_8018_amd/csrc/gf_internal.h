@@ -39,10 +39,16 @@ __host__ __device__ constexpr int line_len_bit(int L) { return L == 16 ? 0 : L =
 // elements (the LDS-staged inverse pass serves the same tiles)
 __host__ __device__ constexpr int xy_reg_planes_for(int L) { return L == 16 ? 8 : L == 24 ? 4 : L == 32 ? 2 : 1; }
 // (z, t) plane shapes of the register (z, t) passes, one instance each:
-// 32 x 32 (k_fft_zt_reg), 16 x 16, 24 x 24, 16 x 32 (k_fft_zt_lines); -1 none
+// 32 x 32 (k_fft_zt_reg), 16 x 16, 24 x 24, 16 x 32, 48 x 48
+// (k_fft_zt_lines); -1 none
 __host__ __device__ constexpr int zt_shape_bit(int Lz, int Lt)
 {
-    return (Lz == 16 && Lt == 16) ? 0 : (Lz == 24 && Lt == 24) ? 1 : (Lz == 32 && Lt == 32) ? 2 : (Lz == 16 && Lt == 32) ? 3 : -1;
+    return (Lz == 16 && Lt == 16)   ? 0
+           : (Lz == 24 && Lt == 24) ? 1
+           : (Lz == 32 && Lt == 32) ? 2
+           : (Lz == 16 && Lt == 32) ? 3
+           : (Lz == 48 && Lt == 48) ? 4
+                                    : -1;
 }
 
 // Transform schedules: which passes make up the 4D transform, scaling and
@@ -113,7 +119,7 @@ struct Cfg {
     int ztP, nzt;         // zt pass: P consecutive xy-sites per tile, nzt tiles per field
     int xyPad;            // LDS elements added to every x-row of an xy tile (bank spreading)
     int ztPad;            // LDS elements added to every t-plane of a zt tile
-    int zt_reg;           // the scaled (z, t) pass runs in registers: k_fft_zt_reg (32 x 32), k_fft_zt_lines (16 x 16, 24 x 24, 16 x 32)
+    int zt_reg;           // the scaled (z, t) pass runs in registers: k_fft_zt_reg (32 x 32), k_fft_zt_lines (the others)
     int xy_reg;           // the iteration's (x, y) passes run in k_fft_xy_reg / k_fft_xy_inv_reg (Lx = Ly = 16 to 64)
     int line[2];          // the 1D z (line[0]) / t (line[1]) passes run in k_fft_line (that extent 16 to 64)
 };

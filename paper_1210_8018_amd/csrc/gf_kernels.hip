@@ -1657,9 +1657,9 @@ __global__ __launch_bounds__(256) void k_fft_line(const Cfg *__restrict__ cfgs, 
     }
 }
 
-// ============================================================ (z, t) pass, 16 x 16, 24 x 24 and 16 x 32 planes in registers
+// ============================================================ (z, t) pass, 16 x 16 to 48 x 48 planes in registers
 // The scaled (z, t) pass of configurations with (Lz, Lt) = (16, 16),
-// (24, 24) or (16, 32) (C.zt_reg), the counterpart of k_fft_zt_reg built
+// (24, 24), (16, 32) or (48, 48) (C.zt_reg), the counterpart of k_fft_zt_reg built
 // from the line transforms above: each z-line (LZ points) and then each
 // t-line (LT points) lives in line_lanes of them in one wave, a tile is P
 // consecutive xy-sites times the (z, t) plane, and LDS moves the tile from
@@ -2906,7 +2906,7 @@ static hipError_t run_zt(const Launch &L, int nf, int mode, int sign, void *fo, 
         hipLaunchKernelGGL((k_fft_zt_lines<T2, LZ_, LT_, P_>), zg, dim3((zt_lines_threads<LZ_, LT_, P_>())),    \
                            (zt_lines_lds_elems<LZ_, LT_, P_>() * sizeof(T2)), L.stream, L.cfgs, L.batch, rd, ng);
         GF_ZTL(16, 16, 2) GF_ZTL(16, 16, 4) GF_ZTL(16, 16, 8) GF_ZTL(24, 24, 4) GF_ZTL(24, 24, 8)
-        GF_ZTL(16, 32, 2) GF_ZTL(16, 32, 4) GF_ZTL(16, 32, 8)
+        GF_ZTL(16, 32, 2) GF_ZTL(16, 32, 4) GF_ZTL(16, 32, 8) GF_ZTL(48, 48, 2)
 #undef GF_ZTL
         ++launched;
         if (!L.zt_lds_any) return hipGetLastError();
@@ -3031,6 +3031,10 @@ static hipError_t set_lds_t()
         e = hipFuncSetAttribute((const void *)k_fft_zt_lines<T2, 16, 32, 8>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)((zt_lines_lds_elems<16, 32, 8>()) * sizeof(T2)));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_fft_zt_lines<T2, 48, 48, 2>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)((zt_lines_lds_elems<48, 48, 2>()) * sizeof(T2)));
 #define GF_XYR(L_)                                                                                              \
     if (e == hipSuccess)                                                                                        \
         e = hipFuncSetAttribute((const void *)k_fft_xy_reg<T2, L_>, hipFuncAttributeMaxDynamicSharedMemorySize, \

@@ -288,13 +288,15 @@ struct Tiles {
 // Whether a configuration's scaled (z, t) pass can run in k_fft_zt_reg, and
 // its (x, y) passes in k_fft_xy_reg / k_fft_xy_inv_reg (tiles of
 // xy_reg_planes_for(Lx) planes).
-// (32 x 32 planes in k_fft_zt_reg; 16 x 16, 24 x 24 and 16 x 32 in
+// (32 x 32 planes in k_fft_zt_reg; 16 x 16, 24 x 24, 16 x 32 and 48 x 48 in
 // k_fft_zt_lines, whose tiles hold whole waves of lines: 2 P Lt a multiple
-// of 64, so 24 x 24 takes 4 or 8 xy-sites per tile)
+// of 64, so 24 x 24 takes 4 or 8 xy-sites per tile; 48 x 48 takes 2, whose
+// tile fills 75 KiB of LDS in FP64)
 bool zt_reg_fits(const Cfg &C, int P)
 {
     const int Lz = C.dims[2], Lt = C.dims[3];
     if (zt_shape_bit(Lz, Lt) < 0 || C.V2 % P) return false;
+    if (Lz == 48) return P == 2;
     return Lz == 32 || (P * Lt * line_lanes(Lz)) % 64 == 0;
 }
 bool xy_reg_fits(const Cfg &C)

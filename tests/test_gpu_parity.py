@@ -812,17 +812,17 @@ def test_two_lane_lines_batch_equals_single_runs(monkeypatch, sched, prec):
 
 # ---------------------------------------------------------------- 32 x 32 (z, t) planes
 
-# 32 x 32 (z, t) planes (k_fft_zt_reg) and 24 x 24, 16 x 16, 16 x 32 ones
-# (k_fft_zt_lines; 24-point planes need 4 or 8 xy-sites per tile, so 2 takes
-# the LDS-staged pass)
+# 32 x 32 (z, t) planes (k_fft_zt_reg) and 24 x 24, 16 x 16, 16 x 32, 48 x 48
+# ones (k_fft_zt_lines; 24-point planes need 4 or 8 xy-sites per tile and
+# 48-point planes 2, other widths take the LDS-staged pass)
 ZT32_SHAPES = [(2, 2, 32, 32), (4, 2, 32, 32), (6, 4, 32, 32), (8, 8, 32, 32), (16, 2, 32, 32), (4, 2, 24, 24),
                (4, 4, 24, 24), (2, 2, 16, 16), (4, 4, 16, 16), (6, 4, 24, 24), (2, 2, 16, 32), (4, 4, 16, 32),
-               (6, 2, 16, 32)]
+               (6, 2, 16, 32), (2, 2, 48, 48), (6, 2, 48, 48)]
 
 
 @pytest.mark.parametrize("dims", ZT32_SHAPES)
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("reg", ["1", "2", "4", "0", "1/4", "2/8", "4/8"])
+@pytest.mark.parametrize("reg", ["1", "2", "4", "0", "1/4", "2/8", "4/8", "2/2"])
 def test_zt_register_pass_matches_oracle(monkeypatch, dims, prec, reg):
     """The scaled (z, t) pass of 32 x 32, 24 x 24, 16 x 16 and 16 x 32 planes
     with its radix stages in registers (GF_ZT_REG = work-groups per tile, 1, 2 or 4; after the slash
@@ -844,7 +844,7 @@ def test_zt_register_pass_matches_oracle(monkeypatch, dims, prec, reg):
 @pytest.mark.parametrize("dims,seed,P", [((4, 2, 32, 32), 48, "2"), ((6, 4, 32, 32), 49, "4"),
                                          ((16, 2, 32, 32), 50, "8"), ((4, 2, 24, 24), 93, "4"),
                                          ((4, 4, 24, 24), 94, "8"), ((2, 4, 16, 16), 95, "2"),
-                                         ((4, 2, 16, 32), 96, "4")])
+                                         ((4, 2, 16, 32), 96, "4"), ((2, 2, 48, 48), 97, "2")])
 def test_zt_register_pass_trajectory(monkeypatch, dims, seed, P):
     monkeypatch.setenv("GF_ZT_REG_P", P)
     U = random_links(dims, 0.3, seed)
